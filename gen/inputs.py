@@ -1,0 +1,105 @@
+"""Workload recipes: Hamiltonians, parameters, samples and weights.
+
+The parameter layout is the library's flat FP32 layout: for each hidden layer
+l = 1..L the weight W_l (row-major [h][in_l], in_1 = n, else h) then its bias
+b_l [h]; then the conditional head W_o [n][h], b_o [n]; then the phase head
+W_phi [4][h], b_phi [4].  All entries are drawn i.i.d. N(0, 0.1^2) in float32.
+
+Samples are bit strings packed into uint64 (bit j = qubit j), drawn uniformly
+from the (n_up, n_dn) spin sector: up electrons on even qubits, down electrons
+on odd qubits.
+"""
+from functools import lru_cache
+
+import numpy as np
+
+from .integrals import molecular_integrals
+from .jw import jordan_wigner_terms, PauliTerms
+
+
+@lru_cache(maxsize=8)
+def _hamiltonian_cached(n_orb, seed, drop_tol):
+    h1, h2 = molecular_integrals(n_orb, seed)
+    return jordan_wigner_terms(h1, h2, drop_tol=drop_tol)
+
+
+def hamiltonian(n_orb: int, seed: int = 0, drop_tol: float = 1e-10) -> PauliTerms:
+    """Merged Pauli-string Hamiltonian on ``2*n_orb`` qubits (cached per process)."""
+    return _hamiltonian_cached(int(n_orb), int(seed), float(drop_tol))
+
+
+def param_count(n: int, n_layers: int, width: int) -> int:
+    h = width
+    total = h * n + h
+    total += (n_layers - 1) * (h * h + h)
+    total += n * h + n
+    total += 4 * h + 4
+    return total
+
+
+def init_params(n: int, n_layers: int, width: int, seed: int = 1, std: float = 0.1):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return (std * rng.standard_normal(param_count(n, n_layers, width))).astype(np.float32)
+
+
+def sector_samples(n: int, n_up: int, n_dn: int, count: int, seed: int = 2):
+    """``count`` i.i.d. uniform draws from the (n_up, n_dn) sector, as uint64."""
+    N = n // 2
+    if not (0 <= n_up <= N and 0 <= n_dn <= N):
+        raise ValueError("sector outside the orbital range")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = np.zeros(count, dtype=np.uint64)
+    for spin, ne in ((0, n_up), (1, n_dn)):
+        if ne == 0:
+            continue
+        keys = rng.random((count, N))
+        chosen = np.argsort(keys, axis=1)[:, :ne]          # uniform ne-subset
+        qubits = (2 * chosen + spin).astype(np.uint64)
+        out |= np.bitwise_or.reduce(np.left_shift(np.uint64(1), qubits), axis=1)
+    return out
+
+
+def unique_with_counts(samples):
+    u, c = np.unique(np.asarray(samples, dtype=np.uint64), return_counts=True)
+    return u, c.astype(np.float64)
+
+
+# The five workloads: spatial orbitals N (n = 2N qubits, half filling),
+# integral seed, batch, hidden layers L, width h, arithmetic of the path.
+CONFIGS = {
+    "c1": dict(N=6, seed=0, B=1024, L=1, h=64, precision="fp64", dedup=True,
+               weights="ones"),
+    "c2": dict(N=12, seed=0, B=8192, L=2, h=256, precision="fp32", dedup=False,
+               weights="counts"),
+    "c3": dict(N=20, seed=0, B=32768, L=3, h=512, precision="bf16", dedup=True,
+               weights="counts"),
+    "c4": dict(N=30, seed=0, B=65536, L=4, h=1024, precision="bf16", dedup=False,
+               weights="counts"),
+    "c5a": dict(N=8, seed=1, B=4096, L=3, h=512, precision="bf16", dedup=True,
+                weights="counts"),
+    "c5b": dict(N=14, seed=2, B=16384, L=3, h=512, precision="bf16", dedup=False,
+                weights="counts"),
+    "c5c": dict(N=22, seed=3, B=32768, L=3, h=512, precision="bf16", dedup=False,
+                weights="counts"),
+    "c5d": dict(N=32, seed=4, B=16384, L=3, h=512, precision="bf16", dedup=False,
+                weights="counts"),
+}
+
+
+def config_inputs(name: str, batch: int = None, sample_seed: int = 2, param_seed: int = 1):
+    """(PauliTerms, params f32, samples u64, weights f64, cfg) for a workload."""
+    cfg = dict(CONFIGS[name])
+    N = cfg["N"]
+    n = 2 * N
+    ham = hamiltonian(N, cfg["seed"])
+    B = cfg["B"] if batch is None else int(batch)
+    params = init_params(n, cfg["L"], cfg["h"], seed=param_seed)
+    raw = sector_samples(n, N // 2, N // 2, B, seed=sample_seed)
+    if cfg["weights"] == "counts":
+        samples, weights = unique_with_counts(raw)
+    else:
+        samples, weights = raw, np.ones(B, dtype=np.float64)
+    cfg["n"] = n
+    cfg["n_up"] = N // 2
+    cfg["n_dn"] = N // 2
+    return ham, params, samples, weights, cfg
