@@ -1,0 +1,255 @@
+/*
+ * nqs.h -- C ABI of the MI355X (gfx950) local-energy / VMC-gradient library.
+ *
+ * The library evaluates, for a batch of bit-string samples x_i and a masked
+ * autoregressive amplitude/phase network psi_theta, the quantities of
+ * Zhao, Stokes & Veerapaneni, "Scalable neural quantum states architecture
+ * for quantum chemistry" (arXiv 2208.05637):
+ *
+ *   local energy   E_loc(x) = sum_k alpha_k <x|P_k|x^k> psi(x^k)/psi(x)
+ *                  (Sec. 5.1, Eq. local_energy_auto; matrix element by
+ *                  Eq. mtx_element; Alg. 1),
+ *   energy         E = sum_i w_i Re E_loc(x_i) / sum_i w_i
+ *                  (Sec. 5.2, Eq. total_energy_sum, with sample weights),
+ *   gradient       g = 2 Re sum_i (w_i/W) (E_loc(x_i) - E) conj(d log psi(x_i))
+ *                  (Sec. 3, Eq. grad, with baseline b = E; this is the
+ *                  gradient of <H>, i.e. twice the gradient of the paper's
+ *                  L = <H>/2).
+ *
+ * Conventions shared by every call
+ *   - Qubit j is bit j of a uint64 (the paper's x_{j+1}); n_qubits <= 64.
+ *   - A Pauli string is (x_mask, z_mask): factor on qubit j is I, X, Z, Y for
+ *     (x_j, z_j) = (0,0), (1,0), (0,1), (1,1) (Sec. 3, Eq. 1).
+ *   - Even qubits carry spin up, odd qubits spin down (Sec. 4, Constraints).
+ *   - Status codes are returned, never exceptions; nqs_last_error() gives a
+ *     thread-local text for the last failing call on the calling thread.
+ *   - Argument errors are detected on the host before anything is enqueued.
+ *     Errors found on the device (zero amplitude of a sample, entry-buffer
+ *     overflow, hash-table overflow) set bits of a device error word kept in
+ *     the first bytes of the workspace; nqs_device_status() reads it.
+ *   - Device pointers ("d_") are caller-owned device memory; the library
+ *     never allocates or frees device memory.  Host pointers are read during
+ *     the call only.  Handles (ctx, ham, plan) are host objects owned by the
+ *     library and released with the matching *_destroy.
+ *   - Every device call is stream-ordered on the context's stream, performs
+ *     no host synchronisation and no allocation (so it can be captured into a
+ *     HIP graph), unless stated otherwise.
+ */
+#ifndef NQS_H
+#define NQS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NQS_OK = 0,
+  NQS_ERR_INVALID_ARGUMENT = 1,
+  NQS_ERR_UNSUPPORTED = 2,          /* n_qubits > 64, width, device not gfx950 */
+  NQS_ERR_NOT_HERMITIAN = 3,        /* nonzero imaginary Pauli coefficient    */
+  NQS_ERR_WORKSPACE_TOO_SMALL = 4,
+  NQS_ERR_HIP = 5,                  /* a HIP runtime call failed              */
+  NQS_ERR_DEVICE = 6                /* device error word is nonzero           */
+} nqs_status;
+
+/* Device error-word bits (nqs_device_status). */
+#define NQS_DEV_ZERO_AMPLITUDE   1u  /* a sample has psi = 0 (outside the sector) */
+#define NQS_DEV_ENTRY_OVERFLOW   2u  /* more connected entries than planned      */
+#define NQS_DEV_HASH_OVERFLOW    4u  /* dedup hash table full                    */
+
+/* Text for a status code (static storage). */
+const char* nqs_status_str(int status);
+/* Copies the calling thread's last error text into buf (NUL-terminated,
+   truncated to len); returns the full length of the text. */
+size_t nqs_last_error(char* buf, size_t len);
+/* Library version, major*10000 + minor*100 + patch. */
+int nqs_version(void);
+
+/* ------------------------------------------------------------------ context */
+typedef struct nqs_ctx nqs_ctx;
+/* Binds a HIP device and stream (a hipStream_t passed as void*; NULL = the
+   default stream).  Fails with NQS_ERR_UNSUPPORTED unless the device is gfx950.
+   No device memory is allocated. */
+nqs_status nqs_ctx_create(int device, void* stream, nqs_ctx** out);
+nqs_status nqs_ctx_set_stream(nqs_ctx* ctx, void* stream);
+void       nqs_ctx_destroy(nqs_ctx* ctx);
+
+/* -------------------------------------------------------------- Hamiltonian
+ * Sec. 3 (Eq. hamiltonpauli) and Sec. 5.1: H = sum_k alpha_k P_k, parsed once
+ * into a tensor of unique flips.  nqs_ham_create works on the host only:
+ *   1. identical (x_mask, z_mask) are merged by sequential FP64 addition in
+ *      input order;
+ *   2. merged terms with |alpha| < drop_tol are removed;
+ *   3. alpha must be real (a Hermitian H has real Pauli coefficients): any
+ *      nonzero coeff_imag[k] gives NQS_ERR_NOT_HERMITIAN;
+ *   4. the factor (-i)^{popcount(x&z)} of Eq. mtx_element is folded into the
+ *      coefficient: ct_k = alpha_k (-i)^{r_k}, stored as (re, im) planes;
+ *   5. terms are sorted by (x_mask, z_mask) ascending and grouped by x_mask
+ *      (one group per distinct flip; group 0 is the empty flip if present).
+ * Device layout (structure of arrays, written by nqs_ham_upload into caller
+ * storage of nqs_ham_info's `bytes`): gx[G] u64 flips, goff[G+1] i64 term
+ * offsets, tz[K] u64 z masks, tc_re[K] f64, tc_im[K] f64 (only if has_imag).
+ */
+typedef struct {
+  int            n_qubits;     /* 1..64 */
+  int64_t        n_terms;      /* input terms, >= 0 */
+  const uint64_t* x_mask;      /* host [n_terms] */
+  const uint64_t* z_mask;      /* host [n_terms] */
+  const double*   coeff;       /* host [n_terms], real part */
+  const double*   coeff_imag;  /* host [n_terms] or NULL; must be all zero */
+  double          drop_tol;    /* merged |alpha| < drop_tol removed (e.g. 1e-10) */
+  uint32_t        flags;       /* NQS_H_* */
+} nqs_pauli_terms;
+
+/* The Hamiltonian conserves the number of up and of down electrons, so a
+   flip group can be skipped for a sample when it changes either count
+   (an integer test).  Without the flag a group is skipped only when its
+   matrix element is exactly 0.0. */
+#define NQS_H_CONSERVES_SPIN_SECTORS 1u
+
+typedef struct nqs_ham nqs_ham;
+nqs_status nqs_ham_create(const nqs_pauli_terms* terms, nqs_ham** out);
+/* K merged terms, G groups, device bytes, has_imag (any odd-Y string). */
+nqs_status nqs_ham_info(const nqs_ham* ham, int64_t* K, int64_t* G, size_t* bytes,
+                        int* has_imag, int* n_qubits);
+/* Copies the tensor into d_storage (>= bytes, 256-byte aligned) on the
+   context's stream and records the pointer; the storage must outlive every
+   plan built on this Hamiltonian.  This call synchronises the stream. */
+nqs_status nqs_ham_upload(nqs_ham* ham, nqs_ctx* ctx, void* d_storage, size_t bytes);
+/* Host copy of the canonical tensor (any pointer may be NULL to skip). */
+nqs_status nqs_ham_export(const nqs_ham* ham, uint64_t* gx, int64_t* goff, uint64_t* tz,
+                          double* tc_re, double* tc_im);
+void       nqs_ham_destroy(nqs_ham* ham);
+
+/* ------------------------------------------------------------------ network
+ * Sec. 4 (Architecture, Constraints): masked autoregressive network with a
+ * shared trunk of n_layers masked ReLU layers of `width` units, a
+ * conditional head (n logits, pi_j = sigmoid) and a 4-way phase head.
+ *   s = 2x - 1;  a_l = ReLU((M_l*W_l) a_{l-1} + b_l);
+ *   o = (M_o*W_o) a_L + b_o;  p = (M_p*W_p) a_L + b_p;
+ *   log|psi| = 1/2 sum_{free j} log pi_j(x_j);  phi = p[2 x_{o[n-2]} + x_{o[n-1]}]
+ * with qubit degrees d(j) = 1 + position of j in `order`, hidden degrees
+ * m_k = 1 + (k mod (n-1)), masks [m_k >= d(j)], [m_k >= m_k'], [d(j) > m_k],
+ * [m_k <= n-2], and the Hamming-weight modifier of Eq. modifier (a position
+ * is forced to 0 once n_s spin-s electrons are placed, to 1 when the
+ * remaining spin-s positions are all needed; forced positions contribute 0,
+ * a contradicted forced value gives psi = 0).
+ * Parameters: one flat FP32 buffer W_1, b_1, ..., W_L, b_L, W_o, b_o, W_p,
+ * b_p, weights row-major [out][in] (in_1 = n).  Gradients use the same
+ * layout in FP64; masked-out weights receive 0.
+ */
+enum { NQS_FP64 = 0, NQS_FP32 = 1, NQS_BF16 = 2, NQS_BF16X3 = 3 };
+
+typedef struct {
+  int            n_qubits;   /* 2..64 */
+  int            n_layers;   /* >= 1 */
+  int            width;      /* 64, 128, 256, 512 or 1024 (precision dependent) */
+  const int32_t* order;      /* host [n_qubits] sampling order, NULL = n-1, ..., 0 */
+  int            n_up, n_dn; /* electrons per spin; both -1 = unconstrained */
+  int            precision;  /* NQS_FP64 | NQS_FP32 | NQS_BF16 | NQS_BF16X3:
+                                arithmetic of the network GEMMs on connected
+                                configurations (FP32 accumulation for BF16 kinds);
+                                Hamiltonian sums, ratios and reductions are FP64 */
+} nqs_net_desc;
+
+nqs_status nqs_net_param_count(const nqs_net_desc* net, int64_t* n_params);
+
+/* --------------------------------------------------------------------- plan */
+#define NQS_PLAN_DEDUP_ON   1u   /* deduplicate connected configurations per chunk */
+#define NQS_PLAN_DEDUP_OFF  2u   /* never deduplicate (default when neither is set) */
+
+typedef struct nqs_plan nqs_plan;
+/* Fixes the chunking (chunk_samples samples per chunk; <= 0 picks a default
+   from the per-sample entry bound) and the kernel variants for batches of
+   up to max_batch samples.  Host only. */
+nqs_status nqs_plan_create(nqs_ctx* ctx, const nqs_ham* ham, const nqs_net_desc* net,
+                           int64_t max_batch, uint32_t flags, int64_t chunk_samples,
+                           nqs_plan** out);
+nqs_status nqs_plan_workspace_size(const nqs_plan* plan, int64_t batch, size_t* bytes);
+/* Plan facts: per-sample entry bound, chunk size, dedup on/off, number of
+   parameters. */
+nqs_status nqs_plan_info(const nqs_plan* plan, int64_t* entries_per_sample,
+                         int64_t* chunk_samples, int* dedup, int64_t* n_params);
+void       nqs_plan_destroy(nqs_plan* plan);
+
+/* ---------------------------------------------------------------- hot path
+ * All pointers are device pointers; d_ws is a workspace of at least
+ * nqs_plan_workspace_size(plan, B) bytes, 256-byte aligned.  Samples are
+ * read as uint64 [B]; weights f64 [B] (NULL = all 1).
+ */
+
+/* log psi for n configurations: d_out[2*i] = log|psi|, d_out[2*i+1] = phi,
+   computed by the connected-configuration forward kernel of the plan's
+   precision (-inf for psi = 0).  Sec. 4, the complex logarithm of f. */
+nqs_status nqs_log_psi(nqs_plan* plan, const float* d_params, const uint64_t* d_x, int64_t n,
+                       double* d_out, void* d_ws, size_t ws_bytes);
+
+/* Local energies d_eloc[2*i] + i d_eloc[2*i+1] (Eq. local_energy_auto). */
+nqs_status nqs_local_energy(nqs_plan* plan, const float* d_params, const uint64_t* d_samples,
+                            int64_t B, double* d_eloc, void* d_ws, size_t ws_bytes);
+
+/* Local energies (d_eloc may be NULL), the energy d_energy[3] = {E, mean of
+   Im E_loc, W = sum w} (Eq. total_energy_sum) and the gradient d_grad
+   [n_params] f64 (Eq. grad, see the top of this file).  The backward pass
+   recomputes the sample forward instead of storing activations of the
+   connected configurations, chunk by chunk (gradient accumulation). */
+nqs_status nqs_energy_grad(nqs_plan* plan, const float* d_params, const uint64_t* d_samples,
+                           const double* d_weights, int64_t B, double* d_eloc,
+                           double* d_energy, double* d_grad, void* d_ws, size_t ws_bytes);
+
+/* Several independent (Hamiltonian, network, samples) instances in one call.
+   Each instance uses its own plan (all plans on the same context); the
+   workspace must hold the largest instance's requirement.  Instances are
+   processed largest first. */
+typedef struct {
+  nqs_plan*       plan;
+  const float*    d_params;
+  const uint64_t* d_samples;
+  const double*   d_weights;
+  int64_t         B;
+  double*         d_eloc;    /* may be NULL */
+  double*         d_energy;  /* [3] */
+  double*         d_grad;    /* [n_params] */
+} nqs_instance;
+nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* d_ws, size_t ws_bytes);
+
+/* ------------------------------------------------------ test / table path
+ * nqs_connected enumerates, for samples [0, B), the diagonal element
+ * d_diag[2*i..] (group with empty flip) and the compacted connected entries
+ * in sample-major, group-ascending order: d_entry_sample[e] (i32),
+ * d_entry_x[e] = x_i ^ f_g (u64), d_entry_h[2*e..] = sum over the group's
+ * terms of ct_k (-1)^{popcount(x_i & z_k)} summed sequentially in canonical
+ * order (FP64).  Entry buffers must hold `capacity` entries; the count is
+ * written to d_n_entries[0] (if it exceeds capacity only the first
+ * `capacity` are written and NQS_DEV_ENTRY_OVERFLOW is raised).  With dedup
+ * (plan flag) d_unique[u] receives the distinct x' (any order), d_n_unique[0]
+ * their number and d_entry_unique[e] the index of entry e's x' in d_unique;
+ * without dedup these outputs may be NULL.
+ */
+nqs_status nqs_connected(nqs_plan* plan, const uint64_t* d_samples, int64_t B, int64_t capacity,
+                         double* d_diag, int32_t* d_entry_sample, uint64_t* d_entry_x,
+                         double* d_entry_h, int64_t* d_n_entries, uint64_t* d_unique,
+                         int32_t* d_entry_unique, int64_t* d_n_unique, void* d_ws, size_t ws_bytes);
+
+/* Ratio-and-reduce with caller-supplied log amplitudes (for example an exact
+   eigenvector): d_eloc[i] = diag[i] + sum_{e: sample(e)=i} h_e
+   exp(logpsi_entry[e] - logpsi_sample[i]) (complex logs as (log|psi|, phi)
+   pairs).  Entries must be sample-major as produced by nqs_connected.  Sum in
+   FP64 with compensation, deterministic order. */
+nqs_status nqs_reduce_table(nqs_plan* plan, int64_t B, const double* d_logpsi_samples,
+                            const double* d_logpsi_entries, const double* d_diag,
+                            const int32_t* d_entry_sample, const double* d_entry_h,
+                            int64_t n_entries, double* d_eloc, void* d_ws, size_t ws_bytes);
+
+/* Synchronises the context's stream, reads the device error word of the
+   workspace d_ws into *flags (NQS_DEV_* bits) and clears it.  Not for use
+   inside graph capture. */
+nqs_status nqs_device_status(nqs_ctx* ctx, void* d_ws, uint32_t* flags);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NQS_H */

@@ -24,9 +24,24 @@ UP_MASK = np.uint64(0x5555555555555555)
 DN_MASK = np.uint64(0xAAAAAAAAAAAAAAAA)
 
 
-def log_psi(net, params, configs):
-    """Complex log psi for each configuration; -inf real part off-sector."""
-    la, phi, _ = made.forward(net, params, configs)
+def log_psi(net, params, configs, rows=32768):
+    """Complex log psi for each configuration; -inf real part off-sector.
+
+    Configurations that contradict a forced value of the modifier have
+    amplitude 0 whatever the network outputs, so the network is evaluated
+    only on the others (in batches of ``rows``); the values are those of
+    ``made.forward``.
+    """
+    configs = np.asarray(configs, dtype=np.uint64)
+    la = np.full(len(configs), -np.inf)
+    phi = np.zeros(len(configs))
+    _, bad = made.constraint(net, made.bits(net, configs))
+    idx = np.nonzero(~bad)[0]
+    for s in range(0, len(idx), rows):
+        sel = idx[s:s + rows]
+        a, p, _ = made.forward(net, params, configs[sel])
+        la[sel] = a
+        phi[sel] = p
     return la, phi
 
 

@@ -1,0 +1,285 @@
+"""Python binding of the nqs C ABI.
+
+Argument marshalling only: every step of the path runs in the HIP library.
+PyTorch supplies device memory (tensors) and the stream
+(``torch.cuda.current_stream()``).  Samples are uint64 bit strings; as torch
+has few uint64 ops they travel as int64 tensors with the same bits.
+"""
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _as_u64_tensor(x, device):
+    if isinstance(x, torch.Tensor):
+        if x.dtype not in (torch.int64, torch.uint64):
+            raise TypeError("samples must be an int64/uint64 tensor of bit strings")
+        return x.to(device).contiguous()
+    arr = np.ascontiguousarray(np.asarray(x, dtype=np.uint64)).view(np.int64)
+    return torch.from_numpy(arr.copy()).to(device)
+
+
+class Context:
+    """A device + stream binding (no device memory is allocated)."""
+
+    def __init__(self, device=0, stream=None):
+        self.lib = L.load()
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        L.check(self.lib.nqs_ctx_create(device, C.c_void_p(self.stream.cuda_stream), C.byref(h)),
+                "nqs_ctx_create")
+        self.handle = h
+
+    def use_stream(self, stream):
+        self.stream = stream
+        L.check(self.lib.nqs_ctx_set_stream(self.handle, C.c_void_p(stream.cuda_stream)),
+                "nqs_ctx_set_stream")
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            self.lib.nqs_ctx_destroy(self.handle)
+            self.handle = None
+
+
+class Hamiltonian:
+    """Pauli-string Hamiltonian canonicalised on the host (merge, drop, fold, sort, group)."""
+
+    def __init__(self, n_qubits, x_mask, z_mask, coeff, coeff_imag=None, drop_tol=1e-10,
+                 conserves_spin=True):
+        self.lib = L.load()
+        self.n = int(n_qubits)
+        self._x = np.ascontiguousarray(np.asarray(x_mask, dtype=np.uint64))
+        self._z = np.ascontiguousarray(np.asarray(z_mask, dtype=np.uint64))
+        self._c = np.ascontiguousarray(np.asarray(coeff, dtype=np.float64))
+        self._ci = None if coeff_imag is None else np.ascontiguousarray(np.asarray(coeff_imag, dtype=np.float64))
+        t = L.PauliTerms(self.n, len(self._x), self._x.ctypes.data, self._z.ctypes.data,
+                         self._c.ctypes.data, None if self._ci is None else self._ci.ctypes.data,
+                         float(drop_tol), L.NQS_H_CONSERVES_SPIN_SECTORS if conserves_spin else 0)
+        h = C.c_void_p()
+        L.check(self.lib.nqs_ham_create(C.byref(t), C.byref(h)), "nqs_ham_create")
+        self.handle = h
+        K, G, nb = C.c_int64(), C.c_int64(), C.c_size_t()
+        im, nq = C.c_int(), C.c_int()
+        L.check(self.lib.nqs_ham_info(h, C.byref(K), C.byref(G), C.byref(nb), C.byref(im), C.byref(nq)),
+                "nqs_ham_info")
+        self.K, self.G, self.bytes, self.has_imag = K.value, G.value, nb.value, bool(im.value)
+        self.storage = None
+
+    @classmethod
+    def from_terms(cls, terms, **kw):
+        return cls(terms.n_qubits, terms.x_mask, terms.z_mask, terms.coeff, **kw)
+
+    def upload(self, ctx):
+        self.storage = torch.empty(self.bytes + 256, dtype=torch.uint8, device=ctx.device)
+        base = self.storage.data_ptr()
+        aligned = (base + 255) & ~255
+        L.check(self.lib.nqs_ham_upload(self.handle, ctx.handle, C.c_void_p(aligned), self.bytes),
+                "nqs_ham_upload")
+        return self
+
+    def export(self):
+        gx = np.zeros(self.G, dtype=np.uint64)
+        goff = np.zeros(self.G + 1, dtype=np.int64)
+        tz = np.zeros(self.K, dtype=np.uint64)
+        tre = np.zeros(self.K, dtype=np.float64)
+        tim = np.zeros(self.K, dtype=np.float64)
+        L.check(self.lib.nqs_ham_export(self.handle, gx.ctypes.data, goff.ctypes.data, tz.ctypes.data,
+                                        tre.ctypes.data, tim.ctypes.data), "nqs_ham_export")
+        return dict(gx=gx, goff=goff, tz=tz, tre=tre, tim=tim)
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            self.lib.nqs_ham_destroy(self.handle)
+            self.handle = None
+
+
+def net_desc(n_qubits, n_layers, width, n_up=-1, n_dn=-1, precision="fp32", order=None):
+    order_arr = None
+    if order is not None:
+        order_arr = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+    d = L.NetDesc(int(n_qubits), int(n_layers), int(width),
+                  None if order_arr is None else order_arr.ctypes.data, int(n_up), int(n_dn),
+                  L.PRECISIONS[precision] if isinstance(precision, str) else int(precision))
+    return d, order_arr
+
+
+def param_count(n_qubits, n_layers, width, precision="fp32"):
+    lib = L.load()
+    d, keep = net_desc(n_qubits, n_layers, width, precision=precision)
+    out = C.c_int64()
+    L.check(lib.nqs_net_param_count(C.byref(d), C.byref(out)), "nqs_net_param_count")
+    return out.value
+
+
+class Plan:
+    """Kernel variants, chunking and workspace layout for one (H, network) pair."""
+
+    def __init__(self, ctx, ham, n_layers, width, n_up=-1, n_dn=-1, precision="fp32",
+                 max_batch=1024, dedup=False, chunk_samples=0, order=None):
+        self.lib = L.load()
+        self.ctx, self.ham = ctx, ham
+        self.precision = precision
+        d, self._order = net_desc(ham.n, n_layers, width, n_up, n_dn, precision, order)
+        flags = L.NQS_PLAN_DEDUP_ON if dedup else L.NQS_PLAN_DEDUP_OFF
+        h = C.c_void_p()
+        L.check(self.lib.nqs_plan_create(ctx.handle, ham.handle, C.byref(d), int(max_batch), flags,
+                                         int(chunk_samples), C.byref(h)), "nqs_plan_create")
+        self.handle = h
+        e, cs, dd, npar = C.c_int64(), C.c_int64(), C.c_int(), C.c_int64()
+        L.check(self.lib.nqs_plan_info(h, C.byref(e), C.byref(cs), C.byref(dd), C.byref(npar)),
+                "nqs_plan_info")
+        self.entries_per_sample, self.chunk_samples = e.value, cs.value
+        self.dedup, self.n_params = bool(dd.value), npar.value
+        self.max_batch = int(max_batch)
+        self._ws = None
+
+    def workspace_size(self, B):
+        out = C.c_size_t()
+        L.check(self.lib.nqs_plan_workspace_size(self.handle, int(B), C.byref(out)),
+                "nqs_plan_workspace_size")
+        return out.value
+
+    def workspace(self, B=None):
+        """A cached device workspace large enough for batch B (default: max_batch)."""
+        need = self.workspace_size(self.max_batch if B is None else B)
+        if self._ws is None or self._ws[1] < need:
+            raw = torch.empty(need + 256, dtype=torch.uint8, device=self.ctx.device)
+            aligned = (raw.data_ptr() + 255) & ~255
+            self._ws = (raw, need, aligned)
+        return C.c_void_p(self._ws[2]), self._ws[1]
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            self.lib.nqs_plan_destroy(self.handle)
+            self.handle = None
+
+
+def _params(plan, params):
+    if params.dtype != torch.float32 or not params.is_cuda or params.numel() != plan.n_params:
+        raise ValueError(f"params must be a float32 CUDA tensor of {plan.n_params} entries")
+    return params.contiguous()
+
+
+def log_psi(plan, params, x):
+    params = _params(plan, params)
+    x = _as_u64_tensor(x, plan.ctx.device)
+    out = torch.empty((x.numel(), 2), dtype=torch.float64, device=plan.ctx.device)
+    ws, nb = plan.workspace()
+    L.check(plan.lib.nqs_log_psi(plan.handle, _ptr(params), _ptr(x), x.numel(), _ptr(out), ws, nb),
+            "nqs_log_psi")
+    return out
+
+
+def local_energy(plan, params, samples):
+    params = _params(plan, params)
+    x = _as_u64_tensor(samples, plan.ctx.device)
+    out = torch.empty((x.numel(), 2), dtype=torch.float64, device=plan.ctx.device)
+    ws, nb = plan.workspace()
+    L.check(plan.lib.nqs_local_energy(plan.handle, _ptr(params), _ptr(x), x.numel(), _ptr(out), ws, nb),
+            "nqs_local_energy")
+    return out
+
+
+def energy_grad(plan, params, samples, weights=None, eloc=None, energy=None, grad=None):
+    """(energy[3] = (E, Im mean, W), grad f64 [n_params], eloc [B,2]) on the device."""
+    params = _params(plan, params)
+    dev = plan.ctx.device
+    x = _as_u64_tensor(samples, dev)
+    B = x.numel()
+    w = None
+    if weights is not None:
+        w = torch.as_tensor(weights, dtype=torch.float64).to(dev).contiguous()
+    eloc = torch.empty((B, 2), dtype=torch.float64, device=dev) if eloc is None else eloc
+    energy = torch.empty(3, dtype=torch.float64, device=dev) if energy is None else energy
+    grad = torch.empty(plan.n_params, dtype=torch.float64, device=dev) if grad is None else grad
+    ws, nb = plan.workspace()
+    L.check(plan.lib.nqs_energy_grad(plan.handle, _ptr(params), _ptr(x), _ptr(w), B, _ptr(eloc),
+                                     _ptr(energy), _ptr(grad), ws, nb), "nqs_energy_grad")
+    return energy, grad, eloc
+
+
+def energy_grad_multi(items, workspace):
+    """items: list of dicts with plan, params, samples, weights, eloc, energy, grad tensors."""
+    arr = (L.Instance * len(items))()
+    for i, it in enumerate(items):
+        arr[i] = L.Instance(it["plan"].handle.value, it["params"].data_ptr(), it["samples"].data_ptr(),
+                            it["weights"].data_ptr() if it.get("weights") is not None else None,
+                            it["samples"].numel(),
+                            it["eloc"].data_ptr() if it.get("eloc") is not None else None,
+                            it["energy"].data_ptr(), it["grad"].data_ptr())
+    ws, nb = workspace
+    lib = L.load()
+    L.check(lib.nqs_energy_grad_multi(len(items), arr, ws, nb), "nqs_energy_grad_multi")
+
+
+def connected(plan, samples, capacity=None):
+    dev = plan.ctx.device
+    x = _as_u64_tensor(samples, dev)
+    B = x.numel()
+    cap = int(capacity if capacity is not None else max(1, B * plan.entries_per_sample))
+    out = dict(
+        diag=torch.empty((B, 2), dtype=torch.float64, device=dev),
+        sample=torch.empty(cap, dtype=torch.int32, device=dev),
+        x=torch.empty(cap, dtype=torch.int64, device=dev),
+        h=torch.empty((cap, 2), dtype=torch.float64, device=dev),
+        n_entries=torch.zeros(1, dtype=torch.int64, device=dev),
+    )
+    if plan.dedup:
+        out.update(unique=torch.empty(cap, dtype=torch.int64, device=dev),
+                   entry_unique=torch.empty(cap, dtype=torch.int32, device=dev),
+                   n_unique=torch.zeros(1, dtype=torch.int64, device=dev))
+    ws, nb = plan.workspace()
+    L.check(plan.lib.nqs_connected(plan.handle, _ptr(x), B, cap, _ptr(out["diag"]), _ptr(out["sample"]),
+                                   _ptr(out["x"]), _ptr(out["h"]), _ptr(out["n_entries"]),
+                                   _ptr(out.get("unique")), _ptr(out.get("entry_unique")),
+                                   _ptr(out.get("n_unique")), ws, nb), "nqs_connected")
+    return out
+
+
+def reduce_table(plan, logpsi_samples, logpsi_entries, diag, entry_sample, entry_h, n_entries):
+    dev = plan.ctx.device
+    B = logpsi_samples.shape[0]
+    eloc = torch.empty((B, 2), dtype=torch.float64, device=dev)
+    ws, nb = plan.workspace()
+    L.check(plan.lib.nqs_reduce_table(plan.handle, B, _ptr(logpsi_samples.contiguous()),
+                                      _ptr(logpsi_entries.contiguous()), _ptr(diag.contiguous()),
+                                      _ptr(entry_sample.contiguous()), _ptr(entry_h.contiguous()),
+                                      int(n_entries), _ptr(eloc), ws, nb), "nqs_reduce_table")
+    return eloc
+
+
+def device_status(plan):
+    ws, _ = plan.workspace()
+    flags = C.c_uint32()
+    st = plan.lib.nqs_device_status(plan.ctx.handle, ws, C.byref(flags))
+    if st not in (L.NQS_OK, 6):
+        L.check(st, "nqs_device_status")
+    return flags.value
+
+
+class EnergyFn(torch.autograd.Function):
+    """(E, eloc) = EnergyFn.apply(params, samples, weights, plan).
+
+    backward returns dL/dE * g with g the VMC gradient of E = <H> (Eq. grad
+    with baseline E, times 2); the local energies are treated as constants,
+    so this is the estimator, not autodiff of the returned estimate.
+    """
+
+    @staticmethod
+    def forward(ctx, params, samples, weights, plan):
+        energy, grad, eloc = energy_grad(plan, params, samples, weights)
+        ctx.save_for_backward(grad)
+        return energy[0].clone(), eloc
+
+    @staticmethod
+    def backward(ctx, g_energy, g_eloc):
+        (grad,) = ctx.saved_tensors
+        return (g_energy * grad).to(torch.float32), None, None, None

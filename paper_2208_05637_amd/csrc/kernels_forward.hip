@@ -1,0 +1,460 @@
+// Fused masked-MLP forward on MFMA: x (uint64 bit string) -> (log|psi|, phi).
+//
+// One workgroup (8 waves) owns a tile of M configurations and carries them
+// through every layer of the network of Sec. 4 without leaving the CU:
+//   * prologue: the configuration bits are permuted into sampling order and
+//     the +-1 input fragments of the first layer are generated in registers
+//     (no input matrix in memory);
+//   * each layer computes C^T = W A^T with MFMA, W streamed from L2 in a
+//     pre-packed fragment layout (1 KB per (unit block, k step), coalesced),
+//     A read from LDS, where the activations of the tile live in MFMA operand
+//     order; bias + ReLU + conversion are applied on the accumulators and
+//     written back in place;
+//   * hidden units are sorted by MADE degree, so every mask is a prefix and
+//     fully masked (block, k step) pairs are neither stored nor multiplied;
+//   * the head produces the n conditional logits and the 4 phases; the
+//     per-row epilogue applies the Hamming-weight modifier (Eq. modifier),
+//     sums the log-sigmoids of free positions in FP64 and selects the phase.
+#include "nqs_internal.h"
+
+namespace nqs {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __attribute__((ext_vector_type(4))) double f64x4;
+
+template <int P> struct Tr;
+template <> struct Tr<P_BF16> {
+  static constexpr int TB = 32, KSTEP = 16, PL = 1, MH = 65536;
+  using Acc = f32x16; using S = float;
+  static constexpr int NACC = 16;
+};
+template <> struct Tr<P_BF16X3> {
+  static constexpr int TB = 32, KSTEP = 16, PL = 2, MH = 32768;
+  using Acc = f32x16; using S = float;
+  static constexpr int NACC = 16;
+};
+template <> struct Tr<P_F32> {
+  static constexpr int TB = 32, KSTEP = 8, PL = 1, MH = 32768;
+  using Acc = f32x16; using S = float;
+  static constexpr int NACC = 16;
+};
+template <> struct Tr<P_F64> {
+  static constexpr int TB = 16, KSTEP = 8, PL = 1, MH = 8192;
+  using Acc = f64x4; using S = double;
+  static constexpr int NACC = 4;
+};
+
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(unsigned short h) {
+  return __uint_as_float(((unsigned)h) << 16);
+}
+
+template <int P>
+__device__ __forceinline__ void mma(typename Tr<P>::Acc& acc, const uint4* w, const uint4* a) {
+  if constexpr (P == P_BF16) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, w[0]),
+                                                  __builtin_bit_cast(bf16x8, a[0]), acc, 0, 0, 0);
+  } else if constexpr (P == P_BF16X3) {
+    bf16x8 wh = __builtin_bit_cast(bf16x8, w[0]), wl = __builtin_bit_cast(bf16x8, w[1]);
+    bf16x8 ah = __builtin_bit_cast(bf16x8, a[0]), al = __builtin_bit_cast(bf16x8, a[1]);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wl, ah, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, al, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, ah, acc, 0, 0, 0);
+  } else if constexpr (P == P_F32) {
+    float4 wf = __builtin_bit_cast(float4, w[0]);
+    float4 af = __builtin_bit_cast(float4, a[0]);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wf.x, af.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wf.y, af.y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wf.z, af.z, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wf.w, af.w, acc, 0, 0, 0);
+  } else {
+    double2 wd = __builtin_bit_cast(double2, w[0]);
+    double2 ad = __builtin_bit_cast(double2, a[0]);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(wd.x, ad.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(wd.y, ad.y, acc, 0, 0, 0);
+  }
+}
+
+// +-1 input fragment of the first layer for m-block mb, k step ks.
+// Element (row m, k) is +1/-1 for occupied/empty position k < n, 0 beyond.
+template <int P>
+__device__ __forceinline__ void input_frag(const uint64_t* ylds, int mb, int ks, int lane, int n,
+                                           uint4* out) {
+  using T = Tr<P>;
+  if constexpr (P == P_BF16 || P == P_BF16X3) {
+    uint64_t y = ylds[mb * 32 + (lane & 31)];
+    int k0 = ks * 16 + 8 * (lane >> 5);
+    unsigned short v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      int k = k0 + j;
+      v[j] = k < n ? (((y >> k) & 1ull) ? (unsigned short)0x3F80 : (unsigned short)0xBF80)
+                   : (unsigned short)0;
+    }
+    out[0] = make_uint4(v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16),
+                        v[6] | (v[7] << 16));
+    if constexpr (T::PL == 2) out[1] = make_uint4(0, 0, 0, 0);
+  } else if constexpr (P == P_F32) {
+    uint64_t y = ylds[mb * 32 + (lane & 31)];
+    int k0 = ks * 8 + 4 * (lane >> 5);
+    float v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int k = k0 + j;
+      v[j] = k < n ? (((y >> k) & 1ull) ? 1.f : -1.f) : 0.f;
+    }
+    out[0] = __builtin_bit_cast(uint4, make_float4(v[0], v[1], v[2], v[3]));
+  } else {
+    uint64_t y = ylds[mb * 16 + (lane & 15)];
+    int k0 = ks * 8 + 2 * (lane >> 4);
+    double v[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      int k = k0 + j;
+      v[j] = k < n ? (((y >> k) & 1ull) ? 1.0 : -1.0) : 0.0;
+    }
+    out[0] = __builtin_bit_cast(uint4, make_double2(v[0], v[1]));
+  }
+}
+
+// Write relu(acc + bias) of tile (nb, mb) into the LDS activations, in the
+// operand order of the next layer.
+template <int P, int MB>
+__device__ __forceinline__ void store_act(char* act, const typename Tr<P>::Acc& acc,
+                                          const typename Tr<P>::S* bias, int nb, int mb, int lane,
+                                          int KSH) {
+  using T = Tr<P>;
+  if constexpr (P == P_F64) {
+    const int m = lane & 15, g = lane >> 4;
+    const int n0 = 16 * nb + 4 * g;
+    double v[4];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      double t = acc[rr] + bias[n0 + rr];
+      v[rr] = t > 0.0 ? t : 0.0;
+    }
+    const int ks = 2 * nb + (g >> 1);
+    const int lp = m + 32 * (g & 1);
+    char* base = act + ((long)(ks * MB + mb) * 64) * 16;
+    *(double2*)(base + lp * 16) = make_double2(v[0], v[1]);
+    *(double2*)(base + (lp + 16) * 16) = make_double2(v[2], v[3]);
+  } else {
+    const int m = lane & 31, hf = lane >> 5;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int n0 = 32 * nb + 8 * q + 4 * hf;
+      const float4 b4 = *(const float4*)(bias + n0);
+      float v0 = acc[4 * q + 0] + b4.x, v1 = acc[4 * q + 1] + b4.y;
+      float v2 = acc[4 * q + 2] + b4.z, v3 = acc[4 * q + 3] + b4.w;
+      v0 = v0 > 0.f ? v0 : 0.f; v1 = v1 > 0.f ? v1 : 0.f;
+      v2 = v2 > 0.f ? v2 : 0.f; v3 = v3 > 0.f ? v3 : 0.f;
+      if constexpr (P == P_F32) {
+        const int ks = 4 * nb + q;
+        const int lp = m + 32 * hf;
+        *(float4*)(act + ((long)(ks * MB + mb) * 64 + lp) * 16) = make_float4(v0, v1, v2, v3);
+      } else {
+        const int ks = 2 * nb + (q >> 1);
+        const int lp = m + 32 * (q & 1);
+        unsigned short h0 = bf16_rne(v0), h1 = bf16_rne(v1), h2 = bf16_rne(v2), h3 = bf16_rne(v3);
+        char* dst = act + ((long)(ks * MB + mb) * 64 + lp) * 16 + 8 * hf;
+        *(uint2*)dst = make_uint2(h0 | ((unsigned)h1 << 16), h2 | ((unsigned)h3 << 16));
+        if constexpr (T::PL == 2) {
+          unsigned short l0 = bf16_rne(v0 - bf16_to_f(h0)), l1 = bf16_rne(v1 - bf16_to_f(h1));
+          unsigned short l2 = bf16_rne(v2 - bf16_to_f(h2)), l3 = bf16_rne(v3 - bf16_to_f(h3));
+          char* dlo = dst + (long)KSH * MB * 64 * 16;
+          *(uint2*)dlo = make_uint2(l0 | ((unsigned)l1 << 16), l2 | ((unsigned)l3 << 16));
+        }
+      }
+    }
+  }
+}
+
+template <typename S>
+__device__ __forceinline__ S softplus(S z) {
+  S a = z > S(0) ? z : -z;
+  S m = z > S(0) ? z : S(0);
+  if constexpr (sizeof(S) == 4) return m + log1pf(expf(-a));
+  else return m + log1p(exp(-a));
+}
+
+template <int P, int H>
+__global__ __launch_bounds__(kThreads) void fused_forward(Geom g, const uint4* __restrict__ wpk,
+                                                          const uint64_t* __restrict__ xs,
+                                                          long long rows_bound,
+                                                          const long long* __restrict__ d_count,
+                                                          double2* __restrict__ out) {
+  using T = Tr<P>;
+  using Acc = typename T::Acc;
+  using S = typename T::S;
+  constexpr int TB = T::TB, PL = T::PL, NACC = T::NACC;
+  constexpr int M = T::MH / H;
+  constexpr int NB = H / TB, MB = M / TB;
+  constexpr int WN = NB < 8 ? NB : 8, WM = 8 / WN;
+  constexpr int NBW = NB / WN, MBW = MB / WM;
+  constexpr int KSH = H / T::KSTEP;
+  constexpr int NHBMAX = (68 + TB - 1) / TB;
+  constexpr int HP = (NHBMAX * MB + 7) / 8;
+  constexpr int SP = NHBMAX * TB + 1;
+  static_assert(MB % WM == 0 && NB % WN == 0 && MB >= 1, "tile shape");
+
+  extern __shared__ uint4 smem[];
+  char* act = (char*)smem;
+  constexpr long ACT_BYTES = (long)PL * KSH * MB * 1024;
+  constexpr long STAGE_BYTES = (long)M * SP * sizeof(S);
+  constexpr long REGION = ACT_BYTES > STAGE_BYTES ? ACT_BYTES : STAGE_BYTES;
+  uint64_t* ylds = (uint64_t*)(act + REGION);
+  S* stage = (S*)act;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wn = wave % WN, wm = wave / WN;
+  long long count = rows_bound;
+  if (d_count) {
+    long long c = *d_count;
+    count = c < rows_bound ? c : rows_bound;
+  }
+  const long long row0 = (long long)blockIdx.x * M;
+  if (row0 >= count) return;
+
+  const long long plane_stride = g.nfrag * 64;   // uint4 per plane
+  const S* biases = (const S*)((const char*)wpk + g.bias_byte);
+
+  for (int t = tid; t < M; t += kThreads) {
+    long long row = row0 + t;
+    uint64_t x = xs[row < count ? row : row0];
+    uint64_t y = 0;
+    for (int p = 0; p < g.n; ++p) y |= ((x >> g.order[p]) & 1ull) << p;
+    ylds[t] = y;
+  }
+  __syncthreads();
+
+  int nbl[NBW], mbl[MBW];
+#pragma unroll
+  for (int i = 0; i < NBW; ++i) nbl[i] = (i & 1) ? (i * WN + WN - 1 - wn) : (i * WN + wn);
+#pragma unroll
+  for (int j = 0; j < MBW; ++j) mbl[j] = j * WM + wm;
+
+  Acc acc[NBW][MBW];
+
+  // ---------------------------------------------------------------- layer 1
+  {
+#pragma unroll
+    for (int i = 0; i < NBW; ++i)
+#pragma unroll
+      for (int j = 0; j < MBW; ++j) acc[i][j] = Acc{};
+    int ksi[NBW], offi[NBW], ksmax = 0;
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) {
+      ksi[i] = g.ks1[nbl[i]];
+      offi[i] = g.off1[nbl[i]];
+      ksmax = ksi[i] > ksmax ? ksi[i] : ksmax;
+    }
+    for (int ks = 0; ks < ksmax; ++ks) {
+      uint4 af[MBW][PL];
+#pragma unroll
+      for (int j = 0; j < MBW; ++j) input_frag<P>(ylds, mbl[j], ks, lane, g.n, af[j]);
+#pragma unroll
+      for (int i = 0; i < NBW; ++i) {
+        if (ks < ksi[i]) {
+          uint4 wf[PL];
+          const uint4* src = wpk + ((long long)(offi[i] + ks)) * 64 + lane;
+          wf[0] = src[0];
+          if constexpr (PL == 2) wf[1] = src[plane_stride];
+#pragma unroll
+          for (int j = 0; j < MBW; ++j) mma<P>(acc[i][j], wf, af[j]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NBW; ++i)
+#pragma unroll
+      for (int j = 0; j < MBW; ++j) store_act<P, MB>(act, acc[i][j], biases, nbl[i], mbl[j], lane, KSH);
+    __syncthreads();
+  }
+
+  // ----------------------------------------------------------- hidden layers
+  for (int l = 2; l <= g.L; ++l) {
+#pragma unroll
+    for (int i = 0; i < NBW; ++i)
+#pragma unroll
+      for (int j = 0; j < MBW; ++j) acc[i][j] = Acc{};
+    const long long lbase = g.frag_h + (long long)(l - 2) * g.offh[NB];
+    int ksi[NBW], ksmax = 0;
+    long long offi[NBW];
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) {
+      ksi[i] = g.ksh[nbl[i]];
+      offi[i] = lbase + g.offh[nbl[i]];
+      ksmax = ksi[i] > ksmax ? ksi[i] : ksmax;
+    }
+    for (int ks = 0; ks < ksmax; ++ks) {
+      uint4 af[MBW][PL];
+#pragma unroll
+      for (int j = 0; j < MBW; ++j) {
+        const uint4* a = (const uint4*)act + ((long)(ks * MB + mbl[j])) * 64 + lane;
+        af[j][0] = a[0];
+        if constexpr (PL == 2) af[j][1] = a[(long)KSH * MB * 64];
+      }
+#pragma unroll
+      for (int i = 0; i < NBW; ++i) {
+        if (ks < ksi[i]) {
+          uint4 wf[PL];
+          const uint4* src = wpk + (offi[i] + ks) * 64 + lane;
+          wf[0] = src[0];
+          if constexpr (PL == 2) wf[1] = src[plane_stride];
+#pragma unroll
+          for (int j = 0; j < MBW; ++j) mma<P>(acc[i][j], wf, af[j]);
+        }
+      }
+    }
+    __syncthreads();
+    const S* bl = biases + (long)(l - 1) * H;
+#pragma unroll
+    for (int i = 0; i < NBW; ++i)
+#pragma unroll
+      for (int j = 0; j < MBW; ++j) store_act<P, MB>(act, acc[i][j], bl, nbl[i], mbl[j], lane, KSH);
+    __syncthreads();
+  }
+
+  // -------------------------------------------------------------------- head
+  Acc hacc[HP];
+  const int npairs = g.NHB * MB;
+#pragma unroll
+  for (int hp = 0; hp < HP; ++hp) {
+    hacc[hp] = Acc{};
+    const int pr = wave + 8 * hp;
+    if (pr < npairs) {
+      const int nb = pr / MB, mb = pr % MB;
+      const int kso = g.kso[nb];
+      const long long base = g.frag_head + g.offo[nb];
+      for (int ks = 0; ks < kso; ++ks) {
+        uint4 af[PL], wf[PL];
+        const uint4* a = (const uint4*)act + ((long)(ks * MB + mb)) * 64 + lane;
+        af[0] = a[0];
+        if constexpr (PL == 2) af[1] = a[(long)KSH * MB * 64];
+        const uint4* src = wpk + (base + ks) * 64 + lane;
+        wf[0] = src[0];
+        if constexpr (PL == 2) wf[1] = src[plane_stride];
+        mma<P>(hacc[hp], wf, af);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int hp = 0; hp < HP; ++hp) {
+    const int pr = wave + 8 * hp;
+    if (pr < npairs) {
+      const int nb = pr / MB, mb = pr % MB;
+      if constexpr (P == P_F64) {
+        const int m = mb * 16 + (lane & 15), gq = lane >> 4;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) stage[m * SP + nb * 16 + 4 * gq + rr] = hacc[hp][rr];
+      } else {
+        const int m = mb * 32 + (lane & 31), hf = lane >> 5;
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          stage[m * SP + nb * 32 + 8 * (r >> 2) + 4 * hf + (r & 3)] = hacc[hp][r];
+      }
+    }
+  }
+  __syncthreads();
+
+  // ------------------------------------------------------------ row epilogue
+  constexpr int TPR = kThreads / M >= 1 ? kThreads / M : 1;
+  const int row = tid / TPR, sub = tid % TPR;
+  if (row < M) {
+    const S* hb = biases + (long)g.L * H;
+    const uint64_t y = ylds[row];
+    const bool constrained = g.n_up >= 0 && g.n_dn >= 0;
+    double sum = 0.0;
+    int bad = 0;
+    for (int t = sub; t < g.n; t += TPR) {
+      const S o = stage[row * SP + t] + hb[t];
+      const int sp = g.order[t] & 1;
+      const int bit = (int)((y >> t) & 1ull);
+      bool fr = true;
+      if (constrained) {
+        const uint64_t low = t == 0 ? 0ull : (~0ull >> (64 - t));
+        const uint64_t high = t >= 63 ? 0ull : (~0ull << (t + 1));
+        const int c = __popcll(y & g.spin_pos[sp] & low);
+        const int rem = __popcll(g.spin_pos[sp] & high);
+        const int ns = sp ? g.n_dn : g.n_up;
+        const bool f0 = c >= ns, f1 = c + rem < ns;
+        bad |= (f0 && bit) || (f1 && !bit);
+        fr = !(f0 || f1);
+      }
+      if (fr) sum -= (double)softplus<S>(bit ? -o : o);
+    }
+#pragma unroll
+    for (int off = TPR / 2; off >= 1; off >>= 1) {
+      sum += __shfl_xor(sum, off);
+      bad |= __shfl_xor(bad, off);
+    }
+    const long long grow = row0 + row;
+    if (sub == 0 && grow < count) {
+      const int sel = (int)(2 * ((y >> (g.n - 2)) & 1ull) + ((y >> (g.n - 1)) & 1ull));
+      const double phi = (double)(stage[row * SP + g.n + sel] + hb[g.n + sel]);
+      out[grow] = make_double2(bad ? -INFINITY : 0.5 * sum, phi);
+    }
+  }
+}
+
+template <int P, int H>
+static void launch_one(const Geom& g, const void* packed, const uint64_t* x, long long rows_bound,
+                       const long long* d_count, double* out, hipStream_t s) {
+  using T = Tr<P>;
+  constexpr int M = T::MH / H;
+  constexpr int KSH = H / T::KSTEP;
+  constexpr int MB = M / T::TB;
+  constexpr int NHBMAX = (68 + T::TB - 1) / T::TB;
+  constexpr int SP = NHBMAX * T::TB + 1;
+  constexpr long ACT = (long)T::PL * KSH * MB * 1024;
+  constexpr long STG = (long)M * SP * sizeof(typename T::S);
+  constexpr size_t LDS = (ACT > STG ? ACT : STG) + M * 8;
+  static_assert(LDS <= 160 * 1024, "LDS budget");
+  auto kern = fused_forward<P, H>;
+  static bool attr_done = false;
+  if (!attr_done) {
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS);
+    attr_done = true;
+  }
+  long long blocks = (rows_bound + M - 1) / M;
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kThreads), LDS, s, g,
+                     (const uint4*)packed, x, rows_bound, d_count, (double2*)out);
+}
+
+int forward_rows_per_block(int prec, int h) {
+  switch (prec) {
+    case P_BF16: return 65536 / h;
+    case P_BF16X3: return 32768 / h;
+    case P_F32: return 32768 / h;
+    default: return 8192 / h;
+  }
+}
+
+bool forward_supported(int prec, int h) {
+  switch (prec) {
+    case P_BF16: case P_BF16X3: return h == 256 || h == 512 || h == 1024;
+    case P_F32: return h == 128 || h == 256 || h == 512 || h == 1024;
+    case P_F64: return h == 64 || h == 128 || h == 256 || h == 512;
+  }
+  return false;
+}
+
+void launch_forward(const Geom& g, const void* packed, const uint64_t* x, long long rows_bound,
+                    const long long* d_count, double* out, hipStream_t s) {
+#define NQS_CASE(P, H) \
+  if (g.prec == P && g.h == H) { launch_one<P, H>(g, packed, x, rows_bound, d_count, out, s); return; }
+  NQS_CASE(P_BF16, 256) NQS_CASE(P_BF16, 512) NQS_CASE(P_BF16, 1024)
+  NQS_CASE(P_BF16X3, 256) NQS_CASE(P_BF16X3, 512) NQS_CASE(P_BF16X3, 1024)
+  NQS_CASE(P_F32, 128) NQS_CASE(P_F32, 256) NQS_CASE(P_F32, 512) NQS_CASE(P_F32, 1024)
+  NQS_CASE(P_F64, 64) NQS_CASE(P_F64, 128) NQS_CASE(P_F64, 256) NQS_CASE(P_F64, 512)
+#undef NQS_CASE
+}
+
+}  // namespace nqs

@@ -1,0 +1,468 @@
+// Hamiltonian-side kernels: enumeration of connected configurations with
+// their matrix elements (Sec. 5.1, Eq. mtx_element, Alg. 1), deduplication of
+// connected configurations per chunk (Sec. 5.2), the ratio-and-reduce of
+// Eq. local_energy_auto and the weighted energy of Eq. total_energy_sum.
+#include "nqs_internal.h"
+
+namespace nqs {
+
+constexpr uint64_t kUp = 0x5555555555555555ull;
+constexpr uint64_t kDn = 0xAAAAAAAAAAAAAAAAull;
+
+__global__ void fill_u32_kernel(unsigned* p, unsigned v, long long count) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) p[i] = v;
+}
+__global__ void fill_u64_kernel(unsigned long long* p, unsigned long long v, long long count) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) p[i] = v;
+}
+void launch_fill_u32(void* p, unsigned v, long long count, hipStream_t s) {
+  if (count <= 0) return;
+  long long blocks = (count + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (unsigned*)p, v, count);
+}
+void launch_fill_u64(void* p, unsigned long long v, long long count, hipStream_t s) {
+  if (count <= 0) return;
+  long long blocks = (count + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                     (unsigned long long*)p, v, count);
+}
+
+// h_g(x) = sum_{k in g} ct_k (-1)^{popcount(x & z_k)}, sequential in canonical
+// order; the sign is applied by flipping the sign bit (exact).
+template <bool IMAG>
+__device__ __forceinline__ void group_h(const HamDev& H, uint64_t x, long long k0, long long k1,
+                                        double& re, double& im) {
+  double a = 0.0, b = 0.0;
+  for (long long k = k0; k < k1; ++k) {
+    const unsigned long long par = (unsigned long long)(__popcll(x & H.tz[k]) & 1) << 63;
+    a += __longlong_as_double(__double_as_longlong(H.tre[k]) ^ par);
+    if constexpr (IMAG) b += __longlong_as_double(__double_as_longlong(H.tim[k]) ^ par);
+  }
+  re = a;
+  im = b;
+}
+
+__device__ __forceinline__ bool sector_ok(uint64_t x, uint64_t f) {
+  return 2 * __popcll(x & f & kUp) == __popcll(f & kUp) &&
+         2 * __popcll(x & f & kDn) == __popcll(f & kDn);
+}
+
+template <bool IMAG>
+__global__ void diag_kernel(HamDev H, const uint64_t* __restrict__ xs, long long S,
+                            double* __restrict__ diag) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S) return;
+  double re = 0.0, im = 0.0;
+  if (H.gfirst) group_h<IMAG>(H, xs[i], H.goff[0], H.goff[1], re, im);
+  diag[2 * i] = re;
+  diag[2 * i + 1] = im;
+}
+
+void launch_diag(const HamDev& H, const uint64_t* x, long long S, double* diag, hipStream_t s) {
+  if (S <= 0) return;
+  unsigned blocks = (unsigned)((S + 255) / 256);
+  if (H.tim) hipLaunchKernelGGL(diag_kernel<true>, dim3(blocks), dim3(256), 0, s, H, x, S, diag);
+  else hipLaunchKernelGGL(diag_kernel<false>, dim3(blocks), dim3(256), 0, s, H, x, S, diag);
+}
+
+// One thread per sample, one block row per range of gper groups (excluding
+// the empty flip).  Counts the valid (sample, group) pairs.
+template <bool IMAG>
+__global__ void count_kernel(HamDev H, const uint64_t* __restrict__ xs, long long S, int R, int gper,
+                             int* __restrict__ cnt) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  const int g0 = H.gfirst + r * gper;
+  const int g1 = min(H.G, g0 + gper);
+  const uint64_t x = xs[i < S ? i : 0];
+  int c = 0;
+  for (int g = g0; g < g1; ++g) {
+    const uint64_t f = H.gx[g];
+    bool ok;
+    if (H.filter) {
+      ok = sector_ok(x, f);
+    } else {
+      double re, im;
+      group_h<IMAG>(H, x, H.goff[g], H.goff[g + 1], re, im);
+      ok = (re != 0.0) || (im != 0.0);
+    }
+    c += ok ? 1 : 0;
+  }
+  if (i < S) cnt[i * R + r] = c;
+}
+
+void launch_count(const HamDev& H, const uint64_t* x, long long S, int R, int gper, int* cnt,
+                  hipStream_t s) {
+  if (S <= 0) return;
+  dim3 grid((unsigned)((S + 255) / 256), (unsigned)R);
+  if (H.tim) hipLaunchKernelGGL(count_kernel<true>, grid, dim3(256), 0, s, H, x, S, R, gper, cnt);
+  else hipLaunchKernelGGL(count_kernel<false>, grid, dim3(256), 0, s, H, x, S, R, gper, cnt);
+}
+
+// Exclusive scan of n counts into off[0..n] (off[n] = total), one workgroup.
+__global__ __launch_bounds__(1024) void scan_kernel(const int* __restrict__ cnt, long long n,
+                                                    long long* __restrict__ off) {
+  __shared__ long long part[1024];
+  const int t = threadIdx.x;
+  const long long per = (n + 1023) / 1024;
+  const long long a = t * per;
+  const long long b = a + per < n ? a + per : n;
+  long long s = 0;
+  for (long long i = a; i < b; ++i) s += cnt[i];
+  part[t] = s;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    long long v = t >= d ? part[t - d] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  long long run = t ? part[t - 1] : 0;
+  for (long long i = a; i < b; ++i) {
+    off[i] = run;
+    run += cnt[i];
+  }
+  if (t == 1023) off[n] = part[1023];
+}
+
+void launch_scan(const int* cnt, long long n, long long* off, hipStream_t s) {
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, cnt, n, off);
+}
+
+template <bool IMAG>
+__global__ void write_kernel(HamDev H, const uint64_t* __restrict__ xs, long long S, int R, int gper,
+                             const long long* __restrict__ off, long long cap,
+                             uint64_t* __restrict__ xe, double* __restrict__ he,
+                             int* __restrict__ esample, int hstride, unsigned* err) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  const int g0 = H.gfirst + r * gper;
+  const int g1 = min(H.G, g0 + gper);
+  const bool live = i < S;
+  const uint64_t x = xs[live ? i : 0];
+  long long pos = live ? off[i * R + r] : 0;
+  bool over = false;
+  for (int g = g0; g < g1; ++g) {
+    const uint64_t f = H.gx[g];
+    double re, im;
+    group_h<IMAG>(H, x, H.goff[g], H.goff[g + 1], re, im);
+    const bool ok = H.filter ? sector_ok(x, f) : ((re != 0.0) || (im != 0.0));
+    if (live && ok) {
+      if (pos < cap) {
+        xe[pos] = x ^ f;
+        he[pos * hstride] = re;
+        if (hstride == 2) he[pos * 2 + 1] = im;
+        if (esample) esample[pos] = (int)i;
+      } else {
+        over = true;
+      }
+      ++pos;
+    }
+  }
+  if (over) atomicOr(err, kErrEntryOverflow);
+}
+
+void launch_write(const HamDev& H, const uint64_t* x, long long S, int R, int gper,
+                  const long long* off, long long cap, uint64_t* xe, double* he, int* esample,
+                  int hstride, unsigned* err, hipStream_t s) {
+  if (S <= 0) return;
+  dim3 grid((unsigned)((S + 255) / 256), (unsigned)R);
+  if (H.tim)
+    hipLaunchKernelGGL(write_kernel<true>, grid, dim3(256), 0, s, H, x, S, R, gper, off, cap, xe, he,
+                       esample, hstride, err);
+  else
+    hipLaunchKernelGGL(write_kernel<false>, grid, dim3(256), 0, s, H, x, S, R, gper, off, cap, xe,
+                       he, esample, hstride, err);
+}
+
+__global__ void copy_i64_kernel(const long long* src, long long* dst) { *dst = *src; }
+void launch_copy_i64(const long long* src, long long* dst, hipStream_t s) {
+  hipLaunchKernelGGL(copy_i64_kernel, dim3(1), dim3(1), 0, s, src, dst);
+}
+
+// off[i] = first entry whose sample index is >= i (entries sample-major), i in [0, B].
+__global__ void seg_offsets_kernel(const int* __restrict__ es, long long n, long long B,
+                                   long long* __restrict__ off) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > B) return;
+  long long lo = 0, hi = n;
+  while (lo < hi) {
+    const long long mid = (lo + hi) >> 1;
+    if (es[mid] < i) lo = mid + 1;
+    else hi = mid;
+  }
+  off[i] = lo;
+}
+void launch_seg_offsets(const int* esample, long long n_entries, long long B, long long* off, hipStream_t s) {
+  hipLaunchKernelGGL(seg_offsets_kernel, dim3((unsigned)((B + 1 + 255) / 256)), dim3(256), 0, s, esample,
+                     n_entries, B, off);
+}
+
+// ------------------------------------------------------------------ dedup
+// Two-level open addressing: each workgroup first collapses its tile of
+// entries in an LDS table, then inserts only the tile-unique keys into the
+// global table.  Keys are x' values; the all-ones word marks an empty slot
+// (the plan disables deduplication at n = 64, the only width where it is a
+// valid configuration).
+constexpr unsigned long long kEmpty = ~0ull;
+constexpr int kDedupTile = 2048;
+constexpr int kDedupLds = 4096;
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+  z ^= z >> 30; z *= 0xbf58476d1ce4e5b9ull;
+  z ^= z >> 27; z *= 0x94d049bb133111ebull;
+  z ^= z >> 31;
+  return z;
+}
+
+__global__ __launch_bounds__(512) void dedup_insert_kernel(const uint64_t* __restrict__ xe,
+                                                           const long long* __restrict__ d_count,
+                                                           long long cap,
+                                                           unsigned long long* __restrict__ hkeys,
+                                                           long long HT, int* __restrict__ eu,
+                                                           unsigned* err) {
+  __shared__ unsigned long long lkeys[kDedupLds];
+  __shared__ int lglob[kDedupLds];
+  long long count = *d_count;
+  if (count > cap) count = cap;
+  const long long e0 = (long long)blockIdx.x * kDedupTile;
+  if (e0 >= count) return;
+  for (int s = threadIdx.x; s < kDedupLds; s += blockDim.x) {
+    lkeys[s] = kEmpty;
+    lglob[s] = -1;
+  }
+  __syncthreads();
+  int lslot[kDedupTile / 512];
+#pragma unroll
+  for (int q = 0; q < kDedupTile / 512; ++q) {
+    const long long e = e0 + q * 512 + threadIdx.x;
+    lslot[q] = -1;
+    if (e < count) {
+      const unsigned long long key = xe[e];
+      unsigned s = (unsigned)mix64(key) & (kDedupLds - 1);
+      for (int probe = 0; probe < kDedupLds; ++probe) {
+        unsigned long long prev = atomicCAS(&lkeys[s], kEmpty, key);
+        if (prev == kEmpty || prev == key) { lslot[q] = (int)s; break; }
+        s = (s + 1) & (kDedupLds - 1);
+      }
+    }
+  }
+  __syncthreads();
+  const unsigned long long hmask = (unsigned long long)HT - 1;
+  for (int s = threadIdx.x; s < kDedupLds; s += blockDim.x) {
+    const unsigned long long key = lkeys[s];
+    if (key == kEmpty) continue;
+    unsigned long long gs = mix64(key) & hmask;
+    int found = -1;
+    for (long long probe = 0; probe < HT; ++probe) {
+      unsigned long long prev = atomicCAS(&hkeys[gs], kEmpty, key);
+      if (prev == kEmpty || prev == key) { found = (int)gs; break; }
+      gs = (gs + 1) & hmask;
+    }
+    if (found < 0) atomicOr(err, kErrHashOverflow);
+    lglob[s] = found;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kDedupTile / 512; ++q) {
+    const long long e = e0 + q * 512 + threadIdx.x;
+    if (e < count) eu[e] = lslot[q] >= 0 ? lglob[lslot[q]] : -1;
+  }
+}
+
+// Compact occupied global slots: wave ballot + mbcnt gives the rank inside a
+// wave, LDS prefix over the 8 waves the rank inside the block, one atomic per
+// block the base.
+__global__ __launch_bounds__(512) void dedup_compact_kernel(const unsigned long long* __restrict__ hkeys,
+                                                            long long HT, int* __restrict__ slot_id,
+                                                            uint64_t* __restrict__ xu,
+                                                            long long* __restrict__ d_nu) {
+  __shared__ int wcount[8];
+  __shared__ long long base;
+  const long long s = (long long)blockIdx.x * 512 + threadIdx.x;
+  const bool occ = s < HT && hkeys[s] != kEmpty;
+  const unsigned long long mask = __ballot(occ);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                             __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0));
+  if (lane == 0) wcount[wave] = __popcll(mask);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int w = 0; w < 8; ++w) tot += wcount[w];
+    base = tot ? atomicAdd((unsigned long long*)d_nu, (unsigned long long)tot) : 0;
+  }
+  __syncthreads();
+  if (occ) {
+    int before = 0;
+    for (int w = 0; w < wave; ++w) before += wcount[w];
+    const long long id = base + before + rank;
+    slot_id[s] = (int)id;
+    xu[id] = hkeys[s];
+  }
+}
+
+__global__ void dedup_remap_kernel(const long long* __restrict__ d_count, long long cap,
+                                   const int* __restrict__ slot_id, int* __restrict__ eu) {
+  long long count = *d_count;
+  if (count > cap) count = cap;
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (; e < count; e += stride) {
+    const int s = eu[e];
+    eu[e] = s >= 0 ? slot_id[s] : -1;
+  }
+}
+
+void launch_dedup(const uint64_t* xe, const long long* d_count, long long cap, uint64_t* hkeys,
+                  int* hslot_id, long long HT, int* eu, uint64_t* xu, long long* d_nu,
+                  unsigned* err, hipStream_t s) {
+  launch_fill_u64(hkeys, kEmpty, HT, s);
+  launch_fill_u64(d_nu, 0ull, 1, s);
+  long long tiles = (cap + kDedupTile - 1) / kDedupTile;
+  if (tiles <= 0) return;
+  hipLaunchKernelGGL(dedup_insert_kernel, dim3((unsigned)tiles), dim3(512), 0, s, xe, d_count, cap,
+                     (unsigned long long*)hkeys, HT, eu, err);
+  hipLaunchKernelGGL(dedup_compact_kernel, dim3((unsigned)((HT + 511) / 512)), dim3(512), 0, s,
+                     (const unsigned long long*)hkeys, HT, hslot_id, xu, d_nu);
+  long long blocks = (cap + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(dedup_remap_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d_count, cap,
+                     hslot_id, eu);
+}
+
+// ------------------------------------------------------- ratio-and-reduce
+// Neumaier-compensated accumulation, then a fixed-shape tree: the result
+// does not depend on scheduling.
+struct Comp {
+  double s, c;
+  __device__ void add(double v) {
+    double t = s + v;
+    if (fabs(s) >= fabs(v)) c += (s - t) + v;
+    else c += (v - t) + s;
+    s = t;
+  }
+  __device__ void merge(const Comp& o) {
+    add(o.s);
+    c += o.c;
+  }
+  __device__ double value() const { return s + c; }
+};
+
+// One block per sample: E_loc(x_i) = diag_i + sum_e h_e exp(lp(x'_e) - lp(x_i)).
+__global__ __launch_bounds__(256) void reduce_kernel(long long S, int R, const long long* __restrict__ off,
+                                                     long long cap, const double* __restrict__ diag,
+                                                     const double* __restrict__ he, int hstride,
+                                                     const int* __restrict__ eu,
+                                                     const double2* __restrict__ lpe,
+                                                     const double2* __restrict__ lps,
+                                                     double* __restrict__ eloc, unsigned* err) {
+  __shared__ double red[4][256];
+  const long long i = blockIdx.x;
+  if (i >= S) return;
+  long long a = off[i * R];
+  long long b = off[(i + 1) * R];
+  if (a > cap) a = cap;
+  if (b > cap) b = cap;
+  const double2 ls = lps[i];
+  Comp cr{0.0, 0.0}, ci{0.0, 0.0};
+  for (long long e = a + threadIdx.x; e < b; e += 256) {
+    const int u = eu ? eu[e] : (int)0;
+    const double2 lp = eu ? (u >= 0 ? lpe[u] : make_double2(-INFINITY, 0.0)) : lpe[e];
+    if (lp.x == -INFINITY) continue;
+    const double hr = he[e * hstride];
+    const double hi = hstride == 2 ? he[e * 2 + 1] : 0.0;
+    const double mag = exp(lp.x - ls.x);
+    double sn, cs;
+    sincos(lp.y - ls.y, &sn, &cs);
+    cr.add(mag * (hr * cs - hi * sn));
+    ci.add(mag * (hr * sn + hi * cs));
+  }
+  red[0][threadIdx.x] = cr.s;
+  red[1][threadIdx.x] = cr.c;
+  red[2][threadIdx.x] = ci.s;
+  red[3][threadIdx.x] = ci.c;
+  __syncthreads();
+  for (int d = 128; d >= 1; d >>= 1) {
+    if (threadIdx.x < d) {
+      Comp x{red[0][threadIdx.x], red[1][threadIdx.x]}, y{red[0][threadIdx.x + d], red[1][threadIdx.x + d]};
+      x.merge(y);
+      red[0][threadIdx.x] = x.s;
+      red[1][threadIdx.x] = x.c;
+      Comp p{red[2][threadIdx.x], red[3][threadIdx.x]}, q{red[2][threadIdx.x + d], red[3][threadIdx.x + d]};
+      p.merge(q);
+      red[2][threadIdx.x] = p.s;
+      red[3][threadIdx.x] = p.c;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    Comp tr{diag[2 * i], 0.0}, ti{diag[2 * i + 1], 0.0};
+    tr.merge(Comp{red[0][0], red[1][0]});
+    ti.merge(Comp{red[2][0], red[3][0]});
+    if (ls.x == -INFINITY) {
+      atomicOr(err, kErrZeroAmp);
+      eloc[2 * i] = NAN;
+      eloc[2 * i + 1] = NAN;
+    } else {
+      eloc[2 * i] = tr.value();
+      eloc[2 * i + 1] = ti.value();
+    }
+  }
+}
+
+void launch_reduce(long long S, int R, const long long* off, long long cap, const double* diag,
+                     const double* he, int hstride, const int* eu, const double* lpe,
+                     const double* lps, double* eloc, unsigned* err, hipStream_t s) {
+  if (S <= 0) return;
+  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)S), dim3(256), 0, s, S, R, off, cap, diag, he,
+                     hstride, eu, (const double2*)lpe, (const double2*)lps, eloc, err);
+}
+
+// Weighted energy: W = sum w, E = sum w Re(l) / W, I = sum w Im(l) / W.
+__global__ __launch_bounds__(1024) void energy_kernel(const double* __restrict__ eloc,
+                                                      const double* __restrict__ w, long long B,
+                                                      double* __restrict__ energy, unsigned* err) {
+  __shared__ double red[6][1024];
+  const int t = threadIdx.x;
+  Comp sw{0, 0}, sr{0, 0}, si{0, 0};
+  for (long long i = t; i < B; i += 1024) {
+    const double wi = w ? w[i] : 1.0;
+    sw.add(wi);
+    sr.add(wi * eloc[2 * i]);
+    si.add(wi * eloc[2 * i + 1]);
+  }
+  red[0][t] = sw.s; red[1][t] = sw.c; red[2][t] = sr.s; red[3][t] = sr.c; red[4][t] = si.s; red[5][t] = si.c;
+  __syncthreads();
+  for (int d = 512; d >= 1; d >>= 1) {
+    if (t < d) {
+      for (int k = 0; k < 3; ++k) {
+        Comp a{red[2 * k][t], red[2 * k + 1][t]}, b{red[2 * k][t + d], red[2 * k + 1][t + d]};
+        a.merge(b);
+        red[2 * k][t] = a.s;
+        red[2 * k + 1][t] = a.c;
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double W = red[0][0] + red[1][0];
+    energy[0] = (red[2][0] + red[3][0]) / W;
+    energy[1] = (red[4][0] + red[5][0]) / W;
+    energy[2] = W;
+    if (!(W > 0.0)) atomicOr(err, kErrZeroAmp);
+  }
+}
+
+void launch_energy(const double* eloc, const double* w, long long B, double* energy, unsigned* err,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(energy_kernel, dim3(1), dim3(1024), 0, s, eloc, w, B, energy, err);
+}
+
+}  // namespace nqs

@@ -1,0 +1,709 @@
+// Host side of the C ABI declared in include/nqs.h: argument checking,
+// Hamiltonian canonicalisation, plans (network geometry, chunking,
+// workspace layout) and the stream-ordered launch sequences of the hot path.
+#include "../../include/nqs.h"
+#include "nqs_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+using namespace nqs;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+nqs_status fail(nqs_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(NQS_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+  } while (0)
+
+nqs_status launch_check(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(NQS_ERR_HIP, "%s: kernel launch failed: %s", what, hipGetErrorString(e));
+  return NQS_OK;
+}
+
+constexpr uint64_t kUpMask = 0x5555555555555555ull;
+constexpr uint64_t kDnMask = 0xAAAAAAAAAAAAAAAAull;
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+double binom(int a, int b) {
+  if (b < 0 || a < 0 || b > a) return 0.0;
+  double r = 1.0;
+  for (int i = 1; i <= b; ++i) r = r * (a - b + i) / i;
+  return r;
+}
+
+}  // namespace
+
+struct nqs_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int cu_count = 0;
+};
+
+struct nqs_ham {
+  int n = 0;
+  bool has_imag = false;
+  uint32_t flags = 0;
+  std::vector<uint64_t> gx;
+  std::vector<long long> goff;
+  std::vector<uint64_t> tz;
+  std::vector<double> tre, tim;
+  // census of non-empty flips by (up bits, down bits) for the entry bound
+  std::map<std::pair<int, int>, long long> census;
+  // device copy
+  char* d_base = nullptr;
+  size_t bytes = 0;
+  size_t o_gx = 0, o_goff = 0, o_tz = 0, o_tre = 0, o_tim = 0;
+};
+
+struct nqs_plan {
+  nqs_ctx* ctx = nullptr;
+  const nqs_ham* ham = nullptr;
+  Geom g{};
+  int64_t max_batch = 0;
+  int64_t S = 0;           // samples per chunk
+  int64_t Emax = 0;        // entries per sample bound
+  int64_t EC = 0;          // entries per chunk capacity
+  int R = 1, gper = 0;     // group ranges of the enumeration grid
+  bool dedup = false;
+  int64_t HT = 0;          // dedup hash slots
+  int64_t Sb = 0;          // backward chunk
+  int bw = 4;              // bytes per element of the backward path
+  size_t packed_bytes = 0;
+};
+
+struct WsLayout {
+  size_t err, packed, wm, lps, eloc, energy, cnt, off, diag, xe, he, lpe, hkeys, hslot, eu, xu, nu,
+      bscratch, total;
+};
+
+static WsLayout layout(const nqs_plan* p, int64_t B) {
+  WsLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+  const int hs = p->ham->has_imag ? 2 : 1;
+  L.err = take(256);
+  L.packed = take(p->packed_bytes);
+  L.wm = take((size_t)p->g.n_params * p->bw);
+  L.lps = take((size_t)std::max<int64_t>(B, 1) * 16);
+  L.eloc = take((size_t)std::max<int64_t>(B, 1) * 16);
+  L.energy = take(3 * 8);
+  L.cnt = take((size_t)p->S * p->R * 4);
+  L.off = take(((size_t)p->S * p->R + 1) * 8);
+  L.diag = take((size_t)p->S * 16);
+  L.xe = take((size_t)p->EC * 8);
+  L.he = take((size_t)p->EC * 8 * hs);
+  L.lpe = take((size_t)p->EC * 16);
+  if (p->dedup) {
+    L.hkeys = take((size_t)p->HT * 8);
+    L.hslot = take((size_t)p->HT * 4);
+    L.eu = take((size_t)p->EC * 4);
+    L.xu = take((size_t)p->EC * 8);
+    L.nu = take(8);
+  }
+  L.bscratch = take((size_t)backward_scratch_elems(p->g, p->Sb) * p->bw);
+  L.total = o;
+  return L;
+}
+
+static HamDev ham_dev(const nqs_plan* p) {
+  const nqs_ham* h = p->ham;
+  HamDev H{};
+  H.gx = (const uint64_t*)(h->d_base + h->o_gx);
+  H.goff = (const long long*)(h->d_base + h->o_goff);
+  H.tz = (const uint64_t*)(h->d_base + h->o_tz);
+  H.tre = (const double*)(h->d_base + h->o_tre);
+  H.tim = h->has_imag ? (const double*)(h->d_base + h->o_tim) : nullptr;
+  H.G = (int)h->gx.size();
+  H.gfirst = (!h->gx.empty() && h->gx[0] == 0) ? 1 : 0;
+  H.filter = (h->flags & NQS_H_CONSERVES_SPIN_SECTORS) ? 1 : 0;
+  return H;
+}
+
+extern "C" {
+
+const char* nqs_status_str(int s) {
+  switch (s) {
+    case NQS_OK: return "ok";
+    case NQS_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case NQS_ERR_UNSUPPORTED: return "unsupported";
+    case NQS_ERR_NOT_HERMITIAN: return "non-real Pauli coefficient";
+    case NQS_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case NQS_ERR_HIP: return "HIP runtime error";
+    case NQS_ERR_DEVICE: return "device error flag set";
+  }
+  return "unknown status";
+}
+
+size_t nqs_last_error(char* buf, size_t len) {
+  if (buf && len) {
+    size_t n = std::min(len - 1, g_last_error.size());
+    memcpy(buf, g_last_error.data(), n);
+    buf[n] = 0;
+  }
+  return g_last_error.size();
+}
+
+int nqs_version(void) { return 100; }
+
+nqs_status nqs_ctx_create(int device, void* stream, nqs_ctx** out) {
+  if (!out) return fail(NQS_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  HIP_TRY(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(NQS_ERR_INVALID_ARGUMENT, "device %d of %d", device, count);
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(NQS_ERR_UNSUPPORTED, "device arch %s is not gfx950", prop.gcnArchName);
+  HIP_TRY(hipSetDevice(device));
+  nqs_ctx* c = new nqs_ctx;
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  c->cu_count = prop.multiProcessorCount;
+  *out = c;
+  return NQS_OK;
+}
+
+nqs_status nqs_ctx_set_stream(nqs_ctx* ctx, void* stream) {
+  if (!ctx) return fail(NQS_ERR_INVALID_ARGUMENT, "ctx is NULL");
+  ctx->stream = (hipStream_t)stream;
+  return NQS_OK;
+}
+
+void nqs_ctx_destroy(nqs_ctx* ctx) { delete ctx; }
+
+// ------------------------------------------------------------ Hamiltonian
+nqs_status nqs_ham_create(const nqs_pauli_terms* t, nqs_ham** out) {
+  if (!t || !out) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
+  *out = nullptr;
+  if (t->n_qubits < 1 || t->n_qubits > 64)
+    return fail(NQS_ERR_UNSUPPORTED, "n_qubits = %d outside 1..64", t->n_qubits);
+  if (t->n_terms < 0) return fail(NQS_ERR_INVALID_ARGUMENT, "n_terms < 0");
+  if (t->n_terms > 0 && (!t->x_mask || !t->z_mask || !t->coeff))
+    return fail(NQS_ERR_INVALID_ARGUMENT, "NULL term arrays");
+  if (!(t->drop_tol >= 0.0)) return fail(NQS_ERR_INVALID_ARGUMENT, "drop_tol must be >= 0");
+  const uint64_t valid = t->n_qubits == 64 ? ~0ull : ((1ull << t->n_qubits) - 1);
+  for (int64_t k = 0; k < t->n_terms; ++k) {
+    if ((t->x_mask[k] | t->z_mask[k]) & ~valid)
+      return fail(NQS_ERR_INVALID_ARGUMENT, "term %lld acts on a qubit >= n_qubits", (long long)k);
+    if (!std::isfinite(t->coeff[k])) return fail(NQS_ERR_INVALID_ARGUMENT, "term %lld: non-finite coefficient", (long long)k);
+    if (t->coeff_imag && t->coeff_imag[k] != 0.0)
+      return fail(NQS_ERR_NOT_HERMITIAN, "term %lld has imaginary coefficient %g", (long long)k, t->coeff_imag[k]);
+  }
+  // 1. merge identical strings, sequential FP64 sums in input order
+  struct KeyHash {
+    size_t operator()(const std::pair<uint64_t, uint64_t>& k) const {
+      return std::hash<uint64_t>()(k.first * 0x9E3779B97F4A7C15ull ^ k.second);
+    }
+  };
+  std::unordered_map<std::pair<uint64_t, uint64_t>, size_t, KeyHash> idx;
+  idx.reserve((size_t)t->n_terms * 2 + 1);
+  std::vector<std::pair<uint64_t, uint64_t>> keys;
+  std::vector<double> vals;
+  for (int64_t k = 0; k < t->n_terms; ++k) {
+    auto key = std::make_pair(t->x_mask[k], t->z_mask[k]);
+    auto it = idx.find(key);
+    if (it == idx.end()) {
+      idx.emplace(key, keys.size());
+      keys.push_back(key);
+      vals.push_back(t->coeff[k]);
+    } else {
+      vals[it->second] = vals[it->second] + t->coeff[k];
+    }
+  }
+  // 2. drop, 5. sort
+  std::vector<size_t> ord;
+  for (size_t i = 0; i < keys.size(); ++i)
+    if (std::fabs(vals[i]) >= t->drop_tol) ord.push_back(i);
+  std::sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return keys[a] < keys[b]; });
+  nqs_ham* h = new nqs_ham;
+  h->n = t->n_qubits;
+  h->flags = t->flags;
+  const size_t K = ord.size();
+  h->tz.resize(K);
+  h->tre.resize(K);
+  h->tim.resize(K);
+  for (size_t j = 0; j < K; ++j) {
+    const auto& key = keys[ord[j]];
+    const double c = vals[ord[j]];
+    h->tz[j] = key.second;
+    // 4. fold (-i)^r, r = number of Y factors
+    switch (__builtin_popcountll(key.first & key.second) & 3) {
+      case 0: h->tre[j] = c; h->tim[j] = 0.0; break;
+      case 1: h->tre[j] = 0.0; h->tim[j] = -c; h->has_imag = true; break;
+      case 2: h->tre[j] = -c; h->tim[j] = 0.0; break;
+      default: h->tre[j] = 0.0; h->tim[j] = c; h->has_imag = true; break;
+    }
+    if (j == 0 || key.first != keys[ord[j - 1]].first) {
+      h->gx.push_back(key.first);
+      h->goff.push_back((long long)j);
+    }
+  }
+  h->goff.push_back((long long)K);
+  for (size_t gi = 0; gi < h->gx.size(); ++gi) {
+    const uint64_t f = h->gx[gi];
+    if (f == 0) continue;
+    h->census[{__builtin_popcountll(f & kUpMask), __builtin_popcountll(f & kDnMask)}] += 1;
+  }
+  // device layout
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+  h->o_gx = take(h->gx.size() * 8);
+  h->o_goff = take(h->goff.size() * 8);
+  h->o_tz = take(K * 8);
+  h->o_tre = take(K * 8);
+  h->o_tim = h->has_imag ? take(K * 8) : 0;
+  h->bytes = std::max<size_t>(o, 256);
+  *out = h;
+  return NQS_OK;
+}
+
+nqs_status nqs_ham_info(const nqs_ham* h, int64_t* K, int64_t* G, size_t* bytes, int* has_imag, int* n) {
+  if (!h) return fail(NQS_ERR_INVALID_ARGUMENT, "ham is NULL");
+  if (K) *K = (int64_t)h->tz.size();
+  if (G) *G = (int64_t)h->gx.size();
+  if (bytes) *bytes = h->bytes;
+  if (has_imag) *has_imag = h->has_imag ? 1 : 0;
+  if (n) *n = h->n;
+  return NQS_OK;
+}
+
+nqs_status nqs_ham_upload(nqs_ham* h, nqs_ctx* ctx, void* d_storage, size_t bytes) {
+  if (!h || !ctx || !d_storage) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (bytes < h->bytes) return fail(NQS_ERR_WORKSPACE_TOO_SMALL, "storage %zu < %zu bytes", bytes, h->bytes);
+  if (((uintptr_t)d_storage) & 255) return fail(NQS_ERR_INVALID_ARGUMENT, "storage not 256-byte aligned");
+  char* d = (char*)d_storage;
+  hipStream_t s = ctx->stream;
+  if (!h->gx.empty()) HIP_TRY(hipMemcpyAsync(d + h->o_gx, h->gx.data(), h->gx.size() * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d + h->o_goff, h->goff.data(), h->goff.size() * 8, hipMemcpyHostToDevice, s));
+  if (!h->tz.empty()) {
+    HIP_TRY(hipMemcpyAsync(d + h->o_tz, h->tz.data(), h->tz.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d + h->o_tre, h->tre.data(), h->tre.size() * 8, hipMemcpyHostToDevice, s));
+    if (h->has_imag)
+      HIP_TRY(hipMemcpyAsync(d + h->o_tim, h->tim.data(), h->tim.size() * 8, hipMemcpyHostToDevice, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  h->d_base = d;
+  return NQS_OK;
+}
+
+nqs_status nqs_ham_export(const nqs_ham* h, uint64_t* gx, int64_t* goff, uint64_t* tz, double* tre, double* tim) {
+  if (!h) return fail(NQS_ERR_INVALID_ARGUMENT, "ham is NULL");
+  if (gx) std::copy(h->gx.begin(), h->gx.end(), gx);
+  if (goff) for (size_t i = 0; i < h->goff.size(); ++i) goff[i] = (int64_t)h->goff[i];
+  if (tz) std::copy(h->tz.begin(), h->tz.end(), tz);
+  if (tre) std::copy(h->tre.begin(), h->tre.end(), tre);
+  if (tim) std::copy(h->tim.begin(), h->tim.end(), tim);
+  return NQS_OK;
+}
+
+void nqs_ham_destroy(nqs_ham* h) { delete h; }
+
+// ---------------------------------------------------------------- network
+static nqs_status build_geom(const nqs_net_desc* nd, Geom& g) {
+  if (!nd) return fail(NQS_ERR_INVALID_ARGUMENT, "net is NULL");
+  const int n = nd->n_qubits, L = nd->n_layers, h = nd->width;
+  if (n < 2 || n > 64) return fail(NQS_ERR_UNSUPPORTED, "n_qubits = %d outside 2..64", n);
+  if (L < 1 || L > kMaxLayers) return fail(NQS_ERR_UNSUPPORTED, "n_layers = %d outside 1..%d", L, kMaxLayers);
+  if (nd->precision < NQS_FP64 || nd->precision > NQS_BF16X3)
+    return fail(NQS_ERR_INVALID_ARGUMENT, "unknown precision %d", nd->precision);
+  if (!forward_supported(nd->precision, h))
+    return fail(NQS_ERR_UNSUPPORTED, "width %d not supported for precision %d", h, nd->precision);
+  const bool cons = nd->n_up >= 0 || nd->n_dn >= 0;
+  if (cons && (nd->n_up < 0 || nd->n_dn < 0 || nd->n_up > (n + 1) / 2 || nd->n_dn > n / 2))
+    return fail(NQS_ERR_INVALID_ARGUMENT, "invalid sector (%d, %d)", nd->n_up, nd->n_dn);
+  memset(&g, 0, sizeof(g));
+  g.n = n; g.L = L; g.h = h; g.prec = nd->precision;
+  g.n_up = cons ? nd->n_up : -1;
+  g.n_dn = cons ? nd->n_dn : -1;
+  std::vector<int> order(n), seen(n, 0);
+  for (int t = 0; t < n; ++t) {
+    order[t] = nd->order ? nd->order[t] : n - 1 - t;
+    if (order[t] < 0 || order[t] >= n || seen[order[t]]++)
+      return fail(NQS_ERR_INVALID_ARGUMENT, "order is not a permutation of the qubits");
+  }
+  for (int t = 0; t < n; ++t) {
+    g.order[t] = (int8_t)order[t];
+    g.pos[order[t]] = (int8_t)t;
+    g.spin_pos[order[t] & 1] |= 1ull << t;
+  }
+  g.TB = g.prec == P_F64 ? 16 : 32;
+  g.KSTEP = (g.prec == P_BF16 || g.prec == P_BF16X3) ? 16 : 8;
+  g.NB = h / g.TB;
+  g.nhead = n + 4;
+  g.NHB = (g.nhead + g.TB - 1) / g.TB;
+  if (g.NB > kMaxNB || g.NHB > kMaxNHB) return fail(NQS_ERR_UNSUPPORTED, "network too wide");
+  if (h >= n - 1) { g.q = h / (n - 1); g.r = h % (n - 1); }
+  else { g.q = 0; g.r = h; }
+  g.planes = g.prec == P_BF16X3 ? 2 : 1;
+  g.acc_bytes = g.prec == P_F64 ? 8 : 4;
+  auto ceil_div = [](int a, int b) { return (a + b - 1) / b; };
+  g.off1[0] = g.offh[0] = g.offo[0] = 0;
+  for (int nb = 0; nb < g.NB; ++nb) {
+    const int ulast = std::min(h, g.TB * (nb + 1)) - 1;
+    const int c = class_of_sorted(g, ulast);
+    const int kend1 = std::min(c + 1, n);
+    const int kendh = prefix_of_class(g, c + 1);
+    g.ks1[nb] = ceil_div(kend1, g.KSTEP);
+    g.ksh[nb] = ceil_div(kendh, g.KSTEP);
+    g.off1[nb + 1] = g.off1[nb] + g.ks1[nb];
+    g.offh[nb + 1] = g.offh[nb] + g.ksh[nb];
+  }
+  for (int nb = 0; nb < g.NHB; ++nb) {
+    int kend = 0;
+    for (int t = g.TB * nb; t < std::min(g.TB * (nb + 1), g.nhead); ++t)
+      kend = std::max(kend, t < n ? prefix_of_class(g, t) : prefix_of_class(g, n - 2));
+    g.kso[nb] = ceil_div(kend, g.KSTEP);
+    g.offo[nb + 1] = g.offo[nb] + g.kso[nb];
+  }
+  g.frag_h = g.off1[g.NB];
+  g.frag_head = g.frag_h + (long long)(L - 1) * g.offh[g.NB];
+  g.nfrag = g.frag_head + g.offo[g.NHB];
+  g.bias_byte = (long long)align256((size_t)g.nfrag * 1024 * g.planes);
+  g.head_bias_off = (long long)L * h;
+  long long o = 0;
+  for (int l = 0; l < L; ++l) {
+    const int in = l == 0 ? n : h;
+    g.poff[2 * l] = o; o += (long long)h * in;
+    g.poff[2 * l + 1] = o; o += h;
+  }
+  g.poff[2 * L] = o; o += (long long)n * h;
+  g.poff[2 * L + 1] = o; o += n;
+  g.poff[2 * L + 2] = o; o += 4LL * h;
+  g.poff[2 * L + 3] = o; o += 4;
+  g.n_params = o;
+  return NQS_OK;
+}
+
+nqs_status nqs_net_param_count(const nqs_net_desc* nd, int64_t* n_params) {
+  Geom g;
+  nqs_status s = build_geom(nd, g);
+  if (s != NQS_OK) return s;
+  if (n_params) *n_params = g.n_params;
+  return NQS_OK;
+}
+
+// -------------------------------------------------------------------- plan
+nqs_status nqs_plan_create(nqs_ctx* ctx, const nqs_ham* ham, const nqs_net_desc* nd, int64_t max_batch,
+                           uint32_t flags, int64_t chunk_samples, nqs_plan** out) {
+  if (!ctx || !ham || !out) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
+  *out = nullptr;
+  if (max_batch < 1) return fail(NQS_ERR_INVALID_ARGUMENT, "max_batch must be >= 1");
+  if ((flags & NQS_PLAN_DEDUP_ON) && (flags & NQS_PLAN_DEDUP_OFF))
+    return fail(NQS_ERR_INVALID_ARGUMENT, "DEDUP_ON and DEDUP_OFF together");
+  Geom g;
+  nqs_status st = build_geom(nd, g);
+  if (st != NQS_OK) return st;
+  if (g.n != ham->n) return fail(NQS_ERR_INVALID_ARGUMENT, "network has %d qubits, Hamiltonian %d", g.n, ham->n);
+  if (!ham->d_base) return fail(NQS_ERR_INVALID_ARGUMENT, "Hamiltonian not uploaded");
+  nqs_plan* p = new nqs_plan;
+  p->ctx = ctx;
+  p->ham = ham;
+  p->g = g;
+  p->max_batch = max_batch;
+  // per-sample entry bound
+  const int G = (int)ham->gx.size();
+  const int gfirst = (G > 0 && ham->gx[0] == 0) ? 1 : 0;
+  if (ham->flags & NQS_H_CONSERVES_SPIN_SECTORS) {
+    const int Nu = (g.n + 1) / 2, Nd = g.n / 2;
+    double bound = 0.0;
+    for (const auto& kv : ham->census) {
+      const int u = kv.first.first, d = kv.first.second;
+      if ((u & 1) || (d & 1)) continue;
+      double best = 0.0;
+      for (int a = 0; a <= Nu; ++a) {
+        if (g.n_up >= 0 && a != g.n_up) continue;
+        for (int b = 0; b <= Nd; ++b) {
+          if (g.n_dn >= 0 && b != g.n_dn) continue;
+          best = std::max(best, binom(a, u / 2) * binom(Nu - a, u / 2) * binom(b, d / 2) * binom(Nd - b, d / 2));
+        }
+      }
+      bound += std::min(best, (double)kv.second);
+    }
+    p->Emax = (int64_t)bound;
+  } else {
+    p->Emax = G - gfirst;
+  }
+  const int64_t target = 16 * 1024 * 1024;
+  if (chunk_samples > 0) p->S = std::min<int64_t>(chunk_samples, max_batch);
+  else p->S = std::max<int64_t>(1, std::min<int64_t>(max_batch, target / std::max<int64_t>(p->Emax, 1)));
+  p->EC = std::max<int64_t>(p->S * p->Emax, 1);
+  if (p->EC >= (1LL << 31)) {
+    delete p;
+    return fail(NQS_ERR_UNSUPPORTED, "chunk of %lld entries exceeds 2^31", (long long)p->S * p->Emax);
+  }
+  const int ngroups = G - gfirst;
+  const int bx = (int)((p->S + 255) / 256);
+  if (ngroups <= 0) { p->R = 1; p->gper = 0; }
+  else {
+    int R = std::max(1, std::min(ngroups, 2048 / bx));
+    p->gper = (ngroups + R - 1) / R;
+    p->R = (ngroups + p->gper - 1) / p->gper;
+  }
+  p->dedup = (flags & NQS_PLAN_DEDUP_ON) != 0;
+  if (p->dedup && g.n == 64) p->dedup = false;   // all-ones word is the empty-slot marker
+  if (p->dedup) {
+    int64_t ht = 4096;
+    while (ht < 2 * p->EC) ht <<= 1;
+    p->HT = ht;
+  }
+  p->Sb = std::min<int64_t>(max_batch, 4096);
+  p->bw = g.prec == P_F64 ? 8 : 4;
+  p->packed_bytes = (size_t)g.bias_byte + ((size_t)g.L * g.h + (size_t)g.NHB * g.TB) * g.acc_bytes;
+  *out = p;
+  return NQS_OK;
+}
+
+nqs_status nqs_plan_workspace_size(const nqs_plan* p, int64_t B, size_t* bytes) {
+  if (!p || !bytes) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (B < 0 || B > p->max_batch) return fail(NQS_ERR_INVALID_ARGUMENT, "batch %lld outside 0..%lld", (long long)B, (long long)p->max_batch);
+  *bytes = layout(p, B).total;
+  return NQS_OK;
+}
+
+nqs_status nqs_plan_info(const nqs_plan* p, int64_t* eps, int64_t* chunk, int* dedup, int64_t* n_params) {
+  if (!p) return fail(NQS_ERR_INVALID_ARGUMENT, "plan is NULL");
+  if (eps) *eps = p->Emax;
+  if (chunk) *chunk = p->S;
+  if (dedup) *dedup = p->dedup ? 1 : 0;
+  if (n_params) *n_params = p->g.n_params;
+  return NQS_OK;
+}
+
+void nqs_plan_destroy(nqs_plan* p) { delete p; }
+
+}  // extern "C"
+
+// ------------------------------------------------------------ hot path
+static nqs_status check_ws(const nqs_plan* p, int64_t B, void* ws, size_t ws_bytes, WsLayout& L) {
+  if (!ws) return fail(NQS_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (((uintptr_t)ws) & 255) return fail(NQS_ERR_INVALID_ARGUMENT, "workspace not 256-byte aligned");
+  if (B < 0 || B > p->max_batch) return fail(NQS_ERR_INVALID_ARGUMENT, "batch %lld outside 0..%lld", (long long)B, (long long)p->max_batch);
+  L = layout(p, B);
+  if (ws_bytes < L.total) return fail(NQS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, L.total);
+  return NQS_OK;
+}
+
+template <typename T>
+static T* at(void* ws, size_t off) { return (T*)((char*)ws + off); }
+
+// local energies of B samples into eloc; lps (sample log psi) computed first.
+static nqs_status run_local_energy(nqs_plan* p, const float* params, const uint64_t* x, int64_t B,
+                                   double* eloc, void* ws, const WsLayout& L) {
+  hipStream_t s = p->ctx->stream;
+  const HamDev H = ham_dev(p);
+  unsigned* err = at<unsigned>(ws, L.err);
+  void* packed = at<void>(ws, L.packed);
+  double* lps = at<double>(ws, L.lps);
+  launch_pack_fused(p->g, params, packed, s);
+  launch_forward(p->g, packed, x, B, nullptr, lps, s);
+  const int hs = p->ham->has_imag ? 2 : 1;
+  for (int64_t c0 = 0; c0 < B; c0 += p->S) {
+    const int64_t Sc = std::min<int64_t>(p->S, B - c0);
+    const uint64_t* xc = x + c0;
+    int* cnt = at<int>(ws, L.cnt);
+    long long* off = at<long long>(ws, L.off);
+    double* diag = at<double>(ws, L.diag);
+    uint64_t* xe = at<uint64_t>(ws, L.xe);
+    double* he = at<double>(ws, L.he);
+    double* lpe = at<double>(ws, L.lpe);
+    launch_diag(H, xc, Sc, diag, s);
+    launch_count(H, xc, Sc, p->R, p->gper, cnt, s);
+    launch_scan(cnt, Sc * p->R, off, s);
+    launch_write(H, xc, Sc, p->R, p->gper, off, p->EC, xe, he, nullptr, hs, err, s);
+    const long long* d_total = off + Sc * p->R;
+    const int64_t bound = std::min<int64_t>(Sc * p->Emax, p->EC);
+    int* eu = nullptr;
+    if (p->dedup) {
+      eu = at<int>(ws, L.eu);
+      uint64_t* xu = at<uint64_t>(ws, L.xu);
+      long long* nu = at<long long>(ws, L.nu);
+      launch_dedup(xe, d_total, p->EC, at<uint64_t>(ws, L.hkeys), at<int>(ws, L.hslot), p->HT, eu, xu, nu, err, s);
+      launch_forward(p->g, packed, xu, bound, nu, lpe, s);
+    } else {
+      launch_forward(p->g, packed, xe, bound, d_total, lpe, s);
+    }
+    launch_reduce(Sc, p->R, off, p->EC, diag, he, hs, eu, lpe, lps + 2 * c0, eloc + 2 * c0, err, s);
+  }
+  return launch_check("local energy");
+}
+
+extern "C" {
+
+nqs_status nqs_log_psi(nqs_plan* p, const float* params, const uint64_t* x, int64_t n, double* out,
+                       void* ws, size_t ws_bytes) {
+  if (!p || !params || (n > 0 && (!x || !out))) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (n < 0) return fail(NQS_ERR_INVALID_ARGUMENT, "n < 0");
+  WsLayout L;
+  nqs_status st = check_ws(p, 0, ws, ws_bytes, L);
+  if (st != NQS_OK) return st;
+  if (n == 0) return NQS_OK;
+  hipStream_t s = p->ctx->stream;
+  void* packed = at<void>(ws, L.packed);
+  launch_pack_fused(p->g, params, packed, s);
+  launch_forward(p->g, packed, x, n, nullptr, out, s);
+  return launch_check("log psi");
+}
+
+nqs_status nqs_local_energy(nqs_plan* p, const float* params, const uint64_t* x, int64_t B, double* eloc,
+                            void* ws, size_t ws_bytes) {
+  if (!p || !params || (B > 0 && (!x || !eloc))) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
+  WsLayout L;
+  nqs_status st = check_ws(p, B, ws, ws_bytes, L);
+  if (st != NQS_OK) return st;
+  launch_fill_u32(at<void>(ws, L.err), 0u, 1, p->ctx->stream);
+  if (B == 0) return launch_check("local energy");
+  return run_local_energy(p, params, x, B, eloc, ws, L);
+}
+
+nqs_status nqs_energy_grad(nqs_plan* p, const float* params, const uint64_t* x, const double* w, int64_t B,
+                           double* eloc, double* energy, double* grad, void* ws, size_t ws_bytes) {
+  if (!p || !params || !energy || !grad || (B > 0 && !x)) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (B < 1) return fail(NQS_ERR_INVALID_ARGUMENT, "energy needs at least one sample");
+  WsLayout L;
+  nqs_status st = check_ws(p, B, ws, ws_bytes, L);
+  if (st != NQS_OK) return st;
+  hipStream_t s = p->ctx->stream;
+  unsigned* err = at<unsigned>(ws, L.err);
+  launch_fill_u32(err, 0u, 1, s);
+  double* el = eloc ? eloc : at<double>(ws, L.eloc);
+  st = run_local_energy(p, params, x, B, el, ws, L);
+  if (st != NQS_OK) return st;
+  launch_energy(el, w, B, energy, err, s);
+  launch_fill_u64(grad, 0ull, p->g.n_params, s);
+  void* wm = at<void>(ws, L.wm);
+  launch_pack_masked(p->g, params, wm, s);
+  void* scratch = at<void>(ws, L.bscratch);
+  for (int64_t c0 = 0; c0 < B; c0 += p->Sb) {
+    const int64_t Sc = std::min<int64_t>(p->Sb, B - c0);
+    launch_backward(p->g, wm, x + c0, Sc, el + 2 * c0, w ? w + c0 : nullptr, energy, scratch, grad, s);
+  }
+  return launch_check("energy gradient");
+}
+
+nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* ws, size_t ws_bytes) {
+  if (n_inst < 0 || (n_inst > 0 && !inst)) return fail(NQS_ERR_INVALID_ARGUMENT, "bad instance list");
+  std::vector<int> ord(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    ord[i] = i;
+    if (!inst[i].plan) return fail(NQS_ERR_INVALID_ARGUMENT, "instance %d has no plan", i);
+    if (inst[i].plan->ctx != inst[0].plan->ctx)
+      return fail(NQS_ERR_INVALID_ARGUMENT, "instances on different contexts");
+    WsLayout L;
+    nqs_status st = check_ws(inst[i].plan, inst[i].B, ws, ws_bytes, L);
+    if (st != NQS_OK) return st;
+  }
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+    return inst[a].B * inst[a].plan->Emax * inst[a].plan->g.n_params >
+           inst[b].B * inst[b].plan->Emax * inst[b].plan->g.n_params;
+  });
+  for (int k : ord) {
+    const nqs_instance& I = inst[k];
+    nqs_status st = nqs_energy_grad(I.plan, I.d_params, I.d_samples, I.d_weights, I.B, I.d_eloc, I.d_energy,
+                                    I.d_grad, ws, ws_bytes);
+    if (st != NQS_OK) return st;
+  }
+  return NQS_OK;
+}
+
+}  // extern "C"
+
+namespace nqs {
+void launch_copy_i64(const long long* src, long long* dst, hipStream_t s);
+void launch_seg_offsets(const int* esample, long long n_entries, long long B, long long* off, hipStream_t s);
+}
+
+extern "C" {
+
+nqs_status nqs_connected(nqs_plan* p, const uint64_t* x, int64_t B, int64_t capacity, double* d_diag,
+                         int32_t* d_esample, uint64_t* d_ex, double* d_eh, int64_t* d_n_entries,
+                         uint64_t* d_unique, int32_t* d_eunique, int64_t* d_n_unique, void* ws, size_t ws_bytes) {
+  if (!p || (B > 0 && (!x || !d_diag || !d_ex || !d_eh || !d_n_entries)))
+    return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (B > p->S) return fail(NQS_ERR_INVALID_ARGUMENT, "batch %lld exceeds the plan's chunk %lld", (long long)B, (long long)p->S);
+  if (capacity < 0 || capacity >= (1LL << 31)) return fail(NQS_ERR_INVALID_ARGUMENT, "capacity out of range");
+  if (p->dedup && (!d_unique || !d_eunique || !d_n_unique))
+    return fail(NQS_ERR_INVALID_ARGUMENT, "dedup plan needs the unique outputs");
+  WsLayout L;
+  nqs_status st = check_ws(p, B, ws, ws_bytes, L);
+  if (st != NQS_OK) return st;
+  hipStream_t s = p->ctx->stream;
+  const HamDev H = ham_dev(p);
+  unsigned* err = at<unsigned>(ws, L.err);
+  launch_fill_u32(err, 0u, 1, s);
+  if (B == 0) {
+    launch_fill_u64(d_n_entries, 0ull, 1, s);
+    if (p->dedup) launch_fill_u64(d_n_unique, 0ull, 1, s);
+    return launch_check("connected");
+  }
+  int* cnt = at<int>(ws, L.cnt);
+  long long* off = at<long long>(ws, L.off);
+  launch_diag(H, x, B, d_diag, s);
+  launch_count(H, x, B, p->R, p->gper, cnt, s);
+  launch_scan(cnt, B * p->R, off, s);
+  launch_write(H, x, B, p->R, p->gper, off, capacity, d_ex, d_eh, d_esample, 2, err, s);
+  launch_copy_i64(off + B * p->R, (long long*)d_n_entries, s);
+  if (p->dedup) {
+    if ((int64_t)2 * capacity > p->HT) return fail(NQS_ERR_INVALID_ARGUMENT, "capacity exceeds the plan's hash table");
+    launch_dedup(d_ex, (const long long*)d_n_entries, capacity, at<uint64_t>(ws, L.hkeys), at<int>(ws, L.hslot),
+                 p->HT, d_eunique, d_unique, (long long*)d_n_unique, err, s);
+  }
+  return launch_check("connected");
+}
+
+nqs_status nqs_reduce_table(nqs_plan* p, int64_t B, const double* lps, const double* lpe, const double* diag,
+                            const int32_t* esample, const double* eh, int64_t n_entries, double* eloc, void* ws,
+                            size_t ws_bytes) {
+  if (!p || (B > 0 && (!lps || !diag || !eloc)) || (n_entries > 0 && (!lpe || !esample || !eh)))
+    return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (n_entries < 0) return fail(NQS_ERR_INVALID_ARGUMENT, "n_entries < 0");
+  if (B > p->S) return fail(NQS_ERR_INVALID_ARGUMENT, "batch exceeds the plan's chunk");
+  WsLayout L;
+  nqs_status st = check_ws(p, B, ws, ws_bytes, L);
+  if (st != NQS_OK) return st;
+  hipStream_t s = p->ctx->stream;
+  unsigned* err = at<unsigned>(ws, L.err);
+  launch_fill_u32(err, 0u, 1, s);
+  if (B == 0) return launch_check("reduce");
+  long long* off = at<long long>(ws, L.off);
+  launch_seg_offsets(esample, n_entries, B, off, s);
+  launch_reduce(B, 1, off, n_entries, diag, eh, 2, nullptr, lpe, lps, eloc, err, s);
+  return launch_check("reduce");
+}
+
+nqs_status nqs_device_status(nqs_ctx* ctx, void* ws, uint32_t* flags) {
+  if (!ctx || !ws || !flags) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  unsigned v = 0;
+  HIP_TRY(hipMemcpy(&v, ws, 4, hipMemcpyDeviceToHost));
+  const unsigned zero = 0;
+  HIP_TRY(hipMemcpy(ws, &zero, 4, hipMemcpyHostToDevice));
+  *flags = v;
+  return v ? fail(NQS_ERR_DEVICE, "device error word 0x%x", v) : NQS_OK;
+}
+
+}  // extern "C"

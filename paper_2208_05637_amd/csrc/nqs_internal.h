@@ -1,0 +1,118 @@
+// Internal declarations shared by the host side (nqs_capi.cpp) and the HIP
+// kernels.  Nothing here is part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace nqs {
+
+constexpr int kMaxLayers = 16;
+constexpr int kMaxNB = 64;        // n-blocks of the fused kernel (h / TB)
+constexpr int kMaxNHB = 8;        // head n-blocks ((n + 4) / TB rounded up)
+constexpr int kThreads = 512;     // fused forward workgroup: 8 waves
+
+enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3 };
+
+// Device error-word bits (mirrors NQS_DEV_* in nqs.h).
+constexpr unsigned kErrZeroAmp = 1u, kErrEntryOverflow = 2u, kErrHashOverflow = 4u;
+
+// Network geometry, passed by value to kernels.  "Sorted units": hidden
+// units reordered by degree m_k = 1 + (k mod (n-1)), ascending, so every
+// mask becomes a prefix in that order.  "Positions": inputs and head rows
+// reordered into sampling order.
+struct Geom {
+  int n, L, h, prec;
+  int n_up, n_dn;           // -1 = unconstrained
+  int TB, KSTEP, NB, NHB;   // MFMA block rows, k per fragment, hidden/head n-blocks
+  int nhead;                // n + 4
+  int q, r;                 // h = q (n-1) + r units per degree class (see class_of)
+  int planes;               // 2 for split bf16 (hi, lo), else 1
+  int acc_bytes;            // 8 for the FP64 path, else 4
+  uint64_t spin_pos[2];     // positions whose qubit has spin 0 (even) / 1 (odd)
+  int8_t order[64];         // position -> qubit
+  int8_t pos[64];           // qubit -> position
+  int ks1[kMaxNB];  int off1[kMaxNB + 1];
+  int ksh[kMaxNB];  int offh[kMaxNB + 1];
+  int kso[kMaxNHB]; int offo[kMaxNHB + 1];
+  long long frag_h;         // first fragment of hidden layer 2
+  long long frag_head;      // first fragment of the head
+  long long nfrag;          // fragments per plane
+  long long bias_byte;      // byte offset of the biases inside the packed buffer
+  long long head_bias_off;  // element offset of the head bias inside the bias array
+  long long poff[2 * kMaxLayers + 4];  // offsets of W_1, b_1, ..., W_o, b_o, W_p, b_p
+  long long n_params;
+};
+
+// Unit-class helpers on the sorted hidden units.
+__host__ __device__ inline int prefix_of_class(const Geom& g, int c) {
+  if (c <= 0) return 0;
+  int nm1 = g.n - 1;
+  if (c > nm1) c = nm1;
+  int v = c * g.q + (c < g.r ? c : g.r);
+  return v < g.h ? v : g.h;
+}
+__host__ __device__ inline int class_of_sorted(const Geom& g, int u) {
+  if (g.q == 0) return u;
+  int big = g.r * (g.q + 1);
+  return u < big ? u / (g.q + 1) : g.r + (u - big) / g.q;
+}
+__host__ __device__ inline int orig_of_sorted(const Geom& g, int u) {
+  int c = class_of_sorted(g, u);
+  return c + (u - prefix_of_class(g, c)) * (g.n - 1);
+}
+
+// Tensor of the Hamiltonian on the device.
+struct HamDev {
+  const uint64_t* gx;
+  const long long* goff;
+  const uint64_t* tz;
+  const double* tre;
+  const double* tim;   // nullptr when every folded coefficient is real
+  int G;
+  int gfirst;          // 1 if group 0 is the empty flip
+  int filter;          // spin-sector filter on
+};
+
+// ---- launchers (kernels_*.hip) -------------------------------------------
+void launch_fill_u32(void* p, unsigned v, long long count, hipStream_t s);
+void launch_fill_u64(void* p, unsigned long long v, long long count, hipStream_t s);
+
+void launch_pack_fused(const Geom& g, const float* params, void* packed, hipStream_t s);
+void launch_pack_masked(const Geom& g, const float* params, void* wm, hipStream_t s);
+
+// fused forward on rows [0, count): x[row] u64 -> out[2 row] = (log|psi|, phi)
+void launch_forward(const Geom& g, const void* packed, const uint64_t* x, long long rows_bound,
+                    const long long* d_count, double* out, hipStream_t s);
+
+void launch_diag(const HamDev& H, const uint64_t* x, long long S, double* diag, hipStream_t s);
+void launch_count(const HamDev& H, const uint64_t* x, long long S, int R, int gper, int* cnt,
+                  hipStream_t s);
+void launch_scan(const int* cnt, long long n, long long* off, hipStream_t s);
+void launch_write(const HamDev& H, const uint64_t* x, long long S, int R, int gper,
+                  const long long* off, long long cap, uint64_t* xe, double* he, int* esample,
+                  int hstride, unsigned* err, hipStream_t s);
+
+void launch_dedup(const uint64_t* xe, const long long* d_count, long long cap, uint64_t* hkeys,
+                  int* hslot_id, long long HT, int* eu, uint64_t* xu, long long* d_nu,
+                  unsigned* err, hipStream_t s);
+
+void launch_reduce(long long S, int R, const long long* off, long long cap, const double* diag,
+                   const double* he, int hstride, const int* eu, const double* lpe,
+                   const double* lps, double* eloc, unsigned* err, hipStream_t s);
+void launch_energy(const double* eloc, const double* w, long long B, double* energy,
+                   unsigned* err, hipStream_t s);
+
+// backward: recompute the sample forward on S samples and accumulate the
+// gradient into grad (f64, flat parameter layout).  scratch holds
+// backward_scratch_elems(g, S) elements of the path's backward type
+// (double for the FP64 path, float otherwise).
+long long backward_scratch_elems(const Geom& g, long long S);
+void launch_backward(const Geom& g, const void* wm, const uint64_t* x, long long S,
+                     const double* eloc, const double* w, const double* energy, void* scratch,
+                     double* grad, hipStream_t s);
+
+int forward_rows_per_block(int prec, int h);
+bool forward_supported(int prec, int h);
+
+}  // namespace nqs

@@ -1,0 +1,100 @@
+"""Host-side checks of the C ABI (no GPU needed): exported symbols, the
+Hamiltonian canonicalisation against the oracle (bit-exact), parameter
+layout, error statuses."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import pauli, made
+from gen import molecular_integrals, jordan_wigner_terms, param_count as gen_param_count
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2208_05637_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libnqs.so not built: run __graft_entry__.build()")
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    header = open(os.path.join(ROOT, "include", "nqs.h")).read()
+    names = set(re.findall(r"\b(nqs_[a-z_0-9]+)\s*\(", header))
+    assert len(names) >= 20
+    for name in sorted(names):
+        assert hasattr(lib, name), name
+    from paper_2208_05637_amd import _lib
+    assert names == set(_lib.SIGNATURES)
+
+
+def _ham(n, x, z, c, ci=None, tol=1e-10, flags=1):
+    from paper_2208_05637_amd import Hamiltonian
+    return Hamiltonian(n, x, z, c, coeff_imag=ci, drop_tol=tol, conserves_spin=bool(flags))
+
+
+@pytest.mark.parametrize("N", [3, 6, 12])
+def test_canonical_tensor_bit_exact_vs_oracle(lib, N):
+    h1, h2 = molecular_integrals(N, seed=0)
+    t = jordan_wigner_terms(h1, h2, drop_tol=0.0)
+    # shuffle and split coefficients so the merge step has real work
+    rng = np.random.default_rng(N)
+    perm = rng.permutation(len(t))
+    x = np.concatenate([t.x_mask[perm], t.x_mask[perm[: len(perm) // 3]]])
+    z = np.concatenate([t.z_mask[perm], t.z_mask[perm[: len(perm) // 3]]])
+    c = np.concatenate([t.coeff[perm], 0.25 * t.coeff[perm[: len(perm) // 3]]])
+    ref = pauli.canonical_terms(x, z, c)
+    gx, goff = pauli.groups(ref)
+    H = _ham(2 * N, x, z, c)
+    ex = H.export()
+    assert H.K == len(ref["x"]) and H.G == len(gx) and not H.has_imag
+    np.testing.assert_array_equal(ex["gx"], gx)
+    np.testing.assert_array_equal(ex["goff"], goff)
+    np.testing.assert_array_equal(ex["tz"], ref["z"])
+    assert np.array_equal(ex["tre"], ref["ct"].real)      # bit-exact, same merge order
+    assert np.array_equal(ex["tim"], ref["ct"].imag)
+
+
+def test_odd_y_terms_fold_into_imaginary_plane(lib):
+    x = np.array([0b10, 0b11, 0b1], dtype=np.uint64)
+    z = np.array([0b10, 0b01, 0b1], dtype=np.uint64)
+    c = np.array([0.5, 0.25, -2.0])
+    H = _ham(2, x, z, c)
+    ref = pauli.canonical_terms(x, z, c)
+    ex = H.export()
+    assert H.has_imag
+    assert np.array_equal(ex["tre"], ref["ct"].real)
+    assert np.array_equal(ex["tim"], ref["ct"].imag)
+
+
+def test_error_statuses(lib):
+    from paper_2208_05637_amd import NQSError
+    with pytest.raises(NQSError) as e:
+        _ham(3, [1], [0], [1.0], ci=[1e-3])
+    assert e.value.status == 3            # NQS_ERR_NOT_HERMITIAN
+    with pytest.raises(NQSError) as e:
+        _ham(65, [1], [0], [1.0])
+    assert e.value.status == 2            # NQS_ERR_UNSUPPORTED
+    with pytest.raises(NQSError) as e:
+        _ham(3, [8], [0], [1.0])          # acts on qubit 3 of a 3-qubit system
+    assert e.value.status == 1
+    with pytest.raises(NQSError):
+        _ham(3, [1], [0], [float("nan")])
+
+
+@pytest.mark.parametrize("n,L,h,prec", [(12, 1, 64, "fp64"), (24, 2, 256, "fp32"),
+                                        (60, 4, 1024, "bf16"), (64, 3, 512, "bf16x3")])
+def test_param_layout(lib, n, L, h, prec):
+    from paper_2208_05637_amd import param_count
+    want = made.n_params(made.Net(n=n, n_layers=L, width=h))
+    assert param_count(n, L, h, prec) == want == gen_param_count(n, L, h)
+
+
+def test_unsupported_width_rejected(lib):
+    from paper_2208_05637_amd import param_count, NQSError
+    with pytest.raises(NQSError):
+        param_count(12, 1, 100, "bf16")
