@@ -244,6 +244,30 @@ nqs_status nqs_reduce_table(nqs_plan* plan, int64_t B, const double* d_logpsi_sa
                             const int32_t* d_entry_sample, const double* d_entry_h,
                             int64_t n_entries, double* d_eloc, void* d_ws, size_t ws_bytes);
 
+/* ------------------------------------------------------------- profiling
+ * While enabled, nqs_local_energy / nqs_energy_grad record HIP events on the
+ * context's stream around each call, around its local-energy phase and
+ * around every connected-configuration forward launch, and the forward
+ * kernel stores the number of rows it processed into a slot of the
+ * workspace.  nqs_plan_profile_read synchronises the stream, returns the
+ * totals accumulated since the last read (or enable) and resets them.
+ * Enabling profiling adds event records to the stream; do not enable it for
+ * graph capture.
+ */
+typedef struct {
+  int64_t calls;            /* profiled hot-path calls                        */
+  int64_t forward_launches; /* connected-configuration forward launches       */
+  double  call_ms;          /* sum of call durations                          */
+  double  eloc_ms;          /* sum of local-energy phase durations            */
+  double  forward_ms;       /* sum of forward kernel durations                */
+  double  forward_rows;     /* configurations evaluated by those launches     */
+  double  forward_flops;    /* forward_rows * 2 * (unmasked weights per row)  */
+  double  forward_flops_executed;  /* forward_rows * MFMA flops issued per row
+                                      (masked tiles skipped, padding included) */
+} nqs_profile;
+nqs_status nqs_plan_profile(nqs_plan* plan, int enable);
+nqs_status nqs_plan_profile_read(nqs_plan* plan, void* d_ws, nqs_profile* out);
+
 /* Synchronises the context's stream, reads the device error word of the
    workspace d_ws into *flags (NQS_DEV_* bits) and clears it.  Not for use
    inside graph capture. */

@@ -31,6 +31,12 @@ class NetDesc(C.Structure):
                 ("precision", C.c_int)]
 
 
+class Profile(C.Structure):
+    _fields_ = [("calls", C.c_int64), ("forward_launches", C.c_int64), ("call_ms", C.c_double),
+                ("eloc_ms", C.c_double), ("forward_ms", C.c_double), ("forward_rows", C.c_double),
+                ("forward_flops", C.c_double), ("forward_flops_executed", C.c_double)]
+
+
 class Instance(C.Structure):
     _fields_ = [("plan", C.c_void_p), ("d_params", C.c_void_p), ("d_samples", C.c_void_p),
                 ("d_weights", C.c_void_p), ("B", C.c_int64), ("d_eloc", C.c_void_p),
@@ -66,6 +72,8 @@ SIGNATURES = {
     "nqs_connected": (C.c_int, [_P, _P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ]),
     "nqs_reduce_table": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _I64, _P, _P, _SZ]),
     "nqs_device_status": (C.c_int, [_P, _P, C.POINTER(C.c_uint32)]),
+    "nqs_plan_profile": (C.c_int, [_P, C.c_int]),
+    "nqs_plan_profile_read": (C.c_int, [_P, _P, C.POINTER(Profile)]),
 }
 
 _lib = None

@@ -156,6 +156,16 @@ class Plan:
             self._ws = (raw, need, aligned)
         return C.c_void_p(self._ws[2]), self._ws[1]
 
+    def profile(self, enable=True):
+        L.check(self.lib.nqs_plan_profile(self.handle, 1 if enable else 0), "nqs_plan_profile")
+
+    def profile_read(self):
+        """Totals since the last read: calls, call/eloc/forward ms, forward rows and flops."""
+        out = L.Profile()
+        ws, _ = self.workspace()
+        L.check(self.lib.nqs_plan_profile_read(self.handle, ws, C.byref(out)), "nqs_plan_profile_read")
+        return {f: getattr(out, f) for f, _ in L.Profile._fields_}
+
     def __del__(self):
         if getattr(self, "handle", None):
             self.lib.nqs_plan_destroy(self.handle)

@@ -130,19 +130,18 @@ __device__ __forceinline__ void store_act(char* act, const typename Tr<P>::Acc& 
                                           int KSH) {
   using T = Tr<P>;
   if constexpr (P == P_F64) {
+    // 16x16x4 f64 accumulator: lane l, register rr holds row (l/16) + 4 rr, column l%16.
     const int m = lane & 15, g = lane >> 4;
-    const int n0 = 16 * nb + 4 * g;
-    double v[4];
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
-      double t = acc[rr] + bias[n0 + rr];
-      v[rr] = t > 0.0 ? t : 0.0;
+      const int nl = g + 4 * rr;                 // unit inside the 16-block
+      double t = acc[rr] + bias[16 * nb + nl];
+      t = t > 0.0 ? t : 0.0;
+      const int ks = 2 * nb + (nl >> 3);
+      const int kk = nl & 7;                     // k inside the 8-wide step
+      const int lp = m + 16 * (kk >> 1);
+      *(double*)(act + ((long)(ks * MB + mb) * 64 + lp) * 16 + 8 * (kk & 1)) = t;
     }
-    const int ks = 2 * nb + (g >> 1);
-    const int lp = m + 32 * (g & 1);
-    char* base = act + ((long)(ks * MB + mb) * 64) * 16;
-    *(double2*)(base + lp * 16) = make_double2(v[0], v[1]);
-    *(double2*)(base + (lp + 16) * 16) = make_double2(v[2], v[3]);
   } else {
     const int m = lane & 31, hf = lane >> 5;
 #pragma unroll
@@ -187,7 +186,8 @@ __global__ __launch_bounds__(kThreads) void fused_forward(Geom g, const uint4* _
                                                           const uint64_t* __restrict__ xs,
                                                           long long rows_bound,
                                                           const long long* __restrict__ d_count,
-                                                          double2* __restrict__ out) {
+                                                          double2* __restrict__ out,
+                                                          long long* __restrict__ prof_slot) {
   using T = Tr<P>;
   using Acc = typename T::Acc;
   using S = typename T::S;
@@ -217,6 +217,7 @@ __global__ __launch_bounds__(kThreads) void fused_forward(Geom g, const uint4* _
     long long c = *d_count;
     count = c < rows_bound ? c : rows_bound;
   }
+  if (prof_slot && blockIdx.x == 0 && threadIdx.x == 0) *prof_slot = count;
   const long long row0 = (long long)blockIdx.x * M;
   if (row0 >= count) return;
 
@@ -352,7 +353,7 @@ __global__ __launch_bounds__(kThreads) void fused_forward(Geom g, const uint4* _
       if constexpr (P == P_F64) {
         const int m = mb * 16 + (lane & 15), gq = lane >> 4;
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) stage[m * SP + nb * 16 + 4 * gq + rr] = hacc[hp][rr];
+        for (int rr = 0; rr < 4; ++rr) stage[m * SP + nb * 16 + gq + 4 * rr] = hacc[hp][rr];
       } else {
         const int m = mb * 32 + (lane & 31), hf = lane >> 5;
 #pragma unroll
@@ -405,7 +406,7 @@ __global__ __launch_bounds__(kThreads) void fused_forward(Geom g, const uint4* _
 
 template <int P, int H>
 static void launch_one(const Geom& g, const void* packed, const uint64_t* x, long long rows_bound,
-                       const long long* d_count, double* out, hipStream_t s) {
+                       const long long* d_count, double* out, long long* prof_slot, hipStream_t s) {
   using T = Tr<P>;
   constexpr int M = T::MH / H;
   constexpr int KSH = H / T::KSTEP;
@@ -425,7 +426,7 @@ static void launch_one(const Geom& g, const void* packed, const uint64_t* x, lon
   long long blocks = (rows_bound + M - 1) / M;
   if (blocks <= 0) return;
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kThreads), LDS, s, g,
-                     (const uint4*)packed, x, rows_bound, d_count, (double2*)out);
+                     (const uint4*)packed, x, rows_bound, d_count, (double2*)out, prof_slot);
 }
 
 int forward_rows_per_block(int prec, int h) {
@@ -447,9 +448,9 @@ bool forward_supported(int prec, int h) {
 }
 
 void launch_forward(const Geom& g, const void* packed, const uint64_t* x, long long rows_bound,
-                    const long long* d_count, double* out, hipStream_t s) {
+                    const long long* d_count, double* out, long long* prof_slot, hipStream_t s) {
 #define NQS_CASE(P, H) \
-  if (g.prec == P && g.h == H) { launch_one<P, H>(g, packed, x, rows_bound, d_count, out, s); return; }
+  if (g.prec == P && g.h == H) { launch_one<P, H>(g, packed, x, rows_bound, d_count, out, prof_slot, s); return; }
   NQS_CASE(P_BF16, 256) NQS_CASE(P_BF16, 512) NQS_CASE(P_BF16, 1024)
   NQS_CASE(P_BF16X3, 256) NQS_CASE(P_BF16X3, 512) NQS_CASE(P_BF16X3, 1024)
   NQS_CASE(P_F32, 128) NQS_CASE(P_F32, 256) NQS_CASE(P_F32, 512) NQS_CASE(P_F32, 1024)

@@ -93,11 +93,19 @@ struct nqs_plan {
   int64_t Sb = 0;          // backward chunk
   int bw = 4;              // bytes per element of the backward path
   size_t packed_bytes = 0;
+  double flops_alg_row = 0, flops_exec_row = 0;   // forward flops per configuration
+  // profiling
+  struct Rec { hipEvent_t a, b; int kind; int slot; };   // kind 0 call, 1 eloc, 2 forward
+  bool prof = false;
+  std::vector<Rec> recs;
+  int next_slot = 0;
 };
 
+constexpr int kProfSlots = 8192;
+
 struct WsLayout {
-  size_t err, packed, wm, lps, eloc, energy, cnt, off, diag, xe, he, lpe, hkeys, hslot, eu, xu, nu,
-      bscratch, total;
+  size_t err, prof, packed, wm, lps, eloc, energy, cnt, off, diag, xe, he, lpe, hkeys, hslot, eu, xu,
+      nu, bscratch, total;
 };
 
 static WsLayout layout(const nqs_plan* p, int64_t B) {
@@ -106,6 +114,7 @@ static WsLayout layout(const nqs_plan* p, int64_t B) {
   auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
   const int hs = p->ham->has_imag ? 2 : 1;
   L.err = take(256);
+  L.prof = take((size_t)kProfSlots * 8);
   L.packed = take(p->packed_bytes);
   L.wm = take((size_t)p->g.n_params * p->bw);
   L.lps = take((size_t)std::max<int64_t>(B, 1) * 16);
@@ -474,7 +483,69 @@ nqs_status nqs_plan_create(nqs_ctx* ctx, const nqs_ham* ham, const nqs_net_desc*
   p->Sb = std::min<int64_t>(max_batch, 4096);
   p->bw = g.prec == P_F64 ? 8 : 4;
   p->packed_bytes = (size_t)g.bias_byte + ((size_t)g.L * g.h + (size_t)g.NHB * g.TB) * g.acc_bytes;
+  {
+    // unmasked weights per configuration (MADE masks) and MFMA work issued
+    const int n = g.n, h = g.h;
+    std::vector<int> m(h);
+    for (int k = 0; k < h; ++k) m[k] = 1 + k % (n - 1);
+    double nnz1 = 0, nnzh = 0, nnzo = 0, nnzp = 0;
+    std::vector<long long> cnt_le(n + 1, 0);   // units with degree <= d
+    for (int k = 0; k < h; ++k) cnt_le[m[k]] += 1;
+    for (int d = 1; d <= n; ++d) cnt_le[d] += cnt_le[d - 1];
+    for (int k = 0; k < h; ++k) {
+      nnz1 += std::min(m[k], n);
+      nnzh += (double)cnt_le[m[k]];
+      if (m[k] <= n - 2) nnzp += 4;
+    }
+    for (int j = 0; j < n; ++j) nnzo += (double)cnt_le[j];   // d(j) = 1 + pos: units with m < d
+    p->flops_alg_row = 2.0 * (nnz1 + (g.L - 1) * nnzh + nnzo + nnzp);
+    long long fr = 0;
+    for (int nb = 0; nb < g.NB; ++nb) fr += g.ks1[nb] + (long long)(g.L - 1) * g.ksh[nb];
+    for (int nb = 0; nb < g.NHB; ++nb) fr += g.kso[nb];
+    p->flops_exec_row = 2.0 * g.TB * g.KSTEP * (double)fr;
+  }
   *out = p;
+  return NQS_OK;
+}
+
+nqs_status nqs_plan_profile(nqs_plan* p, int enable) {
+  if (!p) return fail(NQS_ERR_INVALID_ARGUMENT, "plan is NULL");
+  p->prof = enable != 0;
+  return NQS_OK;
+}
+
+nqs_status nqs_plan_profile_read(nqs_plan* p, void* ws, nqs_profile* out) {
+  if (!p || !out) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
+  memset(out, 0, sizeof(*out));
+  HIP_TRY(hipStreamSynchronize(p->ctx->stream));
+  std::vector<long long> slots;
+  if (p->next_slot > 0) {
+    if (!ws) return fail(NQS_ERR_INVALID_ARGUMENT, "workspace is NULL");
+    WsLayout L = layout(p, 0);
+    slots.resize(std::min(p->next_slot, kProfSlots));
+    HIP_TRY(hipMemcpy(slots.data(), (char*)ws + L.prof, slots.size() * 8, hipMemcpyDeviceToHost));
+  }
+  for (auto& r : p->recs) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+    if (r.kind == 0) { out->calls += 1; out->call_ms += ms; }
+    else if (r.kind == 1) out->eloc_ms += ms;
+    else if (r.kind == 3) { out->calls += 1; out->call_ms += ms; out->eloc_ms += ms; }
+    else {
+      out->forward_launches += 1;
+      out->forward_ms += ms;
+      if (r.slot >= 0 && r.slot < (int)slots.size()) out->forward_rows += (double)slots[r.slot];
+    }
+  }
+  std::vector<hipEvent_t> evs;   // records may share their start event
+  for (auto& r : p->recs) { evs.push_back(r.a); evs.push_back(r.b); }
+  std::sort(evs.begin(), evs.end());
+  evs.erase(std::unique(evs.begin(), evs.end()), evs.end());
+  for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+  out->forward_flops = out->forward_rows * p->flops_alg_row;
+  out->forward_flops_executed = out->forward_rows * p->flops_exec_row;
+  p->recs.clear();
+  p->next_slot = 0;
   return NQS_OK;
 }
 
@@ -511,6 +582,33 @@ static nqs_status check_ws(const nqs_plan* p, int64_t B, void* ws, size_t ws_byt
 template <typename T>
 static T* at(void* ws, size_t off) { return (T*)((char*)ws + off); }
 
+// Event pair on the plan's stream when profiling is on.
+static hipEvent_t prof_mark(nqs_plan* p) {
+  if (!p->prof) return nullptr;
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  (void)hipEventRecord(e, p->ctx->stream);
+  return e;
+}
+static void prof_close(nqs_plan* p, hipEvent_t a, int kind, int slot) {
+  if (!p->prof || !a) return;
+  hipEvent_t b = prof_mark(p);
+  if (b) p->recs.push_back({a, b, kind, slot});
+}
+
+static void forward_profiled(nqs_plan* p, void* ws, const WsLayout& L, const void* packed,
+                             const uint64_t* x, long long bound, const long long* d_count, double* out) {
+  hipEvent_t a = prof_mark(p);
+  long long* slot = nullptr;
+  int si = -1;
+  if (p->prof && p->next_slot < kProfSlots) {
+    si = p->next_slot++;
+    slot = at<long long>(ws, L.prof) + si;
+  }
+  launch_forward(p->g, packed, x, bound, d_count, out, slot, p->ctx->stream);
+  prof_close(p, a, 2, si);
+}
+
 // local energies of B samples into eloc; lps (sample log psi) computed first.
 static nqs_status run_local_energy(nqs_plan* p, const float* params, const uint64_t* x, int64_t B,
                                    double* eloc, void* ws, const WsLayout& L) {
@@ -520,7 +618,7 @@ static nqs_status run_local_energy(nqs_plan* p, const float* params, const uint6
   void* packed = at<void>(ws, L.packed);
   double* lps = at<double>(ws, L.lps);
   launch_pack_fused(p->g, params, packed, s);
-  launch_forward(p->g, packed, x, B, nullptr, lps, s);
+  forward_profiled(p, ws, L, packed, x, B, nullptr, lps);
   const int hs = p->ham->has_imag ? 2 : 1;
   for (int64_t c0 = 0; c0 < B; c0 += p->S) {
     const int64_t Sc = std::min<int64_t>(p->S, B - c0);
@@ -543,9 +641,9 @@ static nqs_status run_local_energy(nqs_plan* p, const float* params, const uint6
       uint64_t* xu = at<uint64_t>(ws, L.xu);
       long long* nu = at<long long>(ws, L.nu);
       launch_dedup(xe, d_total, p->EC, at<uint64_t>(ws, L.hkeys), at<int>(ws, L.hslot), p->HT, eu, xu, nu, err, s);
-      launch_forward(p->g, packed, xu, bound, nu, lpe, s);
+      forward_profiled(p, ws, L, packed, xu, bound, nu, lpe);
     } else {
-      launch_forward(p->g, packed, xe, bound, d_total, lpe, s);
+      forward_profiled(p, ws, L, packed, xe, bound, d_total, lpe);
     }
     launch_reduce(Sc, p->R, off, p->EC, diag, he, hs, eu, lpe, lps + 2 * c0, eloc + 2 * c0, err, s);
   }
@@ -565,7 +663,7 @@ nqs_status nqs_log_psi(nqs_plan* p, const float* params, const uint64_t* x, int6
   hipStream_t s = p->ctx->stream;
   void* packed = at<void>(ws, L.packed);
   launch_pack_fused(p->g, params, packed, s);
-  launch_forward(p->g, packed, x, n, nullptr, out, s);
+  launch_forward(p->g, packed, x, n, nullptr, out, nullptr, s);
   return launch_check("log psi");
 }
 
@@ -575,9 +673,14 @@ nqs_status nqs_local_energy(nqs_plan* p, const float* params, const uint64_t* x,
   WsLayout L;
   nqs_status st = check_ws(p, B, ws, ws_bytes, L);
   if (st != NQS_OK) return st;
+  hipEvent_t t0 = prof_mark(p);
   launch_fill_u32(at<void>(ws, L.err), 0u, 1, p->ctx->stream);
-  if (B == 0) return launch_check("local energy");
-  return run_local_energy(p, params, x, B, eloc, ws, L);
+  if (B > 0) {
+    st = run_local_energy(p, params, x, B, eloc, ws, L);
+    if (st != NQS_OK) return st;
+  }
+  prof_close(p, t0, 3, -1);   // a call that is only a local-energy phase
+  return launch_check("local energy");
 }
 
 nqs_status nqs_energy_grad(nqs_plan* p, const float* params, const uint64_t* x, const double* w, int64_t B,
@@ -589,10 +692,15 @@ nqs_status nqs_energy_grad(nqs_plan* p, const float* params, const uint64_t* x, 
   if (st != NQS_OK) return st;
   hipStream_t s = p->ctx->stream;
   unsigned* err = at<unsigned>(ws, L.err);
+  hipEvent_t t0 = prof_mark(p);
   launch_fill_u32(err, 0u, 1, s);
   double* el = eloc ? eloc : at<double>(ws, L.eloc);
   st = run_local_energy(p, params, x, B, el, ws, L);
   if (st != NQS_OK) return st;
+  if (t0) {
+    hipEvent_t t1 = prof_mark(p);
+    if (t1) p->recs.push_back({t0, t1, 1, -1});
+  }
   launch_energy(el, w, B, energy, err, s);
   launch_fill_u64(grad, 0ull, p->g.n_params, s);
   void* wm = at<void>(ws, L.wm);
@@ -601,6 +709,10 @@ nqs_status nqs_energy_grad(nqs_plan* p, const float* params, const uint64_t* x, 
   for (int64_t c0 = 0; c0 < B; c0 += p->Sb) {
     const int64_t Sc = std::min<int64_t>(p->Sb, B - c0);
     launch_backward(p->g, wm, x + c0, Sc, el + 2 * c0, w ? w + c0 : nullptr, energy, scratch, grad, s);
+  }
+  if (t0) {
+    hipEvent_t t2 = prof_mark(p);
+    if (t2) p->recs.push_back({t0, t2, 0, -1});
   }
   return launch_check("energy gradient");
 }

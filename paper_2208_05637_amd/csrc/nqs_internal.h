@@ -83,7 +83,7 @@ void launch_pack_masked(const Geom& g, const float* params, void* wm, hipStream_
 
 // fused forward on rows [0, count): x[row] u64 -> out[2 row] = (log|psi|, phi)
 void launch_forward(const Geom& g, const void* packed, const uint64_t* x, long long rows_bound,
-                    const long long* d_count, double* out, hipStream_t s);
+                    const long long* d_count, double* out, long long* prof_slot, hipStream_t s);
 
 void launch_diag(const HamDev& H, const uint64_t* x, long long S, double* diag, hipStream_t s);
 void launch_count(const HamDev& H, const uint64_t* x, long long S, int R, int gper, int* cnt,
