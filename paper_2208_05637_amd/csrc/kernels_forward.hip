@@ -173,6 +173,142 @@ __device__ __forceinline__ void store_act(char* act, const typename Tr<P>::Acc& 
   }
 }
 
+// K loop of one layer for the wave's NBW n-blocks and MBW m-blocks.  Weight
+// fragments are double-buffered in registers and requested two k steps
+// before use; blocks whose (masked) k range has ended are skipped.
+// act(j, ks, frag) supplies the activation fragment of m-block j.
+// Loads are unconditional (the k index is clamped into the block's range, a
+// cache hit) so the compiler can count outstanding loads exactly; only the
+// MFMAs of finished blocks are skipped, on a wave-uniform scalar branch.
+//
+// Every block's k extent is even and the extents ascend with the block index
+// inside a wave, so the loop runs in phases with a compile-time set of active
+// blocks {I0..NBW-1}: no branches in the steady state, static register
+// double-buffering, and exact load accounting by the compiler.
+//
+// Weight fragments are read with raw buffer loads: a scalar byte offset per
+// (block, k step), one VGPR for the lane offset, and hardware range checking
+// against the packed buffer.  Scheduling fences keep the compiler from
+// pulling the next loads' consumers up next to them.
+struct WBuf {
+  __amdgpu_buffer_rsrc_t rsrc;
+  int plane_bytes;   // offset of the second (low) bf16 plane
+  int voff;          // lane * 16
+};
+
+__device__ __forceinline__ uint4 wload(const WBuf& b, int soff) {
+  return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(b.rsrc, b.voff, soff, 0));
+}
+
+template <int P, int NBW, int MBW, int I0, class ActFn>
+__device__ __forceinline__ void kphase(typename Tr<P>::Acc (&acc)[NBW][MBW], const WBuf& wb_,
+                                       const int (&wbase)[NBW], const int (&kend)[NBW], int ks,
+                                       uint4 (&wa)[NBW][Tr<P>::PL], uint4 (&wb)[NBW][Tr<P>::PL],
+                                       ActFn& act) {
+  constexpr int PL = Tr<P>::PL;
+  auto loadw = [&](uint4 (&w)[NBW][PL], int k) {
+#pragma unroll
+    for (int i = I0; i < NBW; ++i) {
+      const int kc = max(0, k < kend[i] ? k : kend[i] - 1);   // clamped into the block
+      const int so = wbase[i] + kc * 1024;
+      w[i][0] = wload(wb_, so);
+      if constexpr (PL == 2) w[i][1] = wload(wb_, so + wb_.plane_bytes);
+    }
+  };
+  auto step = [&](uint4 (&w)[NBW][PL], int k) {
+    uint4 af[MBW][PL];
+#pragma unroll
+    for (int j = 0; j < MBW; ++j) act(j, k, af[j]);
+#pragma unroll
+    for (int i = I0; i < NBW; ++i)
+#pragma unroll
+      for (int j = 0; j < MBW; ++j) mma<P>(acc[i][j], w[i], af[j]);
+  };
+  const int stop = kend[I0];
+  auto body = [&]() {
+    step(wa, ks);
+    __builtin_amdgcn_sched_barrier(0);
+    loadw(wa, ks + 2);
+    __builtin_amdgcn_sched_barrier(0);
+    step(wb, ks + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    loadw(wb, ks + 3);
+    __builtin_amdgcn_sched_barrier(0);
+    ks += 2;
+  };
+  if constexpr (I0 == 0) {
+    // the caller guarantees ks < kend[0]: a do-while keeps the preloads of
+    // every block in front of the loop instead of sunk behind an entry test
+    do { body(); } while (ks < stop);
+  } else {
+    while (ks < stop) body();
+  }
+  if constexpr (I0 + 1 < NBW) kphase<P, NBW, MBW, I0 + 1>(acc, wb_, wbase, kend, ks, wa, wb, act);
+}
+
+template <int P, int NBW, int MBW, class ActFn>
+__device__ __forceinline__ void kloop(typename Tr<P>::Acc (&acc)[NBW][MBW], const WBuf& wbuf,
+                                      const int (&fragi)[NBW], const int (&ksi)[NBW], int ks0,
+                                      ActFn act) {
+  constexpr int PL = Tr<P>::PL;
+  uint4 wa[NBW][PL], wb[NBW][PL];
+  int kend[NBW], wbase[NBW];
+#pragma unroll
+  for (int i = 0; i < NBW; ++i) {
+    kend[i] = __builtin_amdgcn_readfirstlane(ksi[i]);
+    wbase[i] = __builtin_amdgcn_readfirstlane(fragi[i] * 1024);
+  }
+  ks0 = __builtin_amdgcn_readfirstlane(ks0);
+  // every block has at least two k steps and the extents ascend, so after
+  // this test phase 0 (all blocks active) is non-empty
+  if (kend[NBW - 1] <= ks0 || kend[0] <= ks0) return;
+  // same issue order as the loop body (all of wa, then all of wb) so the
+  // outstanding-load state is identical on loop entry and on the back edge
+#pragma unroll
+  for (int i = 0; i < NBW; ++i) {
+    const int k0 = max(0, ks0 < kend[i] ? ks0 : kend[i] - 1);
+    wa[i][0] = wload(wbuf, wbase[i] + k0 * 1024);
+    if constexpr (PL == 2) wa[i][1] = wload(wbuf, wbase[i] + k0 * 1024 + wbuf.plane_bytes);
+  }
+#pragma unroll
+  for (int i = 0; i < NBW; ++i) {
+    const int k1 = max(0, ks0 + 1 < kend[i] ? ks0 + 1 : kend[i] - 1);
+    wb[i][0] = wload(wbuf, wbase[i] + k1 * 1024);
+    if constexpr (PL == 2) wb[i][1] = wload(wbuf, wbase[i] + k1 * 1024 + wbuf.plane_bytes);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  kphase<P, NBW, MBW, 0>(acc, wbuf, wbase, kend, ks0, wa, wb, act);
+}
+
+// Head k loop for one (block, m-block) tile over [k0, k1) (multiples of 8):
+// eight weight fragments are requested back to back, then consumed in order,
+// so the load latency is paid once per eight MFMA steps.
+template <int P, class ActFn>
+__device__ __forceinline__ void head_loop(typename Tr<P>::Acc& acc, const WBuf& wbuf, int frag0,
+                                          int k0, int k1, ActFn act) {
+  constexpr int PL = Tr<P>::PL;
+  constexpr int D = 8;
+  const int base = __builtin_amdgcn_readfirstlane(frag0 * 1024);
+  k0 = __builtin_amdgcn_readfirstlane(k0);
+  k1 = __builtin_amdgcn_readfirstlane(k1);
+  for (int k = k0; k < k1; k += D) {
+    uint4 w[D][PL];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      w[d][0] = wload(wbuf, base + (k + d) * 1024);
+      if constexpr (PL == 2) w[d][1] = wload(wbuf, base + (k + d) * 1024 + wbuf.plane_bytes);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      uint4 af[PL];
+      act(k + d, af);
+      mma<P>(acc, w[d], af);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 template <typename S>
 __device__ __forceinline__ S softplus(S z) {
   S a = z > S(0) ? z : -z;
@@ -210,7 +346,8 @@ __global__ __launch_bounds__(kThreads) void fused_forward(Geom g, const uint4* _
   uint64_t* ylds = (uint64_t*)(act + REGION);
   S* stage = (S*)act;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
   const int wn = wave % WN, wm = wave / WN;
   long long count = rows_bound;
   if (d_count) {
@@ -221,8 +358,11 @@ __global__ __launch_bounds__(kThreads) void fused_forward(Geom g, const uint4* _
   const long long row0 = (long long)blockIdx.x * M;
   if (row0 >= count) return;
 
-  const long long plane_stride = g.nfrag * 64;   // uint4 per plane
   const S* biases = (const S*)((const char*)wpk + g.bias_byte);
+  WBuf wbuf;
+  wbuf.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)wpk, (short)0, (int)g.bias_byte, 0x00020000);
+  wbuf.plane_bytes = (int)(g.nfrag * 1024);
+  wbuf.voff = lane * 16;
 
   for (int t = tid; t < M; t += kThreads) {
     long long row = row0 + t;
@@ -233,13 +373,22 @@ __global__ __launch_bounds__(kThreads) void fused_forward(Geom g, const uint4* _
   }
   __syncthreads();
 
+  // n-blocks of this wave: a contiguous group (similar masked k extent, so
+  // every block stays active through the k loop); the two waves that share a
+  // SIMD (w and w+4) take complementary groups so every SIMD does equal work.
   int nbl[NBW], mbl[MBW];
+  const int grp = (WN == 8) ? (wave < 4 ? wave : 11 - wave) : wn;
 #pragma unroll
-  for (int i = 0; i < NBW; ++i) nbl[i] = (i & 1) ? (i * WN + WN - 1 - wn) : (i * WN + wn);
+  for (int i = 0; i < NBW; ++i) nbl[i] = grp * NBW + i;
 #pragma unroll
   for (int j = 0; j < MBW; ++j) mbl[j] = j * WM + wm;
 
   Acc acc[NBW][MBW];
+  auto lds_act = [&](int j, int ks, uint4 (&f)[PL]) {
+    const uint4* a = (const uint4*)act + ((long)(ks * MB + mbl[j])) * 64 + lane;
+    f[0] = a[0];
+    if constexpr (PL == 2) f[1] = a[(long)KSH * MB * 64];
+  };
 
   // ---------------------------------------------------------------- layer 1
   {
@@ -247,29 +396,14 @@ __global__ __launch_bounds__(kThreads) void fused_forward(Geom g, const uint4* _
     for (int i = 0; i < NBW; ++i)
 #pragma unroll
       for (int j = 0; j < MBW; ++j) acc[i][j] = Acc{};
-    int ksi[NBW], offi[NBW], ksmax = 0;
+    int ksi[NBW], fragi[NBW];
 #pragma unroll
     for (int i = 0; i < NBW; ++i) {
       ksi[i] = g.ks1[nbl[i]];
-      offi[i] = g.off1[nbl[i]];
-      ksmax = ksi[i] > ksmax ? ksi[i] : ksmax;
+      fragi[i] = g.off1[nbl[i]];
     }
-    for (int ks = 0; ks < ksmax; ++ks) {
-      uint4 af[MBW][PL];
-#pragma unroll
-      for (int j = 0; j < MBW; ++j) input_frag<P>(ylds, mbl[j], ks, lane, g.n, af[j]);
-#pragma unroll
-      for (int i = 0; i < NBW; ++i) {
-        if (ks < ksi[i]) {
-          uint4 wf[PL];
-          const uint4* src = wpk + ((long long)(offi[i] + ks)) * 64 + lane;
-          wf[0] = src[0];
-          if constexpr (PL == 2) wf[1] = src[plane_stride];
-#pragma unroll
-          for (int j = 0; j < MBW; ++j) mma<P>(acc[i][j], wf, af[j]);
-        }
-      }
-    }
+    kloop<P, NBW, MBW>(acc, wbuf, fragi, ksi, 0,
+                       [&](int j, int ks, uint4 (&f)[PL]) { input_frag<P>(ylds, mbl[j], ks, lane, g.n, f); });
 #pragma unroll
     for (int i = 0; i < NBW; ++i)
 #pragma unroll
@@ -283,35 +417,14 @@ __global__ __launch_bounds__(kThreads) void fused_forward(Geom g, const uint4* _
     for (int i = 0; i < NBW; ++i)
 #pragma unroll
       for (int j = 0; j < MBW; ++j) acc[i][j] = Acc{};
-    const long long lbase = g.frag_h + (long long)(l - 2) * g.offh[NB];
-    int ksi[NBW], ksmax = 0;
-    long long offi[NBW];
+    const int lbase = (int)(g.frag_h + (long long)(l - 2) * g.offh[NB]);
+    int ksi[NBW], fragi[NBW];
 #pragma unroll
     for (int i = 0; i < NBW; ++i) {
       ksi[i] = g.ksh[nbl[i]];
-      offi[i] = lbase + g.offh[nbl[i]];
-      ksmax = ksi[i] > ksmax ? ksi[i] : ksmax;
+      fragi[i] = lbase + g.offh[nbl[i]];
     }
-    for (int ks = 0; ks < ksmax; ++ks) {
-      uint4 af[MBW][PL];
-#pragma unroll
-      for (int j = 0; j < MBW; ++j) {
-        const uint4* a = (const uint4*)act + ((long)(ks * MB + mbl[j])) * 64 + lane;
-        af[j][0] = a[0];
-        if constexpr (PL == 2) af[j][1] = a[(long)KSH * MB * 64];
-      }
-#pragma unroll
-      for (int i = 0; i < NBW; ++i) {
-        if (ks < ksi[i]) {
-          uint4 wf[PL];
-          const uint4* src = wpk + (offi[i] + ks) * 64 + lane;
-          wf[0] = src[0];
-          if constexpr (PL == 2) wf[1] = src[plane_stride];
-#pragma unroll
-          for (int j = 0; j < MBW; ++j) mma<P>(acc[i][j], wf, af[j]);
-        }
-      }
-    }
+    kloop<P, NBW, MBW>(acc, wbuf, fragi, ksi, 0, lds_act);
     __syncthreads();
     const S* bl = biases + (long)(l - 1) * H;
 #pragma unroll
@@ -322,43 +435,56 @@ __global__ __launch_bounds__(kThreads) void fused_forward(Geom g, const uint4* _
   }
 
   // -------------------------------------------------------------------- head
+  // Work items (head n-block, m-block, k slice) are spread over all 8 waves;
+  // k slices of one tile are combined with LDS atomic adds.
   Acc hacc[HP];
   const int npairs = g.NHB * MB;
+  const int ksplit = npairs >= 8 ? 1 : 8 / npairs;
+  const int nitems = npairs * ksplit;
 #pragma unroll
   for (int hp = 0; hp < HP; ++hp) {
     hacc[hp] = Acc{};
-    const int pr = wave + 8 * hp;
-    if (pr < npairs) {
+    const int item = wave + 8 * hp;
+    if (item < nitems) {
+      const int pr = item / ksplit, part = item % ksplit;
       const int nb = pr / MB, mb = pr % MB;
       const int kso = g.kso[nb];
-      const long long base = g.frag_head + g.offo[nb];
-      for (int ks = 0; ks < kso; ++ks) {
-        uint4 af[PL], wf[PL];
+      const int chunk = (((kso + ksplit - 1) / ksplit) + 7) & ~7;   // head extents are multiples of 8
+      const int k0 = part * chunk, k1 = min(kso, k0 + chunk);
+      head_loop<P>(hacc[hp], wbuf, (int)(g.frag_head + g.offo[nb]), k0, k1, [&](int ks, uint4 (&f)[PL]) {
         const uint4* a = (const uint4*)act + ((long)(ks * MB + mb)) * 64 + lane;
-        af[0] = a[0];
-        if constexpr (PL == 2) af[1] = a[(long)KSH * MB * 64];
-        const uint4* src = wpk + (base + ks) * 64 + lane;
-        wf[0] = src[0];
-        if constexpr (PL == 2) wf[1] = src[plane_stride];
-        mma<P>(hacc[hp], wf, af);
-      }
+        f[0] = a[0];
+        if constexpr (PL == 2) f[1] = a[(long)KSH * MB * 64];
+      });
     }
   }
   __syncthreads();
+  if (ksplit > 1) {
+    for (int e = tid; e < M * SP; e += kThreads) stage[e] = S(0);
+    __syncthreads();
+  }
 #pragma unroll
   for (int hp = 0; hp < HP; ++hp) {
-    const int pr = wave + 8 * hp;
-    if (pr < npairs) {
+    const int item = wave + 8 * hp;
+    if (item < nitems) {
+      const int pr = item / ksplit;
       const int nb = pr / MB, mb = pr % MB;
       if constexpr (P == P_F64) {
         const int m = mb * 16 + (lane & 15), gq = lane >> 4;
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) stage[m * SP + nb * 16 + gq + 4 * rr] = hacc[hp][rr];
+        for (int rr = 0; rr < 4; ++rr) {
+          S* dst = &stage[m * SP + nb * 16 + gq + 4 * rr];
+          if (ksplit > 1) atomicAdd(dst, hacc[hp][rr]);
+          else *dst = hacc[hp][rr];
+        }
       } else {
         const int m = mb * 32 + (lane & 31), hf = lane >> 5;
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-          stage[m * SP + nb * 32 + 8 * (r >> 2) + 4 * hf + (r & 3)] = hacc[hp][r];
+        for (int r = 0; r < 16; ++r) {
+          S* dst = &stage[m * SP + nb * 32 + 8 * (r >> 2) + 4 * hf + (r & 3)];
+          if (ksplit > 1) atomicAdd(dst, hacc[hp][r]);
+          else *dst = hacc[hp][r];
+        }
       }
     }
   }

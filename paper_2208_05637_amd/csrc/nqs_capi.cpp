@@ -370,7 +370,9 @@ static nqs_status build_geom(const nqs_net_desc* nd, Geom& g) {
   else { g.q = 0; g.r = h; }
   g.planes = g.prec == P_BF16X3 ? 2 : 1;
   g.acc_bytes = g.prec == P_F64 ? 8 : 4;
-  auto ceil_div = [](int a, int b) { return (a + b - 1) / b; };
+  // k steps per block, rounded up to an even count (the fused kernel steps by
+  // two); the extra fragments hold masked (zero) weights.
+  auto ceil_div = [](int a, int b) { return (((a + b - 1) / b) + 1) & ~1; };
   g.off1[0] = g.offh[0] = g.offo[0] = 0;
   for (int nb = 0; nb < g.NB; ++nb) {
     const int ulast = std::min(h, g.TB * (nb + 1)) - 1;
@@ -386,7 +388,7 @@ static nqs_status build_geom(const nqs_net_desc* nd, Geom& g) {
     int kend = 0;
     for (int t = g.TB * nb; t < std::min(g.TB * (nb + 1), g.nhead); ++t)
       kend = std::max(kend, t < n ? prefix_of_class(g, t) : prefix_of_class(g, n - 2));
-    g.kso[nb] = ceil_div(kend, g.KSTEP);
+    g.kso[nb] = (((kend + g.KSTEP - 1) / g.KSTEP) + 7) & ~7;   // head: multiples of 8 steps
     g.offo[nb + 1] = g.offo[nb] + g.kso[nb];
   }
   g.frag_h = g.off1[g.NB];
