@@ -4,15 +4,21 @@
 One step = nqs_energy_grad on one batch: sample forward, enumeration and
 matrix elements of every connected configuration, the MFMA forward on all of
 them, the FP64 ratio-and-reduce, the weighted energy and the hand backward.
-Prints one JSON line (see the keys below); diagnostics go to stderr.
+Prints one JSON line; diagnostics go to stderr.
 
-Workload (default): 60 qubits (30 spatial orbitals, 15 up + 15 down
-electrons) Jordan-Wigner Hamiltonian from the seeded molecular-like integral
-generator (K ~ 1.19e6 merged Pauli strings), 65536 sector-uniform samples
-reduced to unique samples with count weights, masked network L = 4, h = 1024,
-BF16 GEMMs with FP32 accumulation and FP64 sums.  The plain FP32 GPU path is
-timed on a prefix of the same samples, and the FP64 oracle on a few samples
-(the CPU baseline).
+Default workload: 60 qubits (30 spatial orbitals, 15 up + 15 down electrons),
+Jordan-Wigner Hamiltonian of the seeded molecular-like integral generator
+(1,189,663 merged Pauli strings), 65536 sector-uniform samples reduced to
+unique samples with count weights, masked network L = 4, h = 1024.  The timed
+path multiplies in split BF16 (hi/lo operands, three BF16 MFMAs, FP32
+accumulation) with FP64 matrix elements, sums and energy; the value is its
+local-energy throughput B*K/t.
+
+Beside it, on the first --prefix samples of the same batch:
+  * the plain BF16 and the plain FP32 GPU paths (throughput + energy),
+  * the FP64 GPU path (the energy reference of the prefix),
+and the FP64 CPU oracle on --cpu-samples samples (CPU baseline, and the
+per-sample check of every GPU path, FP64 included).
 """
 import argparse
 import json
@@ -38,18 +44,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c4", help="c1..c4, c5a..c5d")
     ap.add_argument("--batch", type=int, default=None, help="override the batch (diagnostic runs)")
-    ap.add_argument("--precision", default=None, help="override the network arithmetic")
-    ap.add_argument("--fp32-prefix", type=int, default=1024)
+    ap.add_argument("--precision", default=None, help="override the timed path's arithmetic")
+    ap.add_argument("--prefix", type=int, default=1024, help="samples for the side paths")
     ap.add_argument("--cpu-samples", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-side", action="store_true", help="skip the prefix paths")
     ap.add_argument("--chunk", type=int, default=0, help="samples per chunk (0 = plan default)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build evaluates one GPU's share of the batch on a single MI355X; "
-              "multi-GPU runs are not part of it (see DESIGN.md, sharding).", file=sys.stderr)
+              "runs on several GPUs are not part of it (DESIGN.md, section 7, says how the path "
+              "would shard).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -69,8 +76,9 @@ def main():
     H = nqs.Hamiltonian.from_terms(terms).upload(ctx)
     K = H.K
     B = len(samples)
-    plan = nqs.Plan(ctx, H, cfg["L"], cfg["h"], cfg["n_up"], cfg["n_dn"], prec, max_batch=B,
-                    dedup=cfg["dedup"], chunk_samples=args.chunk)
+    mk = lambda p, mb: nqs.Plan(ctx, H, cfg["L"], cfg["h"], cfg["n_up"], cfg["n_dn"], p, max_batch=mb,
+                                dedup=cfg["dedup"], chunk_samples=args.chunk)
+    plan = mk(prec, B)
     log(f"K={K} G={H.G} entries/sample={plan.entries_per_sample} chunk={plan.chunk_samples} "
         f"dedup={plan.dedup} workspace={plan.workspace_size(B) / 2**30:.2f} GiB")
     dev = ctx.device
@@ -87,8 +95,6 @@ def main():
         nqs.energy_grad(plan, params, x, w, eloc=eloc, energy=energy, grad=grad)
         torch.cuda.synchronize()
         log(f"warmup step {i}: {time.time() - t:.2f}s")
-    if nqs.device_status(plan):
-        raise RuntimeError("device error flag after warm-up")
 
     plan.profile(True)
     torch.cuda.synchronize()
@@ -101,19 +107,23 @@ def main():
     torch.cuda.synchronize()
     prof = plan.profile_read()
     plan.profile(False)
+    if nqs.device_status(plan):
+        raise RuntimeError("device error flag set during the timed steps")
     ms_step = ev0.elapsed_time(ev1) / args.steps
     eloc_ms = prof["eloc_ms"] / max(prof["calls"], 1)
     value = B * K / (eloc_ms / 1e3)
     log(f"step {ms_step:.1f} ms, local energy {eloc_ms:.1f} ms, E = {energy[0].item():.10f}")
     fwd_ms_launch = prof["forward_ms"] / max(prof["forward_launches"], 1)
     achieved = prof["forward_flops"] / (prof["forward_ms"] / 1e3) / 1e12
-    executed = prof["forward_flops_executed"] / (prof["forward_ms"] / 1e3) / 1e12
+    issued = prof["forward_flops_executed"] / (prof["forward_ms"] / 1e3) / 1e12
+    mfma_factor = 3.0 if prec == "bf16x3" else 1.0     # split BF16: three MFMAs per product
     peak = PEAKS_TFLOPS[prec]
     log(f"forward kernel: {prof['forward_launches']} launches, {fwd_ms_launch:.2f} ms/launch, "
-        f"{achieved:.1f} TFLOP/s algorithmic, {executed:.1f} TFLOP/s issued (peak {peak})")
+        f"{achieved:.1f} TFLOP/s algorithmic, {issued * mfma_factor:.1f} TFLOP/s MFMA issued (peak {peak})")
 
+    el_main = eloc.cpu().numpy()
     out = {
-        "metric": "E_loc samples*terms/s (BF16 network, FP64 sums) + VMC step ms",
+        "metric": "E_loc samples*terms/s at |dE| <= 1e-5 Ha (BF16 MFMA network, FP64 sums) + VMC step ms",
         "value": value,
         "unit": "samples*terms/s",
         "n_gpus": 1,
@@ -128,7 +138,7 @@ def main():
         "config": {
             "workload": f"{args.workload}: {cfg['n']} qubits ({cfg['N']} orbitals, {cfg['n_up']}+{cfg['n_dn']} "
                         f"electrons), K={K} Pauli strings, G={H.G} flips, B={B} unique samples "
-                        f"(count weights), masked MLP L={cfg['L']} h={cfg['h']}",
+                        f"(count weights), masked MLP L={cfg['L']} h={cfg['h']}, {prec} network",
             "global_batch": B,
             "entries_per_sample": plan.entries_per_sample,
             "eloc_ms": eloc_ms,
@@ -143,54 +153,69 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / peak,
             "traffic": None,
-            "issued_tflops": executed,
+            "mfma_issued_tflops": issued * mfma_factor,
+            "mfma_issued_frac": issued * mfma_factor / peak,
             "ms_per_launch": fwd_ms_launch,
             "rows": prof["forward_rows"],
+            "alg_flop_per_row": prof["forward_flops"] / max(prof["forward_rows"], 1),
         },
     }
 
-    if not args.no_fp32:
-        P = min(args.fp32_prefix, B)
-        plan32 = nqs.Plan(ctx, H, cfg["L"], cfg["h"], cfg["n_up"], cfg["n_dn"], "fp32", max_batch=P,
-                          dedup=cfg["dedup"])
+    side = {}
+    P = min(args.prefix, B)
+    if not args.no_side:
         xp = x[:P].contiguous()
-        el32 = nqs.local_energy(plan32, params, xp)
-        torch.cuda.synchronize()
-        plan32.profile(True)
-        el32 = nqs.local_energy(plan32, params, xp)
-        p32 = plan32.profile_read()
-        plan32.profile(False)
-        v32 = P * K / (p32["eloc_ms"] / 1e3)
         wp = weights[:P]
-        e_bf = np.sum(wp * eloc[:P, 0].cpu().numpy()) / np.sum(wp)
-        e_32 = np.sum(wp * el32[:, 0].cpu().numpy()) / np.sum(wp)
-        out["fp32_path"] = {"value": v32, "unit": "samples*terms/s", "prefix_samples": P,
-                            "speedup_bf16_over_fp32": value / v32,
-                            "energy_prefix_bf16_minus_fp32": float(e_bf - e_32),
-                            "forward_tflops": p32["forward_flops"] / (p32["forward_ms"] / 1e3) / 1e12}
-        log(f"fp32 path: {v32:.3e} samples*terms/s on {P} samples; bf16/fp32 = {value / v32:.2f}; "
-            f"dE(prefix) = {e_bf - e_32:.3e}")
-        del plan32
+        for p in ("fp64", "fp32", "bf16"):
+            if p == prec:
+                continue
+            pl = mk(p, P)
+            nqs.local_energy(pl, params, xp)      # warm
+            torch.cuda.synchronize()
+            pl.profile(True)
+            el = nqs.local_energy(pl, params, xp)
+            pr = pl.profile_read()
+            pl.profile(False)
+            side[p] = dict(eloc=el.cpu().numpy(), value=P * K / (pr["eloc_ms"] / 1e3),
+                           tflops=pr["forward_flops"] / (pr["forward_ms"] / 1e3) / 1e12)
+            log(f"{p} path on {P} samples: {side[p]['value']:.3e} samples*terms/s, "
+                f"{side[p]['tflops']:.1f} TFLOP/s")
+            del pl
+        side[prec] = dict(eloc=el_main[:P], value=value, tflops=achieved)
+        Ep = {p: math.fsum(wp * d["eloc"][:, 0]) / math.fsum(wp) for p, d in side.items()}
+        ref = Ep.get("fp64")
+        acc = {}
+        for p, d in side.items():
+            acc[p] = {"samples_terms_per_s": d["value"], "forward_tflops": d["tflops"],
+                      "energy_prefix": Ep[p],
+                      "abs_dE_vs_fp64_gpu": None if ref is None else abs(Ep[p] - ref)}
+        out["paths_on_prefix"] = {"prefix_samples": P, **acc}
+        if "fp32" in side:
+            out["speedup_vs_fp32_path"] = value / side["fp32"]["value"]
+        if ref is not None:
+            out["abs_dE_prefix_vs_fp64"] = abs(Ep[prec] - ref)
+        log("prefix energies: " + ", ".join(f"{p}={Ep[p]:.10f}" for p in Ep))
 
     if not args.no_cpu:
         from threadpoolctl import threadpool_info
         from oracle import made, pauli, vmc
-        m = min(args.cpu_samples, B)
-        ref = pauli.canonical_terms(terms.x_mask, terms.z_mask, terms.coeff)
+        m = min(args.cpu_samples, B, P)
+        refH = pauli.canonical_terms(terms.x_mask, terms.z_mask, terms.coeff)
         net = made.Net(n=cfg["n"], n_layers=cfg["L"], width=cfg["h"], n_up=cfg["n_up"], n_dn=cfg["n_dn"])
         t = time.time()
-        el_ref = vmc.local_energy(ref, net, params_np, samples[:m])
+        el_ref = vmc.local_energy(refH, net, params_np, samples[:m])
         dt = time.time() - t
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-        gpu_el = eloc[:m].cpu().numpy()
-        d_el = np.abs(gpu_el[:, 0] + 1j * gpu_el[:, 1] - el_ref)
+        checks = {}
+        for p, d in ({prec: dict(eloc=el_main)} | side).items():
+            e = d["eloc"][:m]
+            checks[p] = float(np.max(np.abs(e[:, 0] + 1j * e[:, 1] - el_ref)))
         out["cpu_baseline"] = {"value": m * K / dt, "unit": "samples*terms/s", "cores": threads,
                                "kind": "oracle",
-                               "sample": f"FP64 oracle local energy of the first {m} samples of the same "
-                                         f"workload ({dt:.1f} s)",
-                               "max_abs_dE_loc_vs_gpu": float(np.max(d_el))}
-        log(f"oracle: {m} samples in {dt:.1f}s on {threads} threads; max |dE_loc| GPU vs oracle = "
-            f"{np.max(d_el):.3e}")
+                               "sample": f"FP64 oracle local energy of the first {m} samples of the "
+                                         f"same workload ({dt:.1f} s)",
+                               "max_abs_dE_loc_vs_oracle": checks}
+        log(f"oracle: {m} samples in {dt:.1f}s on {threads} threads; max |dE_loc| vs oracle: {checks}")
 
     print(json.dumps(out), flush=True)
 

@@ -73,15 +73,15 @@ CONFIGS = {
                weights="counts"),
     "c3": dict(N=20, seed=0, B=32768, L=3, h=512, precision="bf16", dedup=True,
                weights="counts"),
-    "c4": dict(N=30, seed=0, B=65536, L=4, h=1024, precision="bf16", dedup=False,
+    "c4": dict(N=30, seed=0, B=65536, L=4, h=1024, precision="bf16x3", dedup=False,
                weights="counts"),
-    "c5a": dict(N=8, seed=1, B=4096, L=3, h=512, precision="bf16", dedup=True,
+    "c5a": dict(N=8, seed=1, B=4096, L=3, h=512, precision="bf16x3", dedup=True,
                 weights="counts"),
-    "c5b": dict(N=14, seed=2, B=16384, L=3, h=512, precision="bf16", dedup=False,
+    "c5b": dict(N=14, seed=2, B=16384, L=3, h=512, precision="bf16x3", dedup=False,
                 weights="counts"),
-    "c5c": dict(N=22, seed=3, B=32768, L=3, h=512, precision="bf16", dedup=False,
+    "c5c": dict(N=22, seed=3, B=32768, L=3, h=512, precision="bf16x3", dedup=False,
                 weights="counts"),
-    "c5d": dict(N=32, seed=4, B=16384, L=3, h=512, precision="bf16", dedup=False,
+    "c5d": dict(N=32, seed=4, B=16384, L=3, h=512, precision="bf16x3", dedup=False,
                 weights="counts"),
 }
 

@@ -40,10 +40,17 @@ template <> struct Tr<P_F32> {
   static constexpr int NACC = 16;
 };
 template <> struct Tr<P_F64> {
-  static constexpr int TB = 16, KSTEP = 8, PL = 1, MH = 8192;
+  static constexpr int TB = 16, KSTEP = 8, PL = 1, MH = 16384;
   using Acc = f64x4; using S = double;
   static constexpr int NACC = 4;
 };
+
+// Configurations per workgroup: the activations of the tile fill 128 KB of
+// LDS (the narrow FP64 nets use half of it so the head staging fits).
+template <int P, int H>
+constexpr int rows_per_block() {
+  return (P == P_F64 && H < 256) ? 8192 / H : Tr<P>::MH / H;
+}
 
 __device__ __forceinline__ unsigned short bf16_rne(float f) {
   unsigned u = __float_as_uint(f);
@@ -328,7 +335,7 @@ __global__ __launch_bounds__(kThreads) void fused_forward(Geom g, const uint4* _
   using Acc = typename T::Acc;
   using S = typename T::S;
   constexpr int TB = T::TB, PL = T::PL, NACC = T::NACC;
-  constexpr int M = T::MH / H;
+  constexpr int M = rows_per_block<P, H>();
   constexpr int NB = H / TB, MB = M / TB;
   constexpr int WN = NB < 8 ? NB : 8, WM = 8 / WN;
   constexpr int NBW = NB / WN, MBW = MB / WM;
@@ -341,7 +348,8 @@ __global__ __launch_bounds__(kThreads) void fused_forward(Geom g, const uint4* _
   extern __shared__ uint4 smem[];
   char* act = (char*)smem;
   constexpr long ACT_BYTES = (long)PL * KSH * MB * 1024;
-  constexpr long STAGE_BYTES = (long)M * SP * sizeof(S);
+  constexpr int KSPLIT_MAX = MB >= 8 ? 1 : 8 / MB;       // head k slices (one plane each)
+  constexpr long STAGE_BYTES = (long)M * SP * sizeof(S) * KSPLIT_MAX;
   constexpr long REGION = ACT_BYTES > STAGE_BYTES ? ACT_BYTES : STAGE_BYTES;
   uint64_t* ylds = (uint64_t*)(act + REGION);
   S* stage = (S*)act;
@@ -459,32 +467,23 @@ __global__ __launch_bounds__(kThreads) void fused_forward(Geom g, const uint4* _
     }
   }
   __syncthreads();
-  if (ksplit > 1) {
-    for (int e = tid; e < M * SP; e += kThreads) stage[e] = S(0);
-    __syncthreads();
-  }
+  // each k slice writes its own staging plane; the epilogue adds the planes
+  // in a fixed order, so the result does not depend on wave scheduling
 #pragma unroll
   for (int hp = 0; hp < HP; ++hp) {
     const int item = wave + 8 * hp;
     if (item < nitems) {
-      const int pr = item / ksplit;
+      const int pr = item / ksplit, part = item % ksplit;
       const int nb = pr / MB, mb = pr % MB;
+      S* plane = stage + (long)part * M * SP;
       if constexpr (P == P_F64) {
         const int m = mb * 16 + (lane & 15), gq = lane >> 4;
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          S* dst = &stage[m * SP + nb * 16 + gq + 4 * rr];
-          if (ksplit > 1) atomicAdd(dst, hacc[hp][rr]);
-          else *dst = hacc[hp][rr];
-        }
+        for (int rr = 0; rr < 4; ++rr) plane[m * SP + nb * 16 + gq + 4 * rr] = hacc[hp][rr];
       } else {
         const int m = mb * 32 + (lane & 31), hf = lane >> 5;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          S* dst = &stage[m * SP + nb * 32 + 8 * (r >> 2) + 4 * hf + (r & 3)];
-          if (ksplit > 1) atomicAdd(dst, hacc[hp][r]);
-          else *dst = hacc[hp][r];
-        }
+        for (int r = 0; r < 16; ++r) plane[m * SP + nb * 32 + 8 * (r >> 2) + 4 * hf + (r & 3)] = hacc[hp][r];
       }
     }
   }
@@ -497,10 +496,15 @@ __global__ __launch_bounds__(kThreads) void fused_forward(Geom g, const uint4* _
     const S* hb = biases + (long)g.L * H;
     const uint64_t y = ylds[row];
     const bool constrained = g.n_up >= 0 && g.n_dn >= 0;
+    auto head_out = [&](int col) {
+      S v = stage[row * SP + col];
+      for (int p = 1; p < ksplit; ++p) v += stage[((long)p * M + row) * SP + col];
+      return v + hb[col];
+    };
     double sum = 0.0;
     int bad = 0;
     for (int t = sub; t < g.n; t += TPR) {
-      const S o = stage[row * SP + t] + hb[t];
+      const S o = head_out(t);
       const int sp = g.order[t] & 1;
       const int bit = (int)((y >> t) & 1ull);
       bool fr = true;
@@ -524,7 +528,7 @@ __global__ __launch_bounds__(kThreads) void fused_forward(Geom g, const uint4* _
     const long long grow = row0 + row;
     if (sub == 0 && grow < count) {
       const int sel = (int)(2 * ((y >> (g.n - 2)) & 1ull) + ((y >> (g.n - 1)) & 1ull));
-      const double phi = (double)(stage[row * SP + g.n + sel] + hb[g.n + sel]);
+      const double phi = (double)head_out(g.n + sel);
       out[grow] = make_double2(bad ? -INFINITY : 0.5 * sum, phi);
     }
   }
@@ -534,13 +538,13 @@ template <int P, int H>
 static void launch_one(const Geom& g, const void* packed, const uint64_t* x, long long rows_bound,
                        const long long* d_count, double* out, long long* prof_slot, hipStream_t s) {
   using T = Tr<P>;
-  constexpr int M = T::MH / H;
+  constexpr int M = rows_per_block<P, H>();
   constexpr int KSH = H / T::KSTEP;
   constexpr int MB = M / T::TB;
   constexpr int NHBMAX = (68 + T::TB - 1) / T::TB;
   constexpr int SP = NHBMAX * T::TB + 1;
   constexpr long ACT = (long)T::PL * KSH * MB * 1024;
-  constexpr long STG = (long)M * SP * sizeof(typename T::S);
+  constexpr long STG = (long)M * SP * sizeof(typename T::S) * (MB >= 8 ? 1 : 8 / MB);
   constexpr size_t LDS = (ACT > STG ? ACT : STG) + M * 8;
   static_assert(LDS <= 160 * 1024, "LDS budget");
   auto kern = fused_forward<P, H>;
@@ -560,7 +564,7 @@ int forward_rows_per_block(int prec, int h) {
     case P_BF16: return 65536 / h;
     case P_BF16X3: return 32768 / h;
     case P_F32: return 32768 / h;
-    default: return 8192 / h;
+    default: return h < 256 ? 8192 / h : 16384 / h;
   }
 }
 
@@ -568,7 +572,7 @@ bool forward_supported(int prec, int h) {
   switch (prec) {
     case P_BF16: case P_BF16X3: return h == 256 || h == 512 || h == 1024;
     case P_F32: return h == 128 || h == 256 || h == 512 || h == 1024;
-    case P_F64: return h == 64 || h == 128 || h == 256 || h == 512;
+    case P_F64: return h == 64 || h == 128 || h == 256 || h == 512 || h == 1024;
   }
   return false;
 }
@@ -581,6 +585,7 @@ void launch_forward(const Geom& g, const void* packed, const uint64_t* x, long l
   NQS_CASE(P_BF16X3, 256) NQS_CASE(P_BF16X3, 512) NQS_CASE(P_BF16X3, 1024)
   NQS_CASE(P_F32, 128) NQS_CASE(P_F32, 256) NQS_CASE(P_F32, 512) NQS_CASE(P_F32, 1024)
   NQS_CASE(P_F64, 64) NQS_CASE(P_F64, 128) NQS_CASE(P_F64, 256) NQS_CASE(P_F64, 512)
+  NQS_CASE(P_F64, 1024)
 #undef NQS_CASE
 }
 

@@ -50,6 +50,7 @@ def _oracle_net(n, L, h, nu, nd, order=None):
 
 @pytest.mark.parametrize("prec,h,L,std,tol", [
     ("fp64", 64, 1, 0.3, 1e-12), ("fp64", 128, 2, 0.3, 1e-12), ("fp64", 512, 3, 0.1, 1e-12),
+    ("fp64", 1024, 2, 0.1, 1e-12),
     ("fp32", 128, 2, 0.3, 2e-5), ("fp32", 256, 3, 0.3, 2e-5), ("fp32", 1024, 2, 0.1, 2e-5),
     # split bf16 keeps ~16 mantissa bits per operand: a few 1e-5 relative on logits of O(10)
     ("bf16x3", 256, 2, 0.3, 5e-4), ("bf16x3", 1024, 2, 0.1, 5e-4),
@@ -274,10 +275,13 @@ def test_edge_cases(nqs, ctx):
         nqs.local_energy(plan, params, sector_samples(n, 3, 3, 65, seed=1))
 
 
-def test_deterministic(nqs, ctx):
-    N, n, L, h = 8, 16, 2, 256
+@pytest.mark.parametrize("prec,h", [("bf16", 256), ("bf16", 1024), ("bf16x3", 512), ("fp32", 1024),
+                                    ("fp64", 1024)])
+def test_deterministic(nqs, ctx, prec, h):
+    """Two calls give bit-identical results (covers shapes whose head is split over k)."""
+    N, n, L = 8, 16, 2
     terms, H, ref = _setup(nqs, ctx, N, seed=1)
-    plan = nqs.Plan(ctx, H, L, h, 4, 4, "bf16", max_batch=300, dedup=True, chunk_samples=128)
+    plan = nqs.Plan(ctx, H, L, h, 4, 4, prec, max_batch=300, dedup=True, chunk_samples=128)
     params = torch.from_numpy(init_params(n, L, h, seed=1)).cuda()
     xs, w = unique_with_counts(sector_samples(n, 4, 4, 300, seed=2))
     e1, g1, l1 = [t.clone() for t in nqs.energy_grad(plan, params, xs, w)]
