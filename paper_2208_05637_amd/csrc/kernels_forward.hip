@@ -52,6 +52,29 @@ constexpr int rows_per_block() {
   return (P == P_F64 && H < 256) ? 8192 / H : Tr<P>::MH / H;
 }
 
+// Waves per workgroup: 16 (four per SIMD) for the wide BF16 nets, so that
+// every SIMD keeps two or more waves in flight until the end of each layer;
+// 8 elsewhere.
+template <int P, int H>
+constexpr int waves_per_block() {
+  return ((P == P_BF16 || P == P_BF16X3) && H >= 512) ? 16 : 8;
+}
+
+// Head k slices (one LDS staging plane each) when the head has fewer
+// (block, m-block) tiles than waves.
+// At most 4 slices, and no more than the planes that fit in 128 KB.
+template <int P, int H>
+constexpr int head_ksplit_max() {
+  constexpr int M = rows_per_block<P, H>();
+  constexpr int MB = M / Tr<P>::TB;
+  constexpr int NW = waves_per_block<P, H>();
+  constexpr int SP = ((68 + Tr<P>::TB - 1) / Tr<P>::TB) * Tr<P>::TB + 1;
+  constexpr int fit = (131072 / (M * SP * (int)sizeof(typename Tr<P>::S))) > 0
+                          ? 131072 / (M * SP * (int)sizeof(typename Tr<P>::S)) : 1;
+  constexpr int want = MB >= NW ? 1 : (NW / MB < 4 ? NW / MB : 4);
+  return want < fit ? want : fit;
+}
+
 __device__ __forceinline__ unsigned short bf16_rne(float f) {
   unsigned u = __float_as_uint(f);
   u += 0x7FFFu + ((u >> 16) & 1u);
@@ -325,30 +348,28 @@ __device__ __forceinline__ S softplus(S z) {
 }
 
 template <int P, int H>
-__global__ __launch_bounds__(kThreads) void fused_forward(Geom g, const uint4* __restrict__ wpk,
-                                                          const uint64_t* __restrict__ xs,
-                                                          long long rows_bound,
-                                                          const long long* __restrict__ d_count,
-                                                          double2* __restrict__ out,
-                                                          long long* __restrict__ prof_slot) {
+__global__ __launch_bounds__((64 * waves_per_block<P, H>())) void fused_forward(
+    Geom g, const uint4* __restrict__ wpk, const uint64_t* __restrict__ xs, long long rows_bound,
+    const long long* __restrict__ d_count, double2* __restrict__ out, long long* __restrict__ prof_slot) {
   using T = Tr<P>;
   using Acc = typename T::Acc;
   using S = typename T::S;
   constexpr int TB = T::TB, PL = T::PL, NACC = T::NACC;
+  constexpr int NW = waves_per_block<P, H>(), NT = 64 * NW;
   constexpr int M = rows_per_block<P, H>();
   constexpr int NB = H / TB, MB = M / TB;
-  constexpr int WN = NB < 8 ? NB : 8, WM = 8 / WN;
+  constexpr int WN = NB < NW ? NB : NW, WM = NW / WN;
   constexpr int NBW = NB / WN, MBW = MB / WM;
   constexpr int KSH = H / T::KSTEP;
   constexpr int NHBMAX = (68 + TB - 1) / TB;
-  constexpr int HP = (NHBMAX * MB + 7) / 8;
+  constexpr int HP = (NHBMAX * MB + NW - 1) / NW;
   constexpr int SP = NHBMAX * TB + 1;
   static_assert(MB % WM == 0 && NB % WN == 0 && MB >= 1, "tile shape");
 
   extern __shared__ uint4 smem[];
   char* act = (char*)smem;
   constexpr long ACT_BYTES = (long)PL * KSH * MB * 1024;
-  constexpr int KSPLIT_MAX = MB >= 8 ? 1 : 8 / MB;       // head k slices (one plane each)
+  constexpr int KSPLIT_MAX = head_ksplit_max<P, H>();
   constexpr long STAGE_BYTES = (long)M * SP * sizeof(S) * KSPLIT_MAX;
   constexpr long REGION = ACT_BYTES > STAGE_BYTES ? ACT_BYTES : STAGE_BYTES;
   uint64_t* ylds = (uint64_t*)(act + REGION);
@@ -372,7 +393,7 @@ __global__ __launch_bounds__(kThreads) void fused_forward(Geom g, const uint4* _
   wbuf.plane_bytes = (int)(g.nfrag * 1024);
   wbuf.voff = lane * 16;
 
-  for (int t = tid; t < M; t += kThreads) {
+  for (int t = tid; t < M; t += NT) {
     long long row = row0 + t;
     uint64_t x = xs[row < count ? row : row0];
     uint64_t y = 0;
@@ -385,7 +406,9 @@ __global__ __launch_bounds__(kThreads) void fused_forward(Geom g, const uint4* _
   // every block stays active through the k loop); the two waves that share a
   // SIMD (w and w+4) take complementary groups so every SIMD does equal work.
   int nbl[NBW], mbl[MBW];
-  const int grp = (WN == 8) ? (wave < 4 ? wave : 11 - wave) : wn;
+  // waves s, s+4, s+8, s+12 share SIMD s: deal the groups in a snake over the
+  // SIMDs so each SIMD gets a light and a heavy group per pair of waves
+  const int grp = (WN == NW) ? (((wave >> 2) & 1) ? (wave & ~3) + 3 - (wave & 3) : wave) : wn;
 #pragma unroll
   for (int i = 0; i < NBW; ++i) nbl[i] = grp * NBW + i;
 #pragma unroll
@@ -447,12 +470,12 @@ __global__ __launch_bounds__(kThreads) void fused_forward(Geom g, const uint4* _
   // k slices of one tile are combined with LDS atomic adds.
   Acc hacc[HP];
   const int npairs = g.NHB * MB;
-  const int ksplit = npairs >= 8 ? 1 : 8 / npairs;
+  const int ksplit = npairs >= NW ? 1 : min(KSPLIT_MAX, NW / npairs);
   const int nitems = npairs * ksplit;
 #pragma unroll
   for (int hp = 0; hp < HP; ++hp) {
     hacc[hp] = Acc{};
-    const int item = wave + 8 * hp;
+    const int item = wave + NW * hp;
     if (item < nitems) {
       const int pr = item / ksplit, part = item % ksplit;
       const int nb = pr / MB, mb = pr % MB;
@@ -471,7 +494,7 @@ __global__ __launch_bounds__(kThreads) void fused_forward(Geom g, const uint4* _
   // in a fixed order, so the result does not depend on wave scheduling
 #pragma unroll
   for (int hp = 0; hp < HP; ++hp) {
-    const int item = wave + 8 * hp;
+    const int item = wave + NW * hp;
     if (item < nitems) {
       const int pr = item / ksplit, part = item % ksplit;
       const int nb = pr / MB, mb = pr % MB;
@@ -490,7 +513,7 @@ __global__ __launch_bounds__(kThreads) void fused_forward(Geom g, const uint4* _
   __syncthreads();
 
   // ------------------------------------------------------------ row epilogue
-  constexpr int TPR = kThreads / M >= 1 ? kThreads / M : 1;
+  constexpr int TPR = NT / M >= 1 ? NT / M : 1;
   const int row = tid / TPR, sub = tid % TPR;
   if (row < M) {
     const S* hb = biases + (long)g.L * H;
@@ -544,7 +567,7 @@ static void launch_one(const Geom& g, const void* packed, const uint64_t* x, lon
   constexpr int NHBMAX = (68 + T::TB - 1) / T::TB;
   constexpr int SP = NHBMAX * T::TB + 1;
   constexpr long ACT = (long)T::PL * KSH * MB * 1024;
-  constexpr long STG = (long)M * SP * sizeof(typename T::S) * (MB >= 8 ? 1 : 8 / MB);
+  constexpr long STG = (long)M * SP * sizeof(typename T::S) * head_ksplit_max<P, H>();
   constexpr size_t LDS = (ACT > STG ? ACT : STG) + M * 8;
   static_assert(LDS <= 160 * 1024, "LDS budget");
   auto kern = fused_forward<P, H>;
@@ -555,7 +578,7 @@ static void launch_one(const Geom& g, const void* packed, const uint64_t* x, lon
   }
   long long blocks = (rows_bound + M - 1) / M;
   if (blocks <= 0) return;
-  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kThreads), LDS, s, g,
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves_per_block<P, H>()), LDS, s, g,
                      (const uint4*)packed, x, rows_bound, d_count, (double2*)out, prof_slot);
 }
 
