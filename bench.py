@@ -9,16 +9,17 @@ Prints one JSON line; diagnostics go to stderr.
 Default workload: 60 qubits (30 spatial orbitals, 15 up + 15 down electrons),
 Jordan-Wigner Hamiltonian of the seeded molecular-like integral generator
 (1,189,663 merged Pauli strings), 65536 sector-uniform samples reduced to
-unique samples with count weights, masked network L = 4, h = 1024.  The timed
-path multiplies in split BF16 (hi/lo operands, three BF16 MFMAs, FP32
-accumulation) with FP64 matrix elements, sums and energy; the value is its
-local-energy throughput B*K/t.
+unique samples with count weights, a BF16 masked network L = 4, h = 1024
+(BF16-valued parameters).  The timed path multiplies BF16 weights with
+activations carried as two BF16 terms (two BF16 MFMAs, FP32 accumulation),
+with FP64 matrix elements, sums and energy; the value is its local-energy
+throughput B*K/t.  The whole step is also replayed from a HIP graph.
 
-Beside it, on the first --prefix samples of the same batch:
-  * the plain BF16 and the plain FP32 GPU paths (throughput + energy),
-  * the FP64 GPU path (the energy reference of the prefix),
-and the FP64 CPU oracle on --cpu-samples samples (CPU baseline, and the
-per-sample check of every GPU path, FP64 included).
+Beside it, on the first --prefix samples of the same batch and the same
+network: the timed path again, the split-BF16, plain BF16 and FP32 GPU paths
+(throughput + energy) and the FP64 GPU path (the energy reference of the
+prefix); and the FP64 CPU oracle on --cpu-samples samples (CPU baseline, and
+the per-sample check of every GPU path).
 """
 import argparse
 import json
@@ -30,7 +31,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAKS_TFLOPS = {"bf16": 2500.0, "bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6}
+ARITH = {"bf16w": "BF16 network (BF16-valued weights x two-term BF16 activations, 2 BF16 MFMAs, FP32 accumulation)",
+         "bf16x3": "split-BF16 network (FP32 weights and activations as two BF16 terms, 3 BF16 MFMAs)",
+         "bf16": "plain BF16 network", "fp32": "FP32 network", "fp64": "FP64 network"}
+PEAKS_TFLOPS = {"bf16": 2500.0, "bf16x3": 2500.0, "bf16w": 2500.0, "fp32": 157.3, "fp64": 78.6}
+METRIC = "E_loc samples\u00b7terms/s + VMC step ms, BF16 vs FP32 GPU at |\u0394E|\u22641e-5 Ha"
 
 
 def log(*a):
@@ -50,6 +55,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-side", action="store_true", help="skip the prefix paths")
     ap.add_argument("--chunk", type=int, default=0, help="samples per chunk (0 = plan default)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (plan defaults)")
+    ap.add_argument("--waves", type=int, default=0, help="force the forward's waves per workgroup")
+    ap.add_argument("--graph-steps", type=int, default=1,
+                    help="replays of the HIP-graph-captured step after the timed steps (0 = none)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -102,6 +111,15 @@ def main():
     energy = torch.empty(3, dtype=torch.float64, device=dev)
     grad = torch.empty(plan.n_params, dtype=torch.float64, device=dev)
     plan.workspace(B)
+    tune = None
+    if args.waves:
+        plan.configure(waves_per_block=args.waves)
+    elif not args.no_tune:
+        t = time.time()
+        tune = plan.autotune(params, x)
+        log(f"autotune ({time.time() - t:.1f}s, probe {tune['probe_samples']} samples): "
+            + ", ".join(f"{c['waves_per_block']}w/dedup{int(c['dedup'])}/S{c['chunk_samples']}: {c['ms']:.1f} ms"
+                        for c in tune["candidates"]) + f" -> {plan.kernel_info()}")
 
     for i in range(args.warmup):
         t = time.time()
@@ -129,14 +147,42 @@ def main():
     fwd_ms_launch = prof["forward_ms"] / max(prof["forward_launches"], 1)
     achieved = prof["forward_flops"] / (prof["forward_ms"] / 1e3) / 1e12
     issued = prof["forward_flops_executed"] / (prof["forward_ms"] / 1e3) / 1e12
-    mfma_factor = 3.0 if prec == "bf16x3" else 1.0     # split BF16: three MFMAs per product
     peak = PEAKS_TFLOPS[prec]
     log(f"forward kernel: {prof['forward_launches']} launches, {fwd_ms_launch:.2f} ms/launch, "
-        f"{achieved:.1f} TFLOP/s algorithmic, {issued * mfma_factor:.1f} TFLOP/s MFMA issued (peak {peak})")
+        f"{achieved:.1f} TFLOP/s algorithmic, {issued:.1f} TFLOP/s MFMA issued (peak {peak})")
 
     el_main = eloc.cpu().numpy()
+    graph = None
+    if args.graph_steps > 0:
+        # the whole step (local energies, energy, gradient) as one captured HIP graph
+        ref = (energy.clone(), grad.clone(), eloc.clone())
+        gs = torch.cuda.Stream()
+        ctx.use_stream(gs)
+        try:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=gs):
+                nqs.energy_grad(plan, params, x, w, eloc=eloc, energy=energy, grad=grad)
+        finally:
+            ctx.use_stream(torch.cuda.current_stream())
+        energy.zero_(); grad.zero_(); eloc.zero_()
+        torch.cuda.synchronize()
+        # replay() launches on the current stream
+        cur = torch.cuda.current_stream()
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        g0.record(cur)
+        for i in range(args.graph_steps):
+            g.replay()
+        g1.record(cur)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(energy, ref[0]) and torch.equal(grad, ref[1]) and torch.equal(eloc, ref[2]))
+        graph = {"ms_per_step": g0.elapsed_time(g1) / args.graph_steps, "replays": args.graph_steps,
+                 "equal_to_eager": same}
+        log(f"graph-captured step: {graph['ms_per_step']:.1f} ms, equal to eager: {same}")
+        del g
+    kinfo = plan.kernel_info()
     out = {
-        "metric": "E_loc samples*terms/s at |dE| <= 1e-5 Ha (BF16 MFMA network, FP64 sums) + VMC step ms",
+        "metric": METRIC,
         "value": value,
         "unit": "samples*terms/s",
         "n_gpus": 1,
@@ -146,16 +192,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": prec,
+        "dtype": {"bf16w": "bf16", "bf16x3": "bf16x3", "bf16": "bf16", "fp32": "fp32", "fp64": "f64"}[prec],
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: {cfg['n']} qubits ({cfg['N']} orbitals, {cfg['n_up']}+{cfg['n_dn']} "
                         f"electrons), K={K} Pauli strings, G={H.G} flips, B={B} unique samples "
-                        f"(count weights), masked MLP L={cfg['L']} h={cfg['h']}, {prec} network",
+                        f"(count weights), masked MLP L={cfg['L']} h={cfg['h']} with {cfg['params'].upper()} "
+                        f"parameters, {ARITH[prec]}; FP64 matrix elements, sums and energy",
             "global_batch": B,
             "entries_per_sample": plan.entries_per_sample,
             "eloc_ms": eloc_ms,
             "chunk_samples": plan.chunk_samples,
+            "dedup": plan.dedup,
+            "forward_waves_per_block": kinfo["waves_per_block"],
+            "forward_rows_per_block": kinfo["rows_per_block"],
+            "autotuned": kinfo["tuned"],
             "energy": energy[0].item(),
         },
         "roofline": {
@@ -166,23 +217,33 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / peak,
             "traffic": None,
-            "mfma_issued_tflops": issued * mfma_factor,
-            "mfma_issued_frac": issued * mfma_factor / peak,
+            "mfma_issued_tflops": issued,
+            "mfma_issued_frac": issued / peak,
             "ms_per_launch": fwd_ms_launch,
             "rows": prof["forward_rows"],
             "alg_flop_per_row": prof["forward_flops"] / max(prof["forward_rows"], 1),
         },
     }
 
+    if tune is not None:
+        out["autotune"] = {"probe_samples": tune["probe_samples"], "from_cache": tune["from_cache"],
+                           "candidates": tune["candidates"], "chosen": tune["chosen"]}
+    if graph is not None:
+        out["graph_step"] = graph
+
     side = {}
     P = min(args.prefix, B)
     if not args.no_side:
         xp = x[:P].contiguous()
         wp = weights[:P]
-        for p in ("fp64", "fp32", "bf16"):
-            if p == prec:
+        for p in (prec, "bf16x3", "bf16", "fp32", "fp64"):
+            if p in side:
                 continue
             pl = mk(p, P)
+            if p == prec:
+                pl.configure(waves_per_block=kinfo["waves_per_block"])
+            elif not args.no_tune and p != "fp64":
+                pl.autotune(params, xp)
             nqs.local_energy(pl, params, xp)      # warm
             torch.cuda.synchronize()
             pl.profile(True)
@@ -194,7 +255,6 @@ def main():
             log(f"{p} path on {P} samples: {side[p]['value']:.3e} samples*terms/s, "
                 f"{side[p]['tflops']:.1f} TFLOP/s")
             del pl
-        side[prec] = dict(eloc=el_main[:P], value=value, tflops=achieved)
         Ep = {p: math.fsum(wp * d["eloc"][:, 0]) / math.fsum(wp) for p, d in side.items()}
         ref = Ep.get("fp64")
         acc = {}
@@ -204,7 +264,8 @@ def main():
                       "abs_dE_vs_fp64_gpu": None if ref is None else abs(Ep[p] - ref)}
         out["paths_on_prefix"] = {"prefix_samples": P, **acc}
         if "fp32" in side:
-            out["speedup_vs_fp32_path"] = value / side["fp32"]["value"]
+            # same samples, same network, each path with its own tuned kernel
+            out["speedup_vs_fp32_path"] = side[prec]["value"] / side["fp32"]["value"]
         if ref is not None:
             out["abs_dE_prefix_vs_fp64"] = abs(Ep[prec] - ref)
         log("prefix energies: " + ", ".join(f"{p}={Ep[p]:.10f}" for p in Ep))
@@ -220,7 +281,7 @@ def main():
         dt = time.time() - t
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
         checks = {}
-        for p, d in ({prec: dict(eloc=el_main)} | side).items():
+        for p, d in ({**side, prec: dict(eloc=el_main)}).items():
             e = d["eloc"][:m]
             checks[p] = float(np.max(np.abs(e[:, 0] + 1j * e[:, 1] - el_ref)))
         out["cpu_baseline"] = {"value": m * K / dt, "unit": "samples*terms/s", "cores": threads,

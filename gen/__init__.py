@@ -14,11 +14,11 @@ carry spin up.  The paper's first qubit ``x_1`` is bit 0.
 """
 from .integrals import molecular_integrals
 from .jw import jordan_wigner_terms, PauliTerms
-from .inputs import (hamiltonian, init_params, param_count, sector_samples,
+from .inputs import (hamiltonian, init_params, param_count, round_bf16, sector_samples,
                      unique_with_counts, CONFIGS, config_inputs)
 
 __all__ = [
     "molecular_integrals", "jordan_wigner_terms", "PauliTerms", "hamiltonian",
-    "init_params", "param_count", "sector_samples", "unique_with_counts",
+    "init_params", "param_count", "round_bf16", "sector_samples", "unique_with_counts",
     "CONFIGS", "config_inputs",
 ]

@@ -3,7 +3,10 @@
 The parameter layout is the library's flat FP32 layout: for each hidden layer
 l = 1..L the weight W_l (row-major [h][in_l], in_1 = n, else h) then its bias
 b_l [h]; then the conditional head W_o [n][h], b_o [n]; then the phase head
-W_phi [4][h], b_phi [4].  All entries are drawn i.i.d. N(0, 0.1^2) in float32.
+W_phi [4][h], b_phi [4].  All entries are drawn i.i.d. N(0, 0.1^2) in float32;
+for the workloads whose network is BF16, every entry is then rounded to the
+nearest BF16 value (the parameters of that network are BF16 values, held in
+float32 storage).
 
 Samples are bit strings packed into uint64 (bit j = qubit j), drawn uniformly
 from the (n_up, n_dn) spin sector: up electrons on even qubits, down electrons
@@ -37,9 +40,22 @@ def param_count(n: int, n_layers: int, width: int) -> int:
     return total
 
 
-def init_params(n: int, n_layers: int, width: int, seed: int = 1, std: float = 0.1):
+def round_bf16(a):
+    """Nearest BF16 values (ties to even) of a float32 array, as float32."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def init_params(n: int, n_layers: int, width: int, seed: int = 1, std: float = 0.1, dtype: str = "fp32"):
+    """N(0, std^2) parameters in float32; dtype "bf16" rounds them to BF16 values."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    return (std * rng.standard_normal(param_count(n, n_layers, width))).astype(np.float32)
+    p = (std * rng.standard_normal(param_count(n, n_layers, width))).astype(np.float32)
+    if dtype == "bf16":
+        p = round_bf16(p)
+    elif dtype != "fp32":
+        raise ValueError(f"unknown parameter dtype {dtype}")
+    return p
 
 
 def sector_samples(n: int, n_up: int, n_dn: int, count: int, seed: int = 2):
@@ -65,24 +81,25 @@ def unique_with_counts(samples):
 
 
 # The five workloads: spatial orbitals N (n = 2N qubits, half filling),
-# integral seed, batch, hidden layers L, width h, arithmetic of the path.
+# integral seed, batch, hidden layers L, width h, arithmetic of the path,
+# parameter values (FP32, or BF16 for the BF16 networks).
 CONFIGS = {
     "c1": dict(N=6, seed=0, B=1024, L=1, h=64, precision="fp64", dedup=True,
-               weights="ones"),
+               weights="ones", params="fp32"),
     "c2": dict(N=12, seed=0, B=8192, L=2, h=256, precision="fp32", dedup=False,
-               weights="counts"),
-    "c3": dict(N=20, seed=0, B=32768, L=3, h=512, precision="bf16", dedup=True,
-               weights="counts"),
-    "c4": dict(N=30, seed=0, B=65536, L=4, h=1024, precision="bf16x3", dedup=False,
-               weights="counts"),
-    "c5a": dict(N=8, seed=1, B=4096, L=3, h=512, precision="bf16x3", dedup=True,
-                weights="counts"),
-    "c5b": dict(N=14, seed=2, B=16384, L=3, h=512, precision="bf16x3", dedup=False,
-                weights="counts"),
-    "c5c": dict(N=22, seed=3, B=32768, L=3, h=512, precision="bf16x3", dedup=False,
-                weights="counts"),
-    "c5d": dict(N=32, seed=4, B=16384, L=3, h=512, precision="bf16x3", dedup=False,
-                weights="counts"),
+               weights="counts", params="fp32"),
+    "c3": dict(N=20, seed=0, B=32768, L=3, h=512, precision="bf16w", dedup=True,
+               weights="counts", params="bf16"),
+    "c4": dict(N=30, seed=0, B=65536, L=4, h=1024, precision="bf16w", dedup=False,
+               weights="counts", params="bf16"),
+    "c5a": dict(N=8, seed=1, B=4096, L=3, h=512, precision="bf16w", dedup=True,
+                weights="counts", params="bf16"),
+    "c5b": dict(N=14, seed=2, B=16384, L=3, h=512, precision="bf16w", dedup=False,
+                weights="counts", params="bf16"),
+    "c5c": dict(N=22, seed=3, B=32768, L=3, h=512, precision="bf16w", dedup=False,
+                weights="counts", params="bf16"),
+    "c5d": dict(N=32, seed=4, B=16384, L=3, h=512, precision="bf16w", dedup=False,
+                weights="counts", params="bf16"),
 }
 
 
@@ -93,7 +110,7 @@ def config_inputs(name: str, batch: int = None, sample_seed: int = 2, param_seed
     n = 2 * N
     ham = hamiltonian(N, cfg["seed"])
     B = cfg["B"] if batch is None else int(batch)
-    params = init_params(n, cfg["L"], cfg["h"], seed=param_seed)
+    params = init_params(n, cfg["L"], cfg["h"], seed=param_seed, dtype=cfg["params"])
     raw = sector_samples(n, N // 2, N // 2, B, seed=sample_seed)
     if cfg["weights"] == "counts":
         samples, weights = unique_with_counts(raw)

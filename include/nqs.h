@@ -141,7 +141,19 @@ void       nqs_ham_destroy(nqs_ham* ham);
  * b_p, weights row-major [out][in] (in_1 = n).  Gradients use the same
  * layout in FP64; masked-out weights receive 0.
  */
-enum { NQS_FP64 = 0, NQS_FP32 = 1, NQS_BF16 = 2, NQS_BF16X3 = 3 };
+/* Arithmetic of the network on the connected configurations:
+ *   NQS_FP64   FP64 MFMA;  NQS_FP32  FP32 MFMA;
+ *   NQS_BF16   BF16 weights and activations, FP32 accumulation;
+ *   NQS_BF16X3 FP32 weights and activations each split into two BF16 terms
+ *              (hi + lo), three BF16 products per multiply-add (lo*lo
+ *              dropped), FP32 accumulation;
+ *   NQS_BF16W  a BF16 network: every weight is the parameter rounded to the
+ *              nearest BF16 (ties to even) when packed, for the forward and
+ *              the backward alike, so the gradient is that network's;
+ *              biases stay FP32; activations are split into two BF16 terms
+ *              (two BF16 products per multiply-add), FP32 accumulation.
+ *              With BF16-valued parameters the rounding is the identity. */
+enum { NQS_FP64 = 0, NQS_FP32 = 1, NQS_BF16 = 2, NQS_BF16X3 = 3, NQS_BF16W = 4 };
 
 typedef struct {
   int            n_qubits;   /* 2..64 */
@@ -149,17 +161,18 @@ typedef struct {
   int            width;      /* 64, 128, 256, 512 or 1024 (precision dependent) */
   const int32_t* order;      /* host [n_qubits] sampling order, NULL = n-1, ..., 0 */
   int            n_up, n_dn; /* electrons per spin; both -1 = unconstrained */
-  int            precision;  /* NQS_FP64 | NQS_FP32 | NQS_BF16 | NQS_BF16X3:
-                                arithmetic of the network GEMMs on connected
-                                configurations (FP32 accumulation for BF16 kinds);
-                                Hamiltonian sums, ratios and reductions are FP64 */
+  int            precision;  /* NQS_FP64 | NQS_FP32 | NQS_BF16 | NQS_BF16X3 | NQS_BF16W
+                                (above); Hamiltonian sums, ratios and reductions
+                                are FP64 in every case */
 } nqs_net_desc;
 
 nqs_status nqs_net_param_count(const nqs_net_desc* net, int64_t* n_params);
 
 /* --------------------------------------------------------------------- plan */
 #define NQS_PLAN_DEDUP_ON   1u   /* deduplicate connected configurations per chunk */
-#define NQS_PLAN_DEDUP_OFF  2u   /* never deduplicate (default when neither is set) */
+#define NQS_PLAN_DEDUP_OFF  2u   /* never deduplicate (default when no flag is set) */
+#define NQS_PLAN_DEDUP_AUTO 4u   /* size the workspace for dedup, start with it on and
+                                    let nqs_plan_autotune decide */
 
 typedef struct nqs_plan nqs_plan;
 /* Fixes the chunking (chunk_samples samples per chunk; <= 0 picks a default
@@ -174,6 +187,49 @@ nqs_status nqs_plan_workspace_size(const nqs_plan* plan, int64_t batch, size_t* 
 nqs_status nqs_plan_info(const nqs_plan* plan, int64_t* entries_per_sample,
                          int64_t* chunk_samples, int* dedup, int64_t* n_params);
 void       nqs_plan_destroy(nqs_plan* plan);
+
+/* Sets what the autotuner chooses: waves per workgroup of the forward (one
+   of the values nqs_plan_autotune reports; <= 0 keeps the current one),
+   dedup (1 on, 0 off, < 0 keep; on needs a plan created with DEDUP_ON or
+   DEDUP_AUTO) and the chunk (between half the created chunk and the created
+   chunk; <= 0 keeps).  Host only. */
+nqs_status nqs_plan_configure(nqs_plan* plan, int waves_per_block, int dedup, int64_t chunk_samples);
+
+/* Workgroup shape of the plan's connected-configuration forward: waves per
+   workgroup, configurations per workgroup, and whether the plan was tuned. */
+nqs_status nqs_plan_kernel_info(const nqs_plan* plan, int* waves_per_block, int* rows_per_block,
+                                int* tuned);
+
+/* Autotuner for the chunked local-energy path (the paper's mini-batches,
+   Sec. 5.2 and Sec. 6): times the local-energy phase on the first
+   min(B, 2 * chunk) samples of d_samples for every candidate
+     forward variant (waves per workgroup) x dedup on/off (only with
+     NQS_PLAN_DEDUP_AUTO) x chunk in {plan chunk, plan chunk / 2}
+   and keeps the fastest in the plan.  The choice is cached per process,
+   keyed by the network shape, the Hamiltonian's term and group counts and
+   the plan's chunk; a later call with the same key applies it without timing
+   (NQS_TUNE_FORCE re-times).  Every candidate computes the same local
+   energies up to the forward's rounding (dedup and chunking change nothing;
+   the two variants split the head's k sum differently).  Synchronises the
+   context's stream; not for use under graph capture.  d_ws must hold
+   nqs_plan_workspace_size(plan, B) bytes.  report may be NULL. */
+#define NQS_TUNE_FORCE 1u
+#define NQS_TUNE_MAX_CANDIDATES 16
+typedef struct {
+  int     waves_per_block;
+  int     dedup;
+  int64_t chunk_samples;
+  double  ms;              /* one local-energy pass over the probe samples */
+} nqs_tune_candidate;
+typedef struct {
+  int     n_candidates;
+  int     chosen;          /* index into cand */
+  int     from_cache;      /* 1: applied from the cache, cand[0] is the cached choice */
+  int64_t probe_samples;
+  nqs_tune_candidate cand[NQS_TUNE_MAX_CANDIDATES];
+} nqs_tune_report;
+nqs_status nqs_plan_autotune(nqs_plan* plan, const float* d_params, const uint64_t* d_samples, int64_t B,
+                             void* d_ws, size_t ws_bytes, uint32_t flags, nqs_tune_report* report);
 
 /* ---------------------------------------------------------------- hot path
  * All pointers are device pointers; d_ws is a workspace of at least
@@ -200,10 +256,16 @@ nqs_status nqs_energy_grad(nqs_plan* plan, const float* d_params, const uint64_t
                            const double* d_weights, int64_t B, double* d_eloc,
                            double* d_energy, double* d_grad, void* d_ws, size_t ws_bytes);
 
-/* Several independent (Hamiltonian, network, samples) instances in one call.
-   Each instance uses its own plan (all plans on the same context); the
-   workspace must hold the largest instance's requirement.  Instances are
-   processed largest first. */
+/* Several independent (Hamiltonian, network, samples) instances in one call
+   (the paper's independent units of work, Sec. 5.2).  Each instance uses
+   its own plan (all plans on the same context) and its own part of d_ws,
+   which must hold nqs_multi_workspace_size bytes.  The sample forwards of
+   all instances are one work list, and so are the connected-configuration
+   forwards of each chunk round (round r holds chunk r of every instance that
+   has one): one forward launch per round and per group of at most 8
+   instances with equal precision, width and forward variant.  Enumeration,
+   ratio-and-reduce, energy and gradient run per instance.  Each instance's
+   results equal those of nqs_energy_grad on it alone. */
 typedef struct {
   nqs_plan*       plan;
   const float*    d_params;
@@ -214,6 +276,7 @@ typedef struct {
   double*         d_energy;  /* [3] */
   double*         d_grad;    /* [n_params] */
 } nqs_instance;
+nqs_status nqs_multi_workspace_size(int n_inst, const nqs_instance* inst, size_t* bytes);
 nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* d_ws, size_t ws_bytes);
 
 /* ------------------------------------------------------ test / table path
@@ -263,7 +326,8 @@ typedef struct {
   double  forward_rows;     /* configurations evaluated by those launches     */
   double  forward_flops;    /* forward_rows * 2 * (unmasked weights per row)  */
   double  forward_flops_executed;  /* forward_rows * MFMA flops issued per row
-                                      (masked tiles skipped, padding included) */
+                                      (masked tiles skipped, padding included;
+                                      NQS_BF16X3 counts each of its BF16 MFMAs) */
 } nqs_profile;
 nqs_status nqs_plan_profile(nqs_plan* plan, int enable);
 nqs_status nqs_plan_profile_read(nqs_plan* plan, void* d_ws, nqs_profile* out);

@@ -12,10 +12,13 @@ STATUS_NAMES = {0: "NQS_OK", 1: "NQS_ERR_INVALID_ARGUMENT", 2: "NQS_ERR_UNSUPPOR
 NQS_H_CONSERVES_SPIN_SECTORS = 1
 NQS_PLAN_DEDUP_ON = 1
 NQS_PLAN_DEDUP_OFF = 2
+NQS_PLAN_DEDUP_AUTO = 4
+NQS_TUNE_FORCE = 1
+NQS_TUNE_MAX_CANDIDATES = 16
 NQS_DEV_ZERO_AMPLITUDE = 1
 NQS_DEV_ENTRY_OVERFLOW = 2
 NQS_DEV_HASH_OVERFLOW = 4
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "bf16w": 4}
 
 
 class PauliTerms(C.Structure):
@@ -35,6 +38,16 @@ class Profile(C.Structure):
     _fields_ = [("calls", C.c_int64), ("forward_launches", C.c_int64), ("call_ms", C.c_double),
                 ("eloc_ms", C.c_double), ("forward_ms", C.c_double), ("forward_rows", C.c_double),
                 ("forward_flops", C.c_double), ("forward_flops_executed", C.c_double)]
+
+
+class TuneCandidate(C.Structure):
+    _fields_ = [("waves_per_block", C.c_int), ("dedup", C.c_int), ("chunk_samples", C.c_int64),
+                ("ms", C.c_double)]
+
+
+class TuneReport(C.Structure):
+    _fields_ = [("n_candidates", C.c_int), ("chosen", C.c_int), ("from_cache", C.c_int),
+                ("probe_samples", C.c_int64), ("cand", TuneCandidate * NQS_TUNE_MAX_CANDIDATES)]
 
 
 class Instance(C.Structure):
@@ -65,9 +78,13 @@ SIGNATURES = {
     "nqs_plan_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(C.c_int),
                                 C.POINTER(_I64)]),
     "nqs_plan_destroy": (None, [_P]),
+    "nqs_plan_configure": (C.c_int, [_P, C.c_int, C.c_int, _I64]),
+    "nqs_plan_kernel_info": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "nqs_plan_autotune": (C.c_int, [_P, _P, _P, _I64, _P, _SZ, C.c_uint32, C.POINTER(TuneReport)]),
     "nqs_log_psi": (C.c_int, [_P, _P, _P, _I64, _P, _P, _SZ]),
     "nqs_local_energy": (C.c_int, [_P, _P, _P, _I64, _P, _P, _SZ]),
     "nqs_energy_grad": (C.c_int, [_P, _P, _P, _P, _I64, _P, _P, _P, _P, _SZ]),
+    "nqs_multi_workspace_size": (C.c_int, [C.c_int, C.POINTER(Instance), C.POINTER(_SZ)]),
     "nqs_energy_grad_multi": (C.c_int, [C.c_int, C.POINTER(Instance), _P, _SZ]),
     "nqs_connected": (C.c_int, [_P, _P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ]),
     "nqs_reduce_table": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _I64, _P, _P, _SZ]),

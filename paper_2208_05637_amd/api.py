@@ -124,22 +124,59 @@ class Plan:
 
     def __init__(self, ctx, ham, n_layers, width, n_up=-1, n_dn=-1, precision="fp32",
                  max_batch=1024, dedup=False, chunk_samples=0, order=None):
+        """dedup: True, False or "auto" (the autotuner decides)."""
         self.lib = L.load()
         self.ctx, self.ham = ctx, ham
         self.precision = precision
         d, self._order = net_desc(ham.n, n_layers, width, n_up, n_dn, precision, order)
-        flags = L.NQS_PLAN_DEDUP_ON if dedup else L.NQS_PLAN_DEDUP_OFF
+        if dedup == "auto":
+            flags = L.NQS_PLAN_DEDUP_AUTO
+        else:
+            flags = L.NQS_PLAN_DEDUP_ON if dedup else L.NQS_PLAN_DEDUP_OFF
         h = C.c_void_p()
         L.check(self.lib.nqs_plan_create(ctx.handle, ham.handle, C.byref(d), int(max_batch), flags,
                                          int(chunk_samples), C.byref(h)), "nqs_plan_create")
         self.handle = h
+        self.max_batch = int(max_batch)
+        self._ws = None
+        self._refresh()
+
+    def _refresh(self):
         e, cs, dd, npar = C.c_int64(), C.c_int64(), C.c_int(), C.c_int64()
-        L.check(self.lib.nqs_plan_info(h, C.byref(e), C.byref(cs), C.byref(dd), C.byref(npar)),
+        L.check(self.lib.nqs_plan_info(self.handle, C.byref(e), C.byref(cs), C.byref(dd), C.byref(npar)),
                 "nqs_plan_info")
         self.entries_per_sample, self.chunk_samples = e.value, cs.value
         self.dedup, self.n_params = bool(dd.value), npar.value
-        self.max_batch = int(max_batch)
-        self._ws = None
+
+    def configure(self, waves_per_block=0, dedup=None, chunk_samples=0):
+        """Set the forward variant (by waves per workgroup), dedup and chunk by hand."""
+        d = -1 if dedup is None else (1 if dedup else 0)
+        L.check(self.lib.nqs_plan_configure(self.handle, int(waves_per_block), d, int(chunk_samples)),
+                "nqs_plan_configure")
+        self._refresh()
+
+    def kernel_info(self):
+        """(waves per workgroup, configurations per workgroup, tuned) of the forward."""
+        w, r, t = C.c_int(), C.c_int(), C.c_int()
+        L.check(self.lib.nqs_plan_kernel_info(self.handle, C.byref(w), C.byref(r), C.byref(t)),
+                "nqs_plan_kernel_info")
+        return dict(waves_per_block=w.value, rows_per_block=r.value, tuned=bool(t.value))
+
+    def autotune(self, params, samples, force=False):
+        """Time the candidate kernel variants / dedup / chunk sizes on a prefix of
+        the samples and keep the fastest; returns the timings."""
+        params = _params(self, params)
+        x = _as_u64_tensor(samples, self.ctx.device)
+        rep = L.TuneReport()
+        ws, nb = self.workspace()
+        L.check(self.lib.nqs_plan_autotune(self.handle, _ptr(params), _ptr(x), x.numel(), ws, nb,
+                                           L.NQS_TUNE_FORCE if force else 0, C.byref(rep)),
+                "nqs_plan_autotune")
+        self._refresh()
+        cands = [dict(waves_per_block=c.waves_per_block, dedup=bool(c.dedup), chunk_samples=c.chunk_samples,
+                      ms=c.ms) for c in rep.cand[:rep.n_candidates]]
+        return dict(candidates=cands, chosen=rep.chosen, from_cache=bool(rep.from_cache),
+                    probe_samples=rep.probe_samples)
 
     def workspace_size(self, B):
         out = C.c_size_t()
@@ -216,8 +253,7 @@ def energy_grad(plan, params, samples, weights=None, eloc=None, energy=None, gra
     return energy, grad, eloc
 
 
-def energy_grad_multi(items, workspace):
-    """items: list of dicts with plan, params, samples, weights, eloc, energy, grad tensors."""
+def _instances(items):
     arr = (L.Instance * len(items))()
     for i, it in enumerate(items):
         arr[i] = L.Instance(it["plan"].handle.value, it["params"].data_ptr(), it["samples"].data_ptr(),
@@ -225,9 +261,26 @@ def energy_grad_multi(items, workspace):
                             it["samples"].numel(),
                             it["eloc"].data_ptr() if it.get("eloc") is not None else None,
                             it["energy"].data_ptr(), it["grad"].data_ptr())
-    ws, nb = workspace
+    return arr
+
+
+def multi_workspace(items):
+    """A device workspace for energy_grad_multi over items: (raw tensor, pointer, bytes)."""
     lib = L.load()
-    L.check(lib.nqs_energy_grad_multi(len(items), arr, ws, nb), "nqs_energy_grad_multi")
+    need = C.c_size_t()
+    L.check(lib.nqs_multi_workspace_size(len(items), _instances(items), C.byref(need)), "nqs_multi_workspace_size")
+    raw = torch.empty(need.value + 256, dtype=torch.uint8, device=items[0]["plan"].ctx.device)
+    return raw, C.c_void_p((raw.data_ptr() + 255) & ~255), need.value
+
+
+def energy_grad_multi(items, workspace=None):
+    """items: list of dicts with plan, params, samples, weights, eloc, energy, grad tensors.
+    workspace: as returned by multi_workspace (allocated here when None)."""
+    if workspace is None:
+        workspace = multi_workspace(items)
+    _, ws, nb = workspace
+    lib = L.load()
+    L.check(lib.nqs_energy_grad_multi(len(items), _instances(items), ws, nb), "nqs_energy_grad_multi")
 
 
 def connected(plan, samples, capacity=None):

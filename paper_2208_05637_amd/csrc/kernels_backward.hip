@@ -59,13 +59,22 @@ __device__ __forceinline__ void locate(const Geom& g, long long p, int& tensor, 
   }
 }
 
+__device__ __forceinline__ unsigned short rne_bf16(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+// With BF16 weights (P_BF16W) the network's weights are the parameters
+// rounded to BF16; the backward differentiates that network.
 template <typename T>
 __global__ void pack_masked_kernel(Geom g, const float* __restrict__ params, T* __restrict__ wm) {
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= g.n_params) return;
   int tensor, kind, row, col, in;
   locate(g, p, tensor, kind, row, col, in);
-  const float v = params[p];
+  float v = params[p];
+  if (kind >= 0 && g.prec == P_BF16W) v = __uint_as_float(((unsigned)rne_bf16(v)) << 16);
   wm[p] = (kind < 0 || mask_at(g, kind, row, col)) ? (T)v : (T)0;
 }
 
@@ -104,12 +113,6 @@ __device__ float packed_value(const Geom& g, const float* params, int part, int 
   return params[g.poff[2 * g.L + 2] + (long long)(row - n) * h + orig_of_sorted(g, k)];
 }
 
-__device__ __forceinline__ unsigned short rne_bf16(float f) {
-  unsigned u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-
 __global__ void pack_fused_kernel(Geom g, const float* __restrict__ params, uint4* __restrict__ out) {
   const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long f = tid >> 6;
@@ -139,7 +142,7 @@ __global__ void pack_fused_kernel(Geom g, const float* __restrict__ params, uint
     ks = (int)(local - g.offo[blk]);
   }
   uint4 hi = make_uint4(0, 0, 0, 0), lo = make_uint4(0, 0, 0, 0);
-  if (g.prec == P_BF16 || g.prec == P_BF16X3) {
+  if (g.prec == P_BF16 || g.prec == P_BF16X3 || g.prec == P_BF16W) {
     const int row = 32 * blk + (lane & 31);
     const int k0 = 16 * ks + 8 * (lane >> 5);
     unsigned short vh[8], vl[8];

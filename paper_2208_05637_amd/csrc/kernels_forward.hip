@@ -1,6 +1,6 @@
 // Fused masked-MLP forward on MFMA: x (uint64 bit string) -> (log|psi|, phi).
 //
-// One workgroup (8 waves) owns a tile of M configurations and carries them
+// One workgroup (8 or 16 waves) owns a tile of M configurations and carries them
 // through every layer of the network of Sec. 4 without leaving the CU:
 //   * prologue: the configuration bits are permuted into sampling order and
 //     the +-1 input fragments of the first layer are generated in registers
@@ -15,6 +15,14 @@
 //   * the head produces the n conditional logits and the 4 phases; the
 //     per-row epilogue applies the Hamming-weight modifier (Eq. modifier),
 //     sums the log-sigmoids of free positions in FP64 and selects the phase.
+// Arithmetic kinds: FP64 and FP32 MFMA; plain BF16; split BF16 (weights and
+// activations as hi + lo BF16 planes, three products); BF16 weights with
+// hi + lo activations (two products).  With two activation planes a tile
+// holds half the rows of plain BF16, so every weight byte streamed from L2
+// serves half as many rows: the BF16-weight kind streams one weight plane,
+// split BF16 two.
+#include <algorithm>
+
 #include "nqs_internal.h"
 
 namespace nqs {
@@ -24,23 +32,29 @@ typedef __attribute__((ext_vector_type(16))) float f32x16;
 typedef __attribute__((ext_vector_type(4))) double f64x4;
 
 template <int P> struct Tr;
+// PL: planes of the activation operand, PLW: planes of the weight operand.
 template <> struct Tr<P_BF16> {
-  static constexpr int TB = 32, KSTEP = 16, PL = 1, MH = 65536;
+  static constexpr int TB = 32, KSTEP = 16, PL = 1, PLW = 1, MH = 65536;
   using Acc = f32x16; using S = float;
   static constexpr int NACC = 16;
 };
 template <> struct Tr<P_BF16X3> {
-  static constexpr int TB = 32, KSTEP = 16, PL = 2, MH = 32768;
+  static constexpr int TB = 32, KSTEP = 16, PL = 2, PLW = 2, MH = 32768;
+  using Acc = f32x16; using S = float;
+  static constexpr int NACC = 16;
+};
+template <> struct Tr<P_BF16W> {
+  static constexpr int TB = 32, KSTEP = 16, PL = 2, PLW = 1, MH = 32768;
   using Acc = f32x16; using S = float;
   static constexpr int NACC = 16;
 };
 template <> struct Tr<P_F32> {
-  static constexpr int TB = 32, KSTEP = 8, PL = 1, MH = 32768;
+  static constexpr int TB = 32, KSTEP = 8, PL = 1, PLW = 1, MH = 32768;
   using Acc = f32x16; using S = float;
   static constexpr int NACC = 16;
 };
 template <> struct Tr<P_F64> {
-  static constexpr int TB = 16, KSTEP = 8, PL = 1, MH = 16384;
+  static constexpr int TB = 16, KSTEP = 8, PL = 1, PLW = 1, MH = 16384;
   using Acc = f64x4; using S = double;
   static constexpr int NACC = 4;
 };
@@ -52,22 +66,26 @@ constexpr int rows_per_block() {
   return (P == P_F64 && H < 256) ? 8192 / H : Tr<P>::MH / H;
 }
 
-// Waves per workgroup: 16 (four per SIMD) for the wide BF16 nets, so that
-// every SIMD keeps two or more waves in flight until the end of each layer;
-// 8 elsewhere.
+// Waves per workgroup of variant 0: 16 (four per SIMD) for the wide BF16
+// nets, so that every SIMD keeps two or more waves in flight until the end of
+// each layer; 8 elsewhere.  Variant 1 (BF16, split BF16, FP32) takes the other
+// count; the autotuner chooses between them.
 template <int P, int H>
-constexpr int waves_per_block() {
-  return ((P == P_BF16 || P == P_BF16X3) && H >= 512) ? 16 : 8;
+constexpr int default_waves() {
+  return ((P == P_BF16 || P == P_BF16X3 || P == P_BF16W) && H >= 512) ? 16 : 8;
+}
+template <int P, int H, int V>
+constexpr int variant_waves() {
+  return V == 0 ? default_waves<P, H>() : (default_waves<P, H>() == 16 ? 8 : 16);
 }
 
 // Head k slices (one LDS staging plane each) when the head has fewer
 // (block, m-block) tiles than waves.
 // At most 4 slices, and no more than the planes that fit in 128 KB.
-template <int P, int H>
+template <int P, int H, int NW>
 constexpr int head_ksplit_max() {
   constexpr int M = rows_per_block<P, H>();
   constexpr int MB = M / Tr<P>::TB;
-  constexpr int NW = waves_per_block<P, H>();
   constexpr int SP = ((68 + Tr<P>::TB - 1) / Tr<P>::TB) * Tr<P>::TB + 1;
   constexpr int fit = (131072 / (M * SP * (int)sizeof(typename Tr<P>::S))) > 0
                           ? 131072 / (M * SP * (int)sizeof(typename Tr<P>::S)) : 1;
@@ -84,7 +102,9 @@ __device__ __forceinline__ float bf16_to_f(unsigned short h) {
   return __uint_as_float(((unsigned)h) << 16);
 }
 
-template <int P>
+// AX: the activation operand is exact in BF16 (its low plane is zero), so the
+// split products need only wl*ah + wh*ah (split BF16) or wh*ah (BF16 weights).
+template <int P, bool AX = false>
 __device__ __forceinline__ void mma(typename Tr<P>::Acc& acc, const uint4* w, const uint4* a) {
   if constexpr (P == P_BF16) {
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, w[0]),
@@ -93,7 +113,13 @@ __device__ __forceinline__ void mma(typename Tr<P>::Acc& acc, const uint4* w, co
     bf16x8 wh = __builtin_bit_cast(bf16x8, w[0]), wl = __builtin_bit_cast(bf16x8, w[1]);
     bf16x8 ah = __builtin_bit_cast(bf16x8, a[0]), al = __builtin_bit_cast(bf16x8, a[1]);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wl, ah, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, al, acc, 0, 0, 0);
+    if constexpr (!AX) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, al, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, ah, acc, 0, 0, 0);
+  } else if constexpr (P == P_BF16W) {
+    // BF16 weights times a two-term BF16 activation
+    bf16x8 wh = __builtin_bit_cast(bf16x8, w[0]);
+    bf16x8 ah = __builtin_bit_cast(bf16x8, a[0]), al = __builtin_bit_cast(bf16x8, a[1]);
+    if constexpr (!AX) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, al, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, ah, acc, 0, 0, 0);
   } else if constexpr (P == P_F32) {
     float4 wf = __builtin_bit_cast(float4, w[0]);
@@ -116,7 +142,7 @@ template <int P>
 __device__ __forceinline__ void input_frag(const uint64_t* ylds, int mb, int ks, int lane, int n,
                                            uint4* out) {
   using T = Tr<P>;
-  if constexpr (P == P_BF16 || P == P_BF16X3) {
+  if constexpr (P == P_BF16 || P == P_BF16X3 || P == P_BF16W) {
     uint64_t y = ylds[mb * 32 + (lane & 31)];
     int k0 = ks * 16 + 8 * (lane >> 5);
     unsigned short v[8];
@@ -230,37 +256,55 @@ __device__ __forceinline__ uint4 wload(const WBuf& b, int soff) {
   return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(b.rsrc, b.voff, soff, 0));
 }
 
-template <int P, int NBW, int MBW, int I0, class ActFn>
+// With PF, activation fragments are double-buffered too: the fragments of
+// step k+1 are requested before the MFMAs of step k, so the LDS latency is
+// covered by those MFMAs; afa holds step ks on entry (and on exit).  Without
+// PF (shapes whose registers would not hold the second buffer) each step
+// reads its fragments right before its MFMAs.
+template <int P, int NBW, int MBW, int I0, bool AX, bool PF, class ActFn>
 __device__ __forceinline__ void kphase(typename Tr<P>::Acc (&acc)[NBW][MBW], const WBuf& wb_,
                                        const int (&wbase)[NBW], const int (&kend)[NBW], int ks,
-                                       uint4 (&wa)[NBW][Tr<P>::PL], uint4 (&wb)[NBW][Tr<P>::PL],
+                                       uint4 (&wa)[NBW][Tr<P>::PLW], uint4 (&wb)[NBW][Tr<P>::PLW],
+                                       uint4 (&afa)[MBW][Tr<P>::PL], uint4 (&afb)[MBW][Tr<P>::PL],
                                        ActFn& act) {
-  constexpr int PL = Tr<P>::PL;
-  auto loadw = [&](uint4 (&w)[NBW][PL], int k) {
+  constexpr int PL = Tr<P>::PL, PLW = Tr<P>::PLW;
+  auto loadw = [&](uint4 (&w)[NBW][PLW], int k) {
 #pragma unroll
     for (int i = I0; i < NBW; ++i) {
       const int kc = max(0, k < kend[i] ? k : kend[i] - 1);   // clamped into the block
       const int so = wbase[i] + kc * 1024;
       w[i][0] = wload(wb_, so);
-      if constexpr (PL == 2) w[i][1] = wload(wb_, so + wb_.plane_bytes);
+      if constexpr (PLW == 2) w[i][1] = wload(wb_, so + wb_.plane_bytes);
     }
   };
-  auto step = [&](uint4 (&w)[NBW][PL], int k) {
-    uint4 af[MBW][PL];
+  // the last block's extent bounds every k this wave reads
+  const int klast = kend[NBW - 1] - 1;
+  auto rd = [&](uint4 (&af)[MBW][PL], int k) {
+    const int kc = k < klast ? k : klast;
 #pragma unroll
-    for (int j = 0; j < MBW; ++j) act(j, k, af[j]);
+    for (int j = 0; j < MBW; ++j) act(j, kc, af[j]);
+  };
+  auto mm = [&](uint4 (&w)[NBW][PLW], uint4 (&af)[MBW][PL]) {
 #pragma unroll
     for (int i = I0; i < NBW; ++i)
 #pragma unroll
-      for (int j = 0; j < MBW; ++j) mma<P>(acc[i][j], w[i], af[j]);
+      for (int j = 0; j < MBW; ++j) mma<P, AX>(acc[i][j], w[i], af[j]);
   };
   const int stop = kend[I0];
   auto body = [&]() {
-    step(wa, ks);
+    if constexpr (PF) rd(afb, ks + 1);
+    else rd(afa, ks);
+    mm(wa, afa);
     __builtin_amdgcn_sched_barrier(0);
     loadw(wa, ks + 2);
     __builtin_amdgcn_sched_barrier(0);
-    step(wb, ks + 1);
+    if constexpr (PF) {
+      rd(afa, ks + 2);
+      mm(wb, afb);
+    } else {
+      rd(afa, ks + 1);
+      mm(wb, afa);
+    }
     __builtin_amdgcn_sched_barrier(0);
     loadw(wb, ks + 3);
     __builtin_amdgcn_sched_barrier(0);
@@ -273,15 +317,25 @@ __device__ __forceinline__ void kphase(typename Tr<P>::Acc (&acc)[NBW][MBW], con
   } else {
     while (ks < stop) body();
   }
-  if constexpr (I0 + 1 < NBW) kphase<P, NBW, MBW, I0 + 1>(acc, wb_, wbase, kend, ks, wa, wb, act);
+  if constexpr (I0 + 1 < NBW) kphase<P, NBW, MBW, I0 + 1, AX, PF>(acc, wb_, wbase, kend, ks, wa, wb, afa, afb, act);
 }
 
-template <int P, int NBW, int MBW, class ActFn>
+// Whether the second activation buffer fits the register budget of a wave
+// (128 VGPRs at 16 waves per workgroup, 256 at 8): accumulators, two weight
+// buffers, two activation buffers and addressing.
+template <int P, int NBW, int MBW, int NW>
+constexpr bool act_prefetch() {
+  constexpr int acc = P == P_F64 ? 8 : 16;
+  constexpr int PL = Tr<P>::PL, PLW = Tr<P>::PLW;
+  return acc * NBW * MBW + 8 * PLW * NBW + 8 * PL * MBW + 40 + 4 * MBW <= 2048 / NW;
+}
+
+template <int P, int NBW, int MBW, int NW, bool AX, class ActFn>
 __device__ __forceinline__ void kloop(typename Tr<P>::Acc (&acc)[NBW][MBW], const WBuf& wbuf,
                                       const int (&fragi)[NBW], const int (&ksi)[NBW], int ks0,
                                       ActFn act) {
-  constexpr int PL = Tr<P>::PL;
-  uint4 wa[NBW][PL], wb[NBW][PL];
+  constexpr int PL = Tr<P>::PL, PLW = Tr<P>::PLW;
+  uint4 wa[NBW][PLW], wb[NBW][PLW];
   int kend[NBW], wbase[NBW];
 #pragma unroll
   for (int i = 0; i < NBW; ++i) {
@@ -298,16 +352,22 @@ __device__ __forceinline__ void kloop(typename Tr<P>::Acc (&acc)[NBW][MBW], cons
   for (int i = 0; i < NBW; ++i) {
     const int k0 = max(0, ks0 < kend[i] ? ks0 : kend[i] - 1);
     wa[i][0] = wload(wbuf, wbase[i] + k0 * 1024);
-    if constexpr (PL == 2) wa[i][1] = wload(wbuf, wbase[i] + k0 * 1024 + wbuf.plane_bytes);
+    if constexpr (PLW == 2) wa[i][1] = wload(wbuf, wbase[i] + k0 * 1024 + wbuf.plane_bytes);
   }
 #pragma unroll
   for (int i = 0; i < NBW; ++i) {
     const int k1 = max(0, ks0 + 1 < kend[i] ? ks0 + 1 : kend[i] - 1);
     wb[i][0] = wload(wbuf, wbase[i] + k1 * 1024);
-    if constexpr (PL == 2) wb[i][1] = wload(wbuf, wbase[i] + k1 * 1024 + wbuf.plane_bytes);
+    if constexpr (PLW == 2) wb[i][1] = wload(wbuf, wbase[i] + k1 * 1024 + wbuf.plane_bytes);
+  }
+  constexpr bool PF = act_prefetch<P, NBW, MBW, NW>();
+  uint4 afa[MBW][PL], afb[MBW][PL];
+  if constexpr (PF) {
+#pragma unroll
+    for (int j = 0; j < MBW; ++j) act(j, ks0, afa[j]);
   }
   __builtin_amdgcn_sched_barrier(0);
-  kphase<P, NBW, MBW, 0>(acc, wbuf, wbase, kend, ks0, wa, wb, act);
+  kphase<P, NBW, MBW, 0, AX, PF>(acc, wbuf, wbase, kend, ks0, wa, wb, afa, afb, act);
 }
 
 // Head k loop for one (block, m-block) tile over [k0, k1) (multiples of 8):
@@ -316,17 +376,17 @@ __device__ __forceinline__ void kloop(typename Tr<P>::Acc (&acc)[NBW][MBW], cons
 template <int P, class ActFn>
 __device__ __forceinline__ void head_loop(typename Tr<P>::Acc& acc, const WBuf& wbuf, int frag0,
                                           int k0, int k1, ActFn act) {
-  constexpr int PL = Tr<P>::PL;
+  constexpr int PL = Tr<P>::PL, PLW = Tr<P>::PLW;
   constexpr int D = 8;
   const int base = __builtin_amdgcn_readfirstlane(frag0 * 1024);
   k0 = __builtin_amdgcn_readfirstlane(k0);
   k1 = __builtin_amdgcn_readfirstlane(k1);
   for (int k = k0; k < k1; k += D) {
-    uint4 w[D][PL];
+    uint4 w[D][PLW];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       w[d][0] = wload(wbuf, base + (k + d) * 1024);
-      if constexpr (PL == 2) w[d][1] = wload(wbuf, base + (k + d) * 1024 + wbuf.plane_bytes);
+      if constexpr (PLW == 2) w[d][1] = wload(wbuf, base + (k + d) * 1024 + wbuf.plane_bytes);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -347,45 +407,56 @@ __device__ __forceinline__ S softplus(S z) {
   else return m + log1p(exp(-a));
 }
 
-template <int P, int H>
-__global__ __launch_bounds__((64 * waves_per_block<P, H>())) void fused_forward(
-    Geom g, const uint4* __restrict__ wpk, const uint64_t* __restrict__ xs, long long rows_bound,
-    const long long* __restrict__ d_count, double2* __restrict__ out, long long* __restrict__ prof_slot) {
+// Shape constants of one (precision, width, waves) instance of the kernel.
+template <int P, int H, int NW_>
+struct Shape {
+  using T = Tr<P>;
+  using S = typename T::S;
+  static constexpr int NW = NW_, NT = 64 * NW;
+  static constexpr int TB = T::TB, PL = T::PL;
+  static constexpr int M = rows_per_block<P, H>();
+  static constexpr int NB = H / TB, MB = M / TB;
+  static constexpr int WN = NB < NW ? NB : NW, WM = NW / WN;
+  static constexpr int NBW = NB / WN, MBW = MB / WM;
+  static constexpr int KSH = H / T::KSTEP;
+  static constexpr int NHBMAX = (68 + TB - 1) / TB;
+  static constexpr int HP = (NHBMAX * MB + NW - 1) / NW;
+  static constexpr int SP = NHBMAX * TB + 1;
+  static constexpr int KSPLIT_MAX = head_ksplit_max<P, H, NW>();
+  static constexpr long ACT_BYTES = (long)PL * KSH * MB * 1024;
+  static constexpr long STAGE_BYTES = (long)M * SP * sizeof(S) * KSPLIT_MAX;
+  static constexpr long REGION = ACT_BYTES > STAGE_BYTES ? ACT_BYTES : STAGE_BYTES;
+  // LDS: activations / head staging, then the tile's bit strings, then the
+  // bias being applied
+  static constexpr long Y_OFF = REGION;
+  static constexpr long B_OFF = Y_OFF + (long)M * 8;
+  static constexpr long LDS = B_OFF + (long)(H + NHBMAX * TB) * sizeof(S);
+  static_assert(MB % WM == 0 && NB % WN == 0 && MB >= 1, "tile shape");
+  static_assert(LDS <= 160 * 1024, "LDS budget");
+};
+
+// Rows [row0, row0 + M) of one batch through the whole network; rows at or
+// beyond count are computed on a copy of row0 and not written.
+template <int P, int H, int NW>
+__device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict__ wpk,
+                                         const uint64_t* __restrict__ xs, long long row0, long long count,
+                                         double2* __restrict__ out, char* act) {
+  using Sh = Shape<P, H, NW>;
   using T = Tr<P>;
   using Acc = typename T::Acc;
   using S = typename T::S;
-  constexpr int TB = T::TB, PL = T::PL, NACC = T::NACC;
-  constexpr int NW = waves_per_block<P, H>(), NT = 64 * NW;
-  constexpr int M = rows_per_block<P, H>();
-  constexpr int NB = H / TB, MB = M / TB;
-  constexpr int WN = NB < NW ? NB : NW, WM = NW / WN;
-  constexpr int NBW = NB / WN, MBW = MB / WM;
-  constexpr int KSH = H / T::KSTEP;
-  constexpr int NHBMAX = (68 + TB - 1) / TB;
-  constexpr int HP = (NHBMAX * MB + NW - 1) / NW;
-  constexpr int SP = NHBMAX * TB + 1;
-  static_assert(MB % WM == 0 && NB % WN == 0 && MB >= 1, "tile shape");
-
-  extern __shared__ uint4 smem[];
-  char* act = (char*)smem;
-  constexpr long ACT_BYTES = (long)PL * KSH * MB * 1024;
-  constexpr int KSPLIT_MAX = head_ksplit_max<P, H>();
-  constexpr long STAGE_BYTES = (long)M * SP * sizeof(S) * KSPLIT_MAX;
-  constexpr long REGION = ACT_BYTES > STAGE_BYTES ? ACT_BYTES : STAGE_BYTES;
-  uint64_t* ylds = (uint64_t*)(act + REGION);
+  constexpr int TB = Sh::TB, PL = Sh::PL, NT = Sh::NT, M = Sh::M;
+  constexpr int NB = Sh::NB, MB = Sh::MB, WN = Sh::WN, WM = Sh::WM, NBW = Sh::NBW, MBW = Sh::MBW;
+  constexpr int KSH = Sh::KSH, HP = Sh::HP, SP = Sh::SP, KSPLIT_MAX = Sh::KSPLIT_MAX;
+  uint64_t* ylds = (uint64_t*)(act + Sh::Y_OFF);
+  // bias of the layer being finished (H entries), then of the head
+  S* blds = (S*)(act + Sh::B_OFF);
   S* stage = (S*)act;
+  constexpr int BPT = (H + NT - 1) / NT;   // bias entries staged per thread
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
   const int wn = wave % WN, wm = wave / WN;
-  long long count = rows_bound;
-  if (d_count) {
-    long long c = *d_count;
-    count = c < rows_bound ? c : rows_bound;
-  }
-  if (prof_slot && blockIdx.x == 0 && threadIdx.x == 0) *prof_slot = count;
-  const long long row0 = (long long)blockIdx.x * M;
-  if (row0 >= count) return;
 
   const S* biases = (const S*)((const char*)wpk + g.bias_byte);
   WBuf wbuf;
@@ -394,23 +465,35 @@ __global__ __launch_bounds__((64 * waves_per_block<P, H>())) void fused_forward(
   wbuf.voff = lane * 16;
 
   for (int t = tid; t < M; t += NT) {
-    long long row = row0 + t;
+    const long long row = row0 + t;
     uint64_t x = xs[row < count ? row : row0];
     uint64_t y = 0;
     for (int p = 0; p < g.n; ++p) y |= ((x >> g.order[p]) & 1ull) << p;
     ylds[t] = y;
   }
+  for (int t = tid; t < H; t += NT) blds[t] = biases[t];
   __syncthreads();
 
-  // n-blocks of this wave: a contiguous group (similar masked k extent, so
-  // every block stays active through the k loop); the two waves that share a
-  // SIMD (w and w+4) take complementary groups so every SIMD does equal work.
+  // n-blocks of this wave.  The masked k extent grows with the block index,
+  // so blocks are dealt in mirrored pairs (p, NB-1-p): every wave then runs
+  // the same number of k steps and all waves of a SIMD stay busy until the
+  // end of the layer.  Inside a wave the blocks are listed in ascending
+  // order, the order in which the k loop retires them.  With one block per
+  // wave, the blocks are dealt over the SIMDs in a snake instead (waves s,
+  // s+4, s+8, s+12 share SIMD s), which balances the SIMDs.
   int nbl[NBW], mbl[MBW];
-  // waves s, s+4, s+8, s+12 share SIMD s: deal the groups in a snake over the
-  // SIMDs so each SIMD gets a light and a heavy group per pair of waves
-  const int grp = (WN == NW) ? (((wave >> 2) & 1) ? (wave & ~3) + 3 - (wave & 3) : wave) : wn;
+  if constexpr (NBW % 2 == 0) {
 #pragma unroll
-  for (int i = 0; i < NBW; ++i) nbl[i] = grp * NBW + i;
+    for (int r = 0; r < NBW / 2; ++r) {
+      const int p = wn + WN * r;
+      nbl[r] = p;
+      nbl[NBW - 1 - r] = NB - 1 - p;
+    }
+  } else {
+    const int grp = (WN == NW) ? (((wave >> 2) & 1) ? (wave & ~3) + 3 - (wave & 3) : wave) : wn;
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) nbl[i] = grp * NBW + i;
+  }
 #pragma unroll
   for (int j = 0; j < MBW; ++j) mbl[j] = j * WM + wm;
 
@@ -433,12 +516,13 @@ __global__ __launch_bounds__((64 * waves_per_block<P, H>())) void fused_forward(
       ksi[i] = g.ks1[nbl[i]];
       fragi[i] = g.off1[nbl[i]];
     }
-    kloop<P, NBW, MBW>(acc, wbuf, fragi, ksi, 0,
-                       [&](int j, int ks, uint4 (&f)[PL]) { input_frag<P>(ylds, mbl[j], ks, lane, g.n, f); });
+    // the +-1 inputs are exact in BF16
+    kloop<P, NBW, MBW, Sh::NW, true>(acc, wbuf, fragi, ksi, 0,
+                             [&](int j, int ks, uint4 (&f)[PL]) { input_frag<P>(ylds, mbl[j], ks, lane, g.n, f); });
 #pragma unroll
     for (int i = 0; i < NBW; ++i)
 #pragma unroll
-      for (int j = 0; j < MBW; ++j) store_act<P, MB>(act, acc[i][j], biases, nbl[i], mbl[j], lane, KSH);
+      for (int j = 0; j < MBW; ++j) store_act<P, MB>(act, acc[i][j], blds, nbl[i], mbl[j], lane, KSH);
     __syncthreads();
   }
 
@@ -455,20 +539,30 @@ __global__ __launch_bounds__((64 * waves_per_block<P, H>())) void fused_forward(
       ksi[i] = g.ksh[nbl[i]];
       fragi[i] = lbase + g.offh[nbl[i]];
     }
-    kloop<P, NBW, MBW>(acc, wbuf, fragi, ksi, 0, lds_act);
+    // this layer's bias is requested before the k loop and parked in LDS
+    // after it, so the epilogue reads it without waiting on L2
+    S breg[BPT];
+    const S* bsrc = biases + (long)(l - 1) * H;
+#pragma unroll
+    for (int e = 0; e < BPT; ++e) breg[e] = (tid + e * NT < H) ? bsrc[tid + e * NT] : S(0);
+    kloop<P, NBW, MBW, Sh::NW, false>(acc, wbuf, fragi, ksi, 0, lds_act);
+#pragma unroll
+    for (int e = 0; e < BPT; ++e)
+      if (tid + e * NT < H) blds[tid + e * NT] = breg[e];
     __syncthreads();
-    const S* bl = biases + (long)(l - 1) * H;
 #pragma unroll
     for (int i = 0; i < NBW; ++i)
 #pragma unroll
-      for (int j = 0; j < MBW; ++j) store_act<P, MB>(act, acc[i][j], bl, nbl[i], mbl[j], lane, KSH);
+      for (int j = 0; j < MBW; ++j) store_act<P, MB>(act, acc[i][j], blds, nbl[i], mbl[j], lane, KSH);
     __syncthreads();
   }
 
   // -------------------------------------------------------------------- head
-  // Work items (head n-block, m-block, k slice) are spread over all 8 waves;
-  // k slices of one tile are combined with LDS atomic adds.
+  // Work items (head n-block, m-block, k slice) are spread over all waves;
+  // k slices of one tile are summed from their staging planes in the epilogue.
   Acc hacc[HP];
+  const int nho = g.n + 4;   // head outputs: n conditionals, 4 phases
+  S hbreg = tid < nho ? biases[(long)g.L * H + tid] : S(0);
   const int npairs = g.NHB * MB;
   const int ksplit = npairs >= NW ? 1 : min(KSPLIT_MAX, NW / npairs);
   const int nitems = npairs * ksplit;
@@ -489,6 +583,7 @@ __global__ __launch_bounds__((64 * waves_per_block<P, H>())) void fused_forward(
       });
     }
   }
+  if (tid < nho) blds[tid] = hbreg;
   __syncthreads();
   // each k slice writes its own staging plane; the epilogue adds the planes
   // in a fixed order, so the result does not depend on wave scheduling
@@ -516,7 +611,7 @@ __global__ __launch_bounds__((64 * waves_per_block<P, H>())) void fused_forward(
   constexpr int TPR = NT / M >= 1 ? NT / M : 1;
   const int row = tid / TPR, sub = tid % TPR;
   if (row < M) {
-    const S* hb = biases + (long)g.L * H;
+    const S* hb = blds;
     const uint64_t y = ylds[row];
     const bool constrained = g.n_up >= 0 && g.n_dn >= 0;
     auto head_out = [&](int col) {
@@ -557,35 +652,85 @@ __global__ __launch_bounds__((64 * waves_per_block<P, H>())) void fused_forward(
   }
 }
 
-template <int P, int H>
-static void launch_one(const Geom& g, const void* packed, const uint64_t* x, long long rows_bound,
-                       const long long* d_count, double* out, long long* prof_slot, hipStream_t s) {
-  using T = Tr<P>;
-  constexpr int M = rows_per_block<P, H>();
-  constexpr int KSH = H / T::KSTEP;
-  constexpr int MB = M / T::TB;
-  constexpr int NHBMAX = (68 + T::TB - 1) / T::TB;
-  constexpr int SP = NHBMAX * T::TB + 1;
-  constexpr long ACT = (long)T::PL * KSH * MB * 1024;
-  constexpr long STG = (long)M * SP * sizeof(typename T::S) * head_ksplit_max<P, H>();
-  constexpr size_t LDS = (ACT > STG ? ACT : STG) + M * 8;
-  static_assert(LDS <= 160 * 1024, "LDS budget");
-  auto kern = fused_forward<P, H>;
+template <typename Seg>
+__device__ __forceinline__ long long seg_rows(const Seg& sg) {
+  long long rows = sg.rows_bound;
+  if (sg.d_count) {
+    const long long c = *sg.d_count;
+    rows = c < rows ? c : rows;
+  }
+  return rows;
+}
+
+// One workgroup per tile of M rows.  The grid covers the row bounds; tiles
+// past a segment's device-side row count exit at once.
+// MULTI = false: one segment, geometry in the kernel arguments.
+// MULTI = true: up to kMaxSeg segments (a work list of tiles from several
+// networks); a tile's segment is found from the tile index and its geometry
+// read from the segment's device copy.
+template <int P, int H, int NW, bool MULTI>
+__global__ __launch_bounds__(64 * NW) void fused_forward(Geom g0, FwdLaunch la) {
+  using Sh = Shape<P, H, NW>;
+  constexpr int M = Sh::M;
+  extern __shared__ uint4 smem[];
+  char* act = (char*)smem;
+  const long long t = blockIdx.x;
+  if constexpr (!MULTI) {
+    const FwdSeg& sg = la.seg[0];
+    const long long rows = seg_rows(sg);
+    if (t * M < rows) fwd_tile<P, H, NW>(g0, (const uint4*)sg.packed, sg.x, t * M, rows, (double2*)sg.out, act);
+  } else {
+    int k = 0;
+    for (int j = 1; j < la.nseg; ++j)
+      if (t >= la.seg[j].tile0) k = j;
+    const FwdSeg& sg = la.seg[k];
+    const long long rows = seg_rows(sg);
+    const long long row0 = (t - sg.tile0) * M;
+    // the geometry is read in place: nothing in this kernel writes global
+    // memory before the tile's outputs, so its loads stay scalar
+    if (row0 < rows) fwd_tile<P, H, NW>(*sg.geom, (const uint4*)sg.packed, sg.x, row0, rows, (double2*)sg.out, act);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int k = 0; k < la.nseg; ++k)
+      if (la.seg[k].prof_slot) *la.seg[k].prof_slot = seg_rows(la.seg[k]);
+  }
+}
+
+__global__ void store_geom_kernel(Geom g, Geom* dst) {
+  const int* src = (const int*)&g;
+  for (int i = threadIdx.x; i < (int)(sizeof(Geom) / 4); i += blockDim.x) ((int*)dst)[i] = src[i];
+}
+
+void launch_store_geom(const Geom& g, Geom* dst, hipStream_t s) {
+  static_assert(sizeof(Geom) % 4 == 0, "Geom is copied in 32-bit words");
+  hipLaunchKernelGGL(store_geom_kernel, dim3(1), dim3(256), 0, s, g, dst);
+}
+
+template <int P, int H, int V, bool MULTI>
+static void launch_one(const Geom& g, FwdLaunch& la, hipStream_t s) {
+  constexpr int NW = variant_waves<P, H, V>();
+  using Sh = Shape<P, H, NW>;
+  constexpr size_t LDS = Sh::LDS;
+  auto kern = fused_forward<P, H, NW, MULTI>;
   static bool attr_done = false;
   if (!attr_done) {
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS);
     attr_done = true;
   }
-  long long blocks = (rows_bound + M - 1) / M;
-  if (blocks <= 0) return;
-  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves_per_block<P, H>()), LDS, s, g,
-                     (const uint4*)packed, x, rows_bound, d_count, (double2*)out, prof_slot);
+  long long tiles = 0;
+  for (int k = 0; k < la.nseg; ++k) {
+    la.seg[k].tile0 = tiles;
+    tiles += (la.seg[k].rows_bound + Sh::M - 1) / Sh::M;
+  }
+  la.ntiles = tiles;
+  if (tiles <= 0) return;
+  hipLaunchKernelGGL(kern, dim3((unsigned)tiles), dim3(64 * NW), LDS, s, g, la);
 }
 
 int forward_rows_per_block(int prec, int h) {
   switch (prec) {
     case P_BF16: return 65536 / h;
-    case P_BF16X3: return 32768 / h;
+    case P_BF16X3: case P_BF16W: return 32768 / h;
     case P_F32: return 32768 / h;
     default: return h < 256 ? 8192 / h : 16384 / h;
   }
@@ -593,23 +738,54 @@ int forward_rows_per_block(int prec, int h) {
 
 bool forward_supported(int prec, int h) {
   switch (prec) {
-    case P_BF16: case P_BF16X3: return h == 256 || h == 512 || h == 1024;
+    case P_BF16: case P_BF16X3: case P_BF16W: return h == 256 || h == 512 || h == 1024;
     case P_F32: return h == 128 || h == 256 || h == 512 || h == 1024;
     case P_F64: return h == 64 || h == 128 || h == 256 || h == 512 || h == 1024;
   }
   return false;
 }
 
-void launch_forward(const Geom& g, const void* packed, const uint64_t* x, long long rows_bound,
-                    const long long* d_count, double* out, long long* prof_slot, hipStream_t s) {
-#define NQS_CASE(P, H) \
-  if (g.prec == P && g.h == H) { launch_one<P, H>(g, packed, x, rows_bound, d_count, out, prof_slot, s); return; }
+int forward_variants(int prec, int h) {
+  (void)h;
+  return prec == P_F64 ? 1 : 2;
+}
+
+int forward_variant_waves(int prec, int h, int v) {
+  const int d = ((prec == P_BF16 || prec == P_BF16X3 || prec == P_BF16W) && h >= 512) ? 16 : 8;
+  return v == 0 ? d : (d == 16 ? 8 : 16);
+}
+
+template <bool MULTI>
+static void dispatch(const Geom& g, int prec, int h, int v, FwdLaunch& la, hipStream_t s) {
+#define NQS_CASE(P, H)                                                  \
+  if (prec == P && h == H) {                                            \
+    if constexpr (P != P_F64) {                                         \
+      if (v == 1) { launch_one<P, H, 1, MULTI>(g, la, s); return; }     \
+    }                                                                   \
+    launch_one<P, H, 0, MULTI>(g, la, s);                               \
+    return;                                                             \
+  }
   NQS_CASE(P_BF16, 256) NQS_CASE(P_BF16, 512) NQS_CASE(P_BF16, 1024)
   NQS_CASE(P_BF16X3, 256) NQS_CASE(P_BF16X3, 512) NQS_CASE(P_BF16X3, 1024)
+  NQS_CASE(P_BF16W, 256) NQS_CASE(P_BF16W, 512) NQS_CASE(P_BF16W, 1024)
   NQS_CASE(P_F32, 128) NQS_CASE(P_F32, 256) NQS_CASE(P_F32, 512) NQS_CASE(P_F32, 1024)
   NQS_CASE(P_F64, 64) NQS_CASE(P_F64, 128) NQS_CASE(P_F64, 256) NQS_CASE(P_F64, 512)
   NQS_CASE(P_F64, 1024)
 #undef NQS_CASE
+}
+
+void launch_forward(const Geom& g, int variant, const void* packed, const uint64_t* x, long long rows_bound,
+                    const long long* d_count, double* out, long long* prof_slot, hipStream_t s) {
+  FwdLaunch la{};
+  la.nseg = 1;
+  la.seg[0] = FwdSeg{nullptr, packed, x, d_count, out, rows_bound, 0, prof_slot};
+  dispatch<false>(g, g.prec, g.h, variant, la, s);
+}
+
+void launch_forward_multi(int prec, int h, int variant, FwdLaunch la, hipStream_t s) {
+  if (la.nseg < 1 || la.nseg > kMaxSeg) return;
+  Geom unused{};
+  dispatch<true>(unused, prec, h, variant, la, s);
 }
 
 }  // namespace nqs

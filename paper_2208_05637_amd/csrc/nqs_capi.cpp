@@ -10,7 +10,9 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -84,11 +86,17 @@ struct nqs_plan {
   const nqs_ham* ham = nullptr;
   Geom g{};
   int64_t max_batch = 0;
-  int64_t S = 0;           // samples per chunk
+  int64_t S = 0;           // samples per chunk (tunable, <= S0)
+  int64_t S0 = 0;          // samples per chunk the workspace is sized for
+  int64_t SRcap = 0;       // capacity of the (sample, group range) count arrays
   int64_t Emax = 0;        // entries per sample bound
-  int64_t EC = 0;          // entries per chunk capacity
-  int R = 1, gper = 0;     // group ranges of the enumeration grid
-  bool dedup = false;
+  int64_t EC = 0;          // entries per chunk capacity (S0 * Emax)
+  int R = 1, gper = 0;     // group ranges of the enumeration grid for S
+  bool dedup = false;      // dedup on for this plan's calls
+  bool dedup_cap = false;  // workspace holds the dedup tables
+  bool dedup_auto = false; // the autotuner may switch dedup
+  int variant = 0;         // forward kernel variant
+  bool tuned = false;
   int64_t HT = 0;          // dedup hash slots
   int64_t Sb = 0;          // backward chunk
   int bw = 4;              // bytes per element of the backward path
@@ -104,9 +112,18 @@ struct nqs_plan {
 constexpr int kProfSlots = 8192;
 
 struct WsLayout {
-  size_t err, prof, packed, wm, lps, eloc, energy, cnt, off, diag, xe, he, lpe, hkeys, hslot, eu, xu,
+  size_t err, prof, geom, packed, wm, lps, eloc, energy, cnt, off, diag, xe, he, lpe, hkeys, hslot, eu, xu,
       nu, bscratch, total;
 };
+
+// Enumeration grid for chunks of S samples: R ranges of gper flip groups.
+static void grid_for(int64_t S, int ngroups, int& R, int& gper) {
+  const int bx = (int)((S + 255) / 256);
+  if (ngroups <= 0) { R = 1; gper = 0; return; }
+  const int r = std::max(1, std::min(ngroups, 2048 / bx));
+  gper = (ngroups + r - 1) / r;
+  R = (ngroups + gper - 1) / gper;
+}
 
 static WsLayout layout(const nqs_plan* p, int64_t B) {
   WsLayout L{};
@@ -115,18 +132,19 @@ static WsLayout layout(const nqs_plan* p, int64_t B) {
   const int hs = p->ham->has_imag ? 2 : 1;
   L.err = take(256);
   L.prof = take((size_t)kProfSlots * 8);
+  L.geom = take(sizeof(Geom));
   L.packed = take(p->packed_bytes);
   L.wm = take((size_t)p->g.n_params * p->bw);
   L.lps = take((size_t)std::max<int64_t>(B, 1) * 16);
   L.eloc = take((size_t)std::max<int64_t>(B, 1) * 16);
   L.energy = take(3 * 8);
-  L.cnt = take((size_t)p->S * p->R * 4);
-  L.off = take(((size_t)p->S * p->R + 1) * 8);
-  L.diag = take((size_t)p->S * 16);
+  L.cnt = take((size_t)p->SRcap * 4);
+  L.off = take(((size_t)p->SRcap + 1) * 8);
+  L.diag = take((size_t)p->S0 * 16);
   L.xe = take((size_t)p->EC * 8);
   L.he = take((size_t)p->EC * 8 * hs);
   L.lpe = take((size_t)p->EC * 16);
-  if (p->dedup) {
+  if (p->dedup_cap) {
     L.hkeys = take((size_t)p->HT * 8);
     L.hslot = take((size_t)p->HT * 4);
     L.eu = take((size_t)p->EC * 4);
@@ -338,7 +356,7 @@ static nqs_status build_geom(const nqs_net_desc* nd, Geom& g) {
   const int n = nd->n_qubits, L = nd->n_layers, h = nd->width;
   if (n < 2 || n > 64) return fail(NQS_ERR_UNSUPPORTED, "n_qubits = %d outside 2..64", n);
   if (L < 1 || L > kMaxLayers) return fail(NQS_ERR_UNSUPPORTED, "n_layers = %d outside 1..%d", L, kMaxLayers);
-  if (nd->precision < NQS_FP64 || nd->precision > NQS_BF16X3)
+  if (nd->precision < NQS_FP64 || nd->precision > NQS_BF16W)
     return fail(NQS_ERR_INVALID_ARGUMENT, "unknown precision %d", nd->precision);
   if (!forward_supported(nd->precision, h))
     return fail(NQS_ERR_UNSUPPORTED, "width %d not supported for precision %d", h, nd->precision);
@@ -361,7 +379,7 @@ static nqs_status build_geom(const nqs_net_desc* nd, Geom& g) {
     g.spin_pos[order[t] & 1] |= 1ull << t;
   }
   g.TB = g.prec == P_F64 ? 16 : 32;
-  g.KSTEP = (g.prec == P_BF16 || g.prec == P_BF16X3) ? 16 : 8;
+  g.KSTEP = (g.prec == P_BF16 || g.prec == P_BF16X3 || g.prec == P_BF16W) ? 16 : 8;
   g.NB = h / g.TB;
   g.nhead = n + 4;
   g.NHB = (g.nhead + g.TB - 1) / g.TB;
@@ -424,8 +442,10 @@ nqs_status nqs_plan_create(nqs_ctx* ctx, const nqs_ham* ham, const nqs_net_desc*
   if (!ctx || !ham || !out) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
   *out = nullptr;
   if (max_batch < 1) return fail(NQS_ERR_INVALID_ARGUMENT, "max_batch must be >= 1");
-  if ((flags & NQS_PLAN_DEDUP_ON) && (flags & NQS_PLAN_DEDUP_OFF))
-    return fail(NQS_ERR_INVALID_ARGUMENT, "DEDUP_ON and DEDUP_OFF together");
+  const uint32_t dflags = flags & (NQS_PLAN_DEDUP_ON | NQS_PLAN_DEDUP_OFF | NQS_PLAN_DEDUP_AUTO);
+  if (dflags & (dflags - 1)) return fail(NQS_ERR_INVALID_ARGUMENT, "more than one of DEDUP_ON/OFF/AUTO");
+  if (flags & ~(NQS_PLAN_DEDUP_ON | NQS_PLAN_DEDUP_OFF | NQS_PLAN_DEDUP_AUTO))
+    return fail(NQS_ERR_INVALID_ARGUMENT, "unknown plan flags 0x%x", flags);
   Geom g;
   nqs_status st = build_geom(nd, g);
   if (st != NQS_OK) return st;
@@ -462,22 +482,26 @@ nqs_status nqs_plan_create(nqs_ctx* ctx, const nqs_ham* ham, const nqs_net_desc*
   const int64_t target = 16 * 1024 * 1024;
   if (chunk_samples > 0) p->S = std::min<int64_t>(chunk_samples, max_batch);
   else p->S = std::max<int64_t>(1, std::min<int64_t>(max_batch, target / std::max<int64_t>(p->Emax, 1)));
+  p->S0 = p->S;
   p->EC = std::max<int64_t>(p->S * p->Emax, 1);
   if (p->EC >= (1LL << 31)) {
     delete p;
     return fail(NQS_ERR_UNSUPPORTED, "chunk of %lld entries exceeds 2^31", (long long)p->S * p->Emax);
   }
   const int ngroups = G - gfirst;
-  const int bx = (int)((p->S + 255) / 256);
-  if (ngroups <= 0) { p->R = 1; p->gper = 0; }
-  else {
-    int R = std::max(1, std::min(ngroups, 2048 / bx));
-    p->gper = (ngroups + R - 1) / R;
-    p->R = (ngroups + p->gper - 1) / p->gper;
+  grid_for(p->S, ngroups, p->R, p->gper);
+  // count arrays sized for every chunk the autotuner may pick (S0, S0/2)
+  {
+    int r2 = 1, gp2 = 0;
+    const int64_t half = std::max<int64_t>(1, p->S0 / 2);
+    grid_for(half, ngroups, r2, gp2);
+    p->SRcap = std::max<int64_t>(p->S0 * p->R, half * r2);
   }
-  p->dedup = (flags & NQS_PLAN_DEDUP_ON) != 0;
-  if (p->dedup && g.n == 64) p->dedup = false;   // all-ones word is the empty-slot marker
-  if (p->dedup) {
+  // all-ones is the empty-slot marker of the hash table, so no dedup at 64 qubits
+  p->dedup_cap = (flags & (NQS_PLAN_DEDUP_ON | NQS_PLAN_DEDUP_AUTO)) != 0 && g.n < 64;
+  p->dedup = p->dedup_cap;
+  p->dedup_auto = (flags & NQS_PLAN_DEDUP_AUTO) != 0 && p->dedup_cap;
+  if (p->dedup_cap) {
     int64_t ht = 4096;
     while (ht < 2 * p->EC) ht <<= 1;
     p->HT = ht;
@@ -501,10 +525,18 @@ nqs_status nqs_plan_create(nqs_ctx* ctx, const nqs_ham* ham, const nqs_net_desc*
     }
     for (int j = 0; j < n; ++j) nnzo += (double)cnt_le[j];   // d(j) = 1 + pos: units with m < d
     p->flops_alg_row = 2.0 * (nnz1 + (g.L - 1) * nnzh + nnzo + nnzp);
-    long long fr = 0;
-    for (int nb = 0; nb < g.NB; ++nb) fr += g.ks1[nb] + (long long)(g.L - 1) * g.ksh[nb];
+    // fragments issued per configuration; split BF16 multiplies each with
+    // three BF16 MFMAs, BF16 weights with two; one fewer in layer 1 (its +-1
+    // inputs have no low part)
+    long long fr1 = 0, fr = 0;
+    for (int nb = 0; nb < g.NB; ++nb) {
+      fr1 += g.ks1[nb];
+      fr += (long long)(g.L - 1) * g.ksh[nb];
+    }
     for (int nb = 0; nb < g.NHB; ++nb) fr += g.kso[nb];
-    p->flops_exec_row = 2.0 * g.TB * g.KSTEP * (double)fr;
+    const double mult = g.prec == P_BF16X3 ? 3.0 : (g.prec == P_BF16W ? 2.0 : 1.0);
+    const double mult1 = mult > 1.0 ? mult - 1.0 : 1.0;
+    p->flops_exec_row = 2.0 * g.TB * g.KSTEP * (mult1 * (double)fr1 + mult * (double)fr);
   }
   *out = p;
   return NQS_OK;
@@ -607,49 +639,83 @@ static void forward_profiled(nqs_plan* p, void* ws, const WsLayout& L, const voi
     si = p->next_slot++;
     slot = at<long long>(ws, L.prof) + si;
   }
-  launch_forward(p->g, packed, x, bound, d_count, out, slot, p->ctx->stream);
+  launch_forward(p->g, p->variant, packed, x, bound, d_count, out, slot, p->ctx->stream);
   prof_close(p, a, 2, si);
+}
+
+// The connected configurations of one chunk, ready for the forward.
+struct ChunkFwd {
+  const uint64_t* x;          // configurations to evaluate
+  const long long* d_count;   // their number (device)
+  long long bound;            // host bound on that number
+  double* out;                // log psi of each
+};
+
+// Enumerate (and optionally deduplicate) the connected configurations of
+// samples [c0, c0 + Sc).
+static ChunkFwd enum_chunk(nqs_plan* p, const uint64_t* x, int64_t c0, int64_t Sc, void* ws, const WsLayout& L) {
+  hipStream_t s = p->ctx->stream;
+  const HamDev H = ham_dev(p);
+  const int hs = p->ham->has_imag ? 2 : 1;
+  const uint64_t* xc = x + c0;
+  unsigned* err = at<unsigned>(ws, L.err);
+  int* cnt = at<int>(ws, L.cnt);
+  long long* off = at<long long>(ws, L.off);
+  uint64_t* xe = at<uint64_t>(ws, L.xe);
+  launch_diag(H, xc, Sc, at<double>(ws, L.diag), s);
+  launch_count(H, xc, Sc, p->R, p->gper, cnt, s);
+  launch_scan(cnt, Sc * p->R, off, s);
+  launch_write(H, xc, Sc, p->R, p->gper, off, p->EC, xe, at<double>(ws, L.he), nullptr, hs, err, s);
+  const long long* d_total = off + Sc * p->R;
+  const int64_t bound = std::min<int64_t>(Sc * p->Emax, p->EC);
+  if (p->dedup) {
+    uint64_t* xu = at<uint64_t>(ws, L.xu);
+    long long* nu = at<long long>(ws, L.nu);
+    launch_dedup(xe, d_total, p->EC, at<uint64_t>(ws, L.hkeys), at<int>(ws, L.hslot), p->HT, at<int>(ws, L.eu), xu,
+                 nu, err, s);
+    return {xu, nu, bound, at<double>(ws, L.lpe)};
+  }
+  return {xe, d_total, bound, at<double>(ws, L.lpe)};
+}
+
+// Ratio-and-reduce of the chunk into eloc[c0 .. c0 + Sc).
+static void reduce_chunk(nqs_plan* p, int64_t c0, int64_t Sc, void* ws, const WsLayout& L, double* eloc) {
+  const int hs = p->ham->has_imag ? 2 : 1;
+  launch_reduce(Sc, p->R, at<long long>(ws, L.off), p->EC, at<double>(ws, L.diag), at<double>(ws, L.he), hs,
+                p->dedup ? at<int>(ws, L.eu) : nullptr, at<double>(ws, L.lpe), at<double>(ws, L.lps) + 2 * c0,
+                eloc + 2 * c0, at<unsigned>(ws, L.err), p->ctx->stream);
 }
 
 // local energies of B samples into eloc; lps (sample log psi) computed first.
 static nqs_status run_local_energy(nqs_plan* p, const float* params, const uint64_t* x, int64_t B,
                                    double* eloc, void* ws, const WsLayout& L) {
-  hipStream_t s = p->ctx->stream;
-  const HamDev H = ham_dev(p);
-  unsigned* err = at<unsigned>(ws, L.err);
   void* packed = at<void>(ws, L.packed);
-  double* lps = at<double>(ws, L.lps);
-  launch_pack_fused(p->g, params, packed, s);
-  forward_profiled(p, ws, L, packed, x, B, nullptr, lps);
-  const int hs = p->ham->has_imag ? 2 : 1;
+  launch_pack_fused(p->g, params, packed, p->ctx->stream);
+  forward_profiled(p, ws, L, packed, x, B, nullptr, at<double>(ws, L.lps));
   for (int64_t c0 = 0; c0 < B; c0 += p->S) {
     const int64_t Sc = std::min<int64_t>(p->S, B - c0);
-    const uint64_t* xc = x + c0;
-    int* cnt = at<int>(ws, L.cnt);
-    long long* off = at<long long>(ws, L.off);
-    double* diag = at<double>(ws, L.diag);
-    uint64_t* xe = at<uint64_t>(ws, L.xe);
-    double* he = at<double>(ws, L.he);
-    double* lpe = at<double>(ws, L.lpe);
-    launch_diag(H, xc, Sc, diag, s);
-    launch_count(H, xc, Sc, p->R, p->gper, cnt, s);
-    launch_scan(cnt, Sc * p->R, off, s);
-    launch_write(H, xc, Sc, p->R, p->gper, off, p->EC, xe, he, nullptr, hs, err, s);
-    const long long* d_total = off + Sc * p->R;
-    const int64_t bound = std::min<int64_t>(Sc * p->Emax, p->EC);
-    int* eu = nullptr;
-    if (p->dedup) {
-      eu = at<int>(ws, L.eu);
-      uint64_t* xu = at<uint64_t>(ws, L.xu);
-      long long* nu = at<long long>(ws, L.nu);
-      launch_dedup(xe, d_total, p->EC, at<uint64_t>(ws, L.hkeys), at<int>(ws, L.hslot), p->HT, eu, xu, nu, err, s);
-      forward_profiled(p, ws, L, packed, xu, bound, nu, lpe);
-    } else {
-      forward_profiled(p, ws, L, packed, xe, bound, d_total, lpe);
-    }
-    launch_reduce(Sc, p->R, off, p->EC, diag, he, hs, eu, lpe, lps + 2 * c0, eloc + 2 * c0, err, s);
+    const ChunkFwd cf = enum_chunk(p, x, c0, Sc, ws, L);
+    forward_profiled(p, ws, L, packed, cf.x, cf.bound, cf.d_count, cf.out);
+    reduce_chunk(p, c0, Sc, ws, L, eloc);
   }
   return launch_check("local energy");
+}
+
+// Energy (Eq. total_energy_sum) and gradient (Eq. grad) from the local
+// energies el of B samples: the backward recomputes the sample forward in
+// chunks of Sb samples and accumulates into grad.
+static void energy_and_grad(nqs_plan* p, const float* params, const uint64_t* x, const double* w, int64_t B,
+                            const double* el, double* energy, double* grad, void* ws, const WsLayout& L) {
+  hipStream_t s = p->ctx->stream;
+  launch_energy(el, w, B, energy, at<unsigned>(ws, L.err), s);
+  launch_fill_u64(grad, 0ull, p->g.n_params, s);
+  void* wm = at<void>(ws, L.wm);
+  launch_pack_masked(p->g, params, wm, s);
+  void* scratch = at<void>(ws, L.bscratch);
+  for (int64_t c0 = 0; c0 < B; c0 += p->Sb) {
+    const int64_t Sc = std::min<int64_t>(p->Sb, B - c0);
+    launch_backward(p->g, wm, x + c0, Sc, el + 2 * c0, w ? w + c0 : nullptr, energy, scratch, grad, s);
+  }
 }
 
 extern "C" {
@@ -665,7 +731,7 @@ nqs_status nqs_log_psi(nqs_plan* p, const float* params, const uint64_t* x, int6
   hipStream_t s = p->ctx->stream;
   void* packed = at<void>(ws, L.packed);
   launch_pack_fused(p->g, params, packed, s);
-  launch_forward(p->g, packed, x, n, nullptr, out, nullptr, s);
+  launch_forward(p->g, p->variant, packed, x, n, nullptr, out, nullptr, s);
   return launch_check("log psi");
 }
 
@@ -703,15 +769,7 @@ nqs_status nqs_energy_grad(nqs_plan* p, const float* params, const uint64_t* x, 
     hipEvent_t t1 = prof_mark(p);
     if (t1) p->recs.push_back({t0, t1, 1, -1});
   }
-  launch_energy(el, w, B, energy, err, s);
-  launch_fill_u64(grad, 0ull, p->g.n_params, s);
-  void* wm = at<void>(ws, L.wm);
-  launch_pack_masked(p->g, params, wm, s);
-  void* scratch = at<void>(ws, L.bscratch);
-  for (int64_t c0 = 0; c0 < B; c0 += p->Sb) {
-    const int64_t Sc = std::min<int64_t>(p->Sb, B - c0);
-    launch_backward(p->g, wm, x + c0, Sc, el + 2 * c0, w ? w + c0 : nullptr, energy, scratch, grad, s);
-  }
+  energy_and_grad(p, params, x, w, B, el, energy, grad, ws, L);
   if (t0) {
     hipEvent_t t2 = prof_mark(p);
     if (t2) p->recs.push_back({t0, t2, 0, -1});
@@ -719,28 +777,252 @@ nqs_status nqs_energy_grad(nqs_plan* p, const float* params, const uint64_t* x, 
   return launch_check("energy gradient");
 }
 
-nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* ws, size_t ws_bytes) {
+// Workspace of a multi-instance call: each instance's layout, 256-byte aligned, in order.
+static nqs_status multi_layout(int n_inst, const nqs_instance* inst, std::vector<size_t>& base, size_t& total) {
   if (n_inst < 0 || (n_inst > 0 && !inst)) return fail(NQS_ERR_INVALID_ARGUMENT, "bad instance list");
-  std::vector<int> ord(n_inst);
+  base.assign(n_inst, 0);
+  total = 0;
   for (int i = 0; i < n_inst; ++i) {
-    ord[i] = i;
-    if (!inst[i].plan) return fail(NQS_ERR_INVALID_ARGUMENT, "instance %d has no plan", i);
-    if (inst[i].plan->ctx != inst[0].plan->ctx)
-      return fail(NQS_ERR_INVALID_ARGUMENT, "instances on different contexts");
-    WsLayout L;
-    nqs_status st = check_ws(inst[i].plan, inst[i].B, ws, ws_bytes, L);
-    if (st != NQS_OK) return st;
+    const nqs_instance& I = inst[i];
+    if (!I.plan) return fail(NQS_ERR_INVALID_ARGUMENT, "instance %d has no plan", i);
+    if (I.plan->ctx != inst[0].plan->ctx) return fail(NQS_ERR_INVALID_ARGUMENT, "instances on different contexts");
+    if (I.B < 1 || I.B > I.plan->max_batch)
+      return fail(NQS_ERR_INVALID_ARGUMENT, "instance %d: batch %lld outside 1..%lld", i, (long long)I.B,
+                  (long long)I.plan->max_batch);
+    base[i] = total;
+    total += align256(layout(I.plan, I.B).total);
   }
-  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
-    return inst[a].B * inst[a].plan->Emax * inst[a].plan->g.n_params >
-           inst[b].B * inst[b].plan->Emax * inst[b].plan->g.n_params;
-  });
-  for (int k : ord) {
-    const nqs_instance& I = inst[k];
-    nqs_status st = nqs_energy_grad(I.plan, I.d_params, I.d_samples, I.d_weights, I.B, I.d_eloc, I.d_energy,
-                                    I.d_grad, ws, ws_bytes);
-    if (st != NQS_OK) return st;
+  return NQS_OK;
+}
+
+nqs_status nqs_multi_workspace_size(int n_inst, const nqs_instance* inst, size_t* bytes) {
+  if (!bytes) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
+  std::vector<size_t> base;
+  return multi_layout(n_inst, inst, base, *bytes);
+}
+
+nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* ws, size_t ws_bytes) {
+  std::vector<size_t> base;
+  size_t total = 0;
+  nqs_status st = multi_layout(n_inst, inst, base, total);
+  if (st != NQS_OK) return st;
+  if (n_inst == 0) return NQS_OK;
+  if (!ws) return fail(NQS_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (((uintptr_t)ws) & 255) return fail(NQS_ERR_INVALID_ARGUMENT, "workspace not 256-byte aligned");
+  if (ws_bytes < total) return fail(NQS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, total);
+  for (int i = 0; i < n_inst; ++i) {
+    const nqs_instance& I = inst[i];
+    if (!I.d_params || !I.d_samples || !I.d_energy || !I.d_grad)
+      return fail(NQS_ERR_INVALID_ARGUMENT, "instance %d: NULL argument", i);
   }
+  nqs_plan* p0 = inst[0].plan;
+  hipStream_t s = p0->ctx->stream;
+  hipEvent_t t0 = prof_mark(p0);
+  std::vector<WsLayout> L(n_inst);
+  std::vector<void*> W(n_inst);
+  std::vector<double*> EL(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    nqs_plan* p = inst[i].plan;
+    W[i] = (char*)ws + base[i];
+    L[i] = layout(p, inst[i].B);
+    EL[i] = inst[i].d_eloc ? inst[i].d_eloc : at<double>(W[i], L[i].eloc);
+    launch_fill_u32(at<void>(W[i], L[i].err), 0u, 1, s);
+    launch_store_geom(p->g, at<Geom>(W[i], L[i].geom), s);
+    launch_pack_fused(p->g, inst[i].d_params, at<void>(W[i], L[i].packed), s);
+  }
+  // One forward launch per group of segments whose networks share
+  // (precision, width, variant): the segments' tiles form one work list.
+  auto launch_groups = [&](const std::vector<int>& ids, const std::vector<FwdSeg>& segs) {
+    std::vector<bool> done(ids.size(), false);
+    for (size_t a = 0; a < ids.size(); ++a) {
+      if (done[a]) continue;
+      const Geom& ga = inst[ids[a]].plan->g;
+      const int va = inst[ids[a]].plan->variant;
+      FwdLaunch la{};
+      for (size_t b = a; b < ids.size(); ++b) {
+        const Geom& gb = inst[ids[b]].plan->g;
+        if (done[b] || gb.prec != ga.prec || gb.h != ga.h || inst[ids[b]].plan->variant != va) continue;
+        la.seg[la.nseg++] = segs[b];
+        done[b] = true;
+        if (la.nseg == kMaxSeg) {
+          launch_forward_multi(ga.prec, ga.h, va, la, s);
+          la = FwdLaunch{};
+        }
+      }
+      if (la.nseg > 0) launch_forward_multi(ga.prec, ga.h, va, la, s);
+    }
+  };
+  std::vector<int> ids;
+  std::vector<FwdSeg> segs;
+  for (int i = 0; i < n_inst; ++i) {
+    ids.push_back(i);
+    segs.push_back(FwdSeg{at<Geom>(W[i], L[i].geom), at<void>(W[i], L[i].packed), inst[i].d_samples, nullptr,
+                          at<double>(W[i], L[i].lps), inst[i].B, 0, nullptr});
+  }
+  launch_groups(ids, segs);
+  // chunk rounds: round r takes chunk r of every instance that still has one
+  for (int64_t r = 0;; ++r) {
+    ids.clear();
+    segs.clear();
+    std::vector<int64_t> c0s, scs;
+    for (int i = 0; i < n_inst; ++i) {
+      nqs_plan* p = inst[i].plan;
+      const int64_t c0 = r * p->S;
+      if (c0 >= inst[i].B) continue;
+      const int64_t Sc = std::min<int64_t>(p->S, inst[i].B - c0);
+      const ChunkFwd cf = enum_chunk(p, inst[i].d_samples, c0, Sc, W[i], L[i]);
+      ids.push_back(i);
+      c0s.push_back(c0);
+      scs.push_back(Sc);
+      segs.push_back(FwdSeg{at<Geom>(W[i], L[i].geom), at<void>(W[i], L[i].packed), cf.x, cf.d_count, cf.out,
+                            cf.bound, 0, nullptr});
+    }
+    if (ids.empty()) break;
+    launch_groups(ids, segs);
+    for (size_t k = 0; k < ids.size(); ++k) reduce_chunk(inst[ids[k]].plan, c0s[k], scs[k], W[ids[k]], L[ids[k]], EL[ids[k]]);
+  }
+  for (int i = 0; i < n_inst; ++i) {
+    const nqs_instance& I = inst[i];
+    energy_and_grad(I.plan, I.d_params, I.d_samples, I.d_weights, I.B, EL[i], I.d_energy, I.d_grad, W[i], L[i]);
+  }
+  if (t0) {
+    hipEvent_t t1 = prof_mark(p0);
+    if (t1) p0->recs.push_back({t0, t1, 0, -1});
+  }
+  return launch_check("energy gradient (multi)");
+}
+
+// ------------------------------------------------------------- autotuner
+namespace {
+using TuneKey = std::tuple<int, int, int, int, int64_t, int64_t, int64_t, int64_t, int, int>;
+struct TuneVal { int variant; bool dedup; int64_t S; double ms; };
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune_cache;
+
+TuneKey tune_key(const nqs_plan* p) {
+  return TuneKey{p->g.n, p->g.L, p->g.h, p->g.prec, (int64_t)p->ham->tz.size(), (int64_t)p->ham->gx.size(),
+                 p->Emax, p->S0, p->dedup_auto ? 1 : 0, p->ctx->device};
+}
+
+void set_chunk(nqs_plan* p, int64_t S) {
+  const int G = (int)p->ham->gx.size();
+  const int gfirst = (G > 0 && p->ham->gx[0] == 0) ? 1 : 0;
+  p->S = S;
+  grid_for(S, G - gfirst, p->R, p->gper);
+}
+}  // namespace
+
+nqs_status nqs_plan_autotune(nqs_plan* p, const float* params, const uint64_t* x, int64_t B, void* ws,
+                             size_t ws_bytes, uint32_t flags, nqs_tune_report* rep) {
+  if (!p || !params || !x) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (B < 1) return fail(NQS_ERR_INVALID_ARGUMENT, "autotuning needs at least one sample");
+  if (flags & ~NQS_TUNE_FORCE) return fail(NQS_ERR_INVALID_ARGUMENT, "unknown tune flags 0x%x", flags);
+  WsLayout L;
+  nqs_status st = check_ws(p, B, ws, ws_bytes, L);
+  if (st != NQS_OK) return st;
+  nqs_tune_report local{};
+  nqs_tune_report& R = rep ? *rep : local;
+  memset(&R, 0, sizeof(R));
+  const TuneKey key = tune_key(p);
+  if (!(flags & NQS_TUNE_FORCE)) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      p->variant = it->second.variant;
+      p->dedup = it->second.dedup;
+      set_chunk(p, it->second.S);
+      p->tuned = true;
+      R.from_cache = 1;
+      R.n_candidates = 1;
+      R.chosen = 0;
+      R.cand[0] = nqs_tune_candidate{forward_variant_waves(p->g.prec, p->g.h, p->variant), p->dedup ? 1 : 0, p->S,
+                                     it->second.ms};
+      return NQS_OK;
+    }
+  }
+  struct Cand { int v; bool d; int64_t S; };
+  std::vector<Cand> cands;
+  const int nv = forward_variants(p->g.prec, p->g.h);
+  std::vector<bool> dd = p->dedup_auto ? std::vector<bool>{false, true} : std::vector<bool>{p->dedup};
+  std::vector<int64_t> ss{p->S0};
+  if (p->S0 >= 2) ss.push_back(p->S0 / 2);
+  for (int v = 0; v < nv; ++v)
+    for (bool d : dd)
+      for (int64_t S : ss) cands.push_back({v, d, S});
+  if ((int)cands.size() > NQS_TUNE_MAX_CANDIDATES) cands.resize(NQS_TUNE_MAX_CANDIDATES);
+  const int64_t probe = std::min<int64_t>(B, 2 * p->S0);
+  const bool prof = p->prof;
+  p->prof = false;
+  double* el = at<double>(ws, L.eloc);
+  hipStream_t s = p->ctx->stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int best = -1;
+  double best_ms = 0.0;
+  for (size_t c = 0; c < cands.size(); ++c) {
+    p->variant = cands[c].v;
+    p->dedup = cands[c].d;
+    set_chunk(p, cands[c].S);
+    launch_fill_u32(at<void>(ws, L.err), 0u, 1, s);
+    st = run_local_energy(p, params, x, probe, el, ws, L);   // warm-up
+    if (st == NQS_OK) {
+      HIP_TRY(hipEventRecord(e0, s));
+      for (int k = 0; k < 2 && st == NQS_OK; ++k) st = run_local_energy(p, params, x, probe, el, ws, L);
+      HIP_TRY(hipEventRecord(e1, s));
+    }
+    if (st != NQS_OK) break;
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    R.cand[c] = nqs_tune_candidate{forward_variant_waves(p->g.prec, p->g.h, cands[c].v), cands[c].d ? 1 : 0,
+                                   cands[c].S, ms / 2.0};
+    if (best < 0 || ms / 2.0 < best_ms) { best = (int)c; best_ms = ms / 2.0; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->prof = prof;
+  if (st != NQS_OK || best < 0) return st != NQS_OK ? st : fail(NQS_ERR_INVALID_ARGUMENT, "no candidate");
+  R.n_candidates = (int)cands.size();
+  R.chosen = best;
+  R.probe_samples = probe;
+  p->variant = cands[best].v;
+  p->dedup = cands[best].d;
+  set_chunk(p, cands[best].S);
+  p->tuned = true;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = TuneVal{p->variant, p->dedup, p->S, best_ms};
+  }
+  return NQS_OK;
+}
+
+nqs_status nqs_plan_configure(nqs_plan* p, int waves_per_block, int dedup, int64_t chunk_samples) {
+  if (!p) return fail(NQS_ERR_INVALID_ARGUMENT, "plan is NULL");
+  int v = -1;
+  if (waves_per_block <= 0) v = p->variant;
+  for (int k = 0; v < 0 && k < forward_variants(p->g.prec, p->g.h); ++k)
+    if (forward_variant_waves(p->g.prec, p->g.h, k) == waves_per_block) v = k;
+  if (v < 0) return fail(NQS_ERR_UNSUPPORTED, "no forward variant with %d waves per workgroup", waves_per_block);
+  if (dedup > 0 && !p->dedup_cap)
+    return fail(NQS_ERR_INVALID_ARGUMENT, "plan was not created for dedup (DEDUP_ON or DEDUP_AUTO)");
+  if (chunk_samples > p->S0)
+    return fail(NQS_ERR_INVALID_ARGUMENT, "chunk %lld exceeds the plan's %lld", (long long)chunk_samples,
+                (long long)p->S0);
+  if (chunk_samples > 0 && chunk_samples < std::max<int64_t>(1, p->S0 / 2))
+    return fail(NQS_ERR_INVALID_ARGUMENT, "chunk %lld below half the plan's %lld", (long long)chunk_samples,
+                (long long)p->S0);
+  p->variant = v;
+  if (dedup >= 0) p->dedup = dedup > 0;
+  if (chunk_samples > 0) set_chunk(p, chunk_samples);
+  return NQS_OK;
+}
+
+nqs_status nqs_plan_kernel_info(const nqs_plan* p, int* waves_per_block, int* rows_per_block, int* tuned) {
+  if (!p) return fail(NQS_ERR_INVALID_ARGUMENT, "plan is NULL");
+  if (waves_per_block) *waves_per_block = forward_variant_waves(p->g.prec, p->g.h, p->variant);
+  if (rows_per_block) *rows_per_block = forward_rows_per_block(p->g.prec, p->g.h);
+  if (tuned) *tuned = p->tuned ? 1 : 0;
   return NQS_OK;
 }
 

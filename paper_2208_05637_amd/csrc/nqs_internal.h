@@ -10,9 +10,9 @@ namespace nqs {
 constexpr int kMaxLayers = 16;
 constexpr int kMaxNB = 64;        // n-blocks of the fused kernel (h / TB)
 constexpr int kMaxNHB = 8;        // head n-blocks ((n + 4) / TB rounded up)
-constexpr int kThreads = 512;     // fused forward workgroup: 8 waves
+constexpr int kMaxSeg = 8;        // segments of one multi-segment forward launch
 
-enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3 };
+enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3, P_BF16W = 4 };
 
 // Device error-word bits (mirrors NQS_DEV_* in nqs.h).
 constexpr unsigned kErrZeroAmp = 1u, kErrEntryOverflow = 2u, kErrHashOverflow = 4u;
@@ -81,9 +81,37 @@ void launch_fill_u64(void* p, unsigned long long v, long long count, hipStream_t
 void launch_pack_fused(const Geom& g, const float* params, void* packed, hipStream_t s);
 void launch_pack_masked(const Geom& g, const float* params, void* wm, hipStream_t s);
 
-// fused forward on rows [0, count): x[row] u64 -> out[2 row] = (log|psi|, phi)
-void launch_forward(const Geom& g, const void* packed, const uint64_t* x, long long rows_bound,
-                    const long long* d_count, double* out, long long* prof_slot, hipStream_t s);
+// One batch of configurations of one network inside a forward launch:
+// rows [0, min(*d_count, rows_bound)) of x -> out[row] = (log|psi|, phi).
+struct FwdSeg {
+  const Geom* geom;          // device copy of the geometry (multi-segment launches)
+  const void* packed;        // packed weights (launch_pack_fused)
+  const uint64_t* x;
+  const long long* d_count;  // nullable: then rows = rows_bound
+  double* out;               // [rows][2]
+  long long rows_bound;
+  long long tile0;           // first tile of the segment inside the launch
+  long long* prof_slot;      // nullable: receives the row count
+};
+struct FwdLaunch {
+  int nseg;
+  long long ntiles;
+  FwdSeg seg[kMaxSeg];
+};
+
+// Fused forward, one workgroup per tile of forward_rows_per_block rows.
+// variant selects the workgroup shape (forward_variants /
+// forward_variant_waves).
+void launch_forward(const Geom& g, int variant, const void* packed, const uint64_t* x,
+                    long long rows_bound, const long long* d_count, double* out,
+                    long long* prof_slot, hipStream_t s);
+// Several segments of networks with equal (precision, width); each segment's
+// geometry is read from seg.geom, a device copy written by launch_store_geom.
+// la.seg[*].tile0 and la.ntiles are filled in here.
+void launch_forward_multi(int prec, int h, int variant, FwdLaunch la, hipStream_t s);
+void launch_store_geom(const Geom& g, Geom* dst, hipStream_t s);
+int forward_variants(int prec, int h);
+int forward_variant_waves(int prec, int h, int variant);
 
 void launch_diag(const HamDev& H, const uint64_t* x, long long S, double* diag, hipStream_t s);
 void launch_count(const HamDev& H, const uint64_t* x, long long S, int R, int gper, int* cnt,

@@ -1,0 +1,167 @@
+"""GPU checks of the tunable parts of the path, through the C ABI.
+
+* every forward variant (waves per workgroup) against the oracle, at the
+  same bars as the default variant;
+* dedup on/off and the two chunk sizes the autotuner may pick give
+  bit-identical local energies (they change only which rows are evaluated
+  together, never a row's arithmetic or a sample's summation order);
+* the autotuner times every candidate, applies the fastest and caches it;
+* the multi-instance call with instances of different precisions (several
+  forward launch groups) equals single-instance calls bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import made, pauli, vmc
+from gen import hamiltonian, init_params, sector_samples, unique_with_counts
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nqs():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2208_05637_amd as m
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(nqs):
+    return nqs.Context(0)
+
+
+@pytest.mark.parametrize("prec,h,L,tol", [
+    ("fp32", 256, 2, 2e-5), ("fp32", 1024, 2, 2e-5),
+    ("bf16x3", 256, 2, 5e-4), ("bf16x3", 512, 3, 5e-4), ("bf16x3", 1024, 2, 5e-4),
+    ("bf16", 256, 2, 0.05), ("bf16", 512, 3, 0.05), ("bf16", 1024, 3, 0.05)])
+def test_forward_variants_log_psi(nqs, ctx, prec, h, L, tol):
+    N = 6
+    n = 2 * N
+    terms = hamiltonian(N, 0)
+    H = nqs.Hamiltonian.from_terms(terms).upload(ctx)
+    plan = nqs.Plan(ctx, H, L, h, 3, 3, prec, max_batch=16)
+    params = init_params(n, L, h, seed=7, std=0.1)
+    rng = np.random.default_rng(2)
+    xs = rng.integers(0, 1 << n, 2500).astype(np.uint64)       # ragged last tile
+    xs[:400] = pauli.sector_basis(n, 3, 3)
+    la_ref, ph_ref, _ = made.forward(made.Net(n=n, n_layers=L, width=h, n_up=3, n_dn=3), params, xs)
+    fin = np.isfinite(la_ref)
+    p = torch.from_numpy(params).cuda()
+    default = plan.kernel_info()["waves_per_block"]
+    for waves in (default, 8 if default == 16 else 16):
+        plan.configure(waves_per_block=waves)
+        assert plan.kernel_info()["waves_per_block"] == waves
+        out = nqs.log_psi(plan, p, xs).cpu().numpy()
+        assert np.array_equal(np.isfinite(out[:, 0]), fin)
+        e1 = np.max(np.abs(out[fin, 0] - la_ref[fin]))
+        e2 = np.max(np.abs(out[:, 1] - ph_ref))
+        print(f"{prec} h={h} waves={waves}: {e1:.3e} {e2:.3e}")
+        assert e1 <= tol and e2 <= tol
+
+
+def test_configure_rejects_bad_values(nqs, ctx):
+    terms = hamiltonian(6, 0)
+    H = nqs.Hamiltonian.from_terms(terms).upload(ctx)
+    plan = nqs.Plan(ctx, H, 1, 64, 3, 3, "fp64", max_batch=64, dedup=False, chunk_samples=40)
+    with pytest.raises(nqs.NQSError):
+        plan.configure(waves_per_block=16)          # the FP64 forward has one variant
+    with pytest.raises(nqs.NQSError):
+        plan.configure(dedup=True)                  # no dedup tables in this plan's workspace
+    with pytest.raises(nqs.NQSError):
+        plan.configure(chunk_samples=41)            # above the created chunk
+    with pytest.raises(nqs.NQSError):
+        plan.configure(chunk_samples=19)            # below half of it
+    plan.configure(chunk_samples=20)
+    assert plan.chunk_samples == 20
+
+
+def test_dedup_and_chunk_bit_identical(nqs, ctx):
+    """40 qubits: the four (dedup, chunk) choices give identical local energies."""
+    N = 20
+    n = 2 * N
+    terms = hamiltonian(N, 0)
+    H = nqs.Hamiltonian.from_terms(terms).upload(ctx)
+    xs, w = unique_with_counts(sector_samples(n, N // 2, N // 2, 300, seed=9))
+    plan = nqs.Plan(ctx, H, 2, 256, N // 2, N // 2, "bf16x3", max_batch=len(xs), dedup="auto",
+                    chunk_samples=64)
+    p = torch.from_numpy(init_params(n, 2, 256, seed=3)).cuda()
+    outs = {}
+    for dedup in (False, True):
+        for chunk in (64, 32):
+            plan.configure(dedup=dedup, chunk_samples=chunk)
+            assert plan.dedup == dedup and plan.chunk_samples == chunk
+            outs[(dedup, chunk)] = nqs.local_energy(plan, p, xs)
+    torch.cuda.synchronize()
+    assert nqs.device_status(plan) == 0
+    first = outs[(False, 64)]
+    for k, v in outs.items():
+        assert torch.equal(v, first), k
+
+
+def test_autotune_times_candidates_and_caches(nqs, ctx):
+    N = 12
+    n = 2 * N
+    terms = hamiltonian(N, 0)
+    ref = pauli.canonical_terms(terms.x_mask, terms.z_mask, terms.coeff)
+    H = nqs.Hamiltonian.from_terms(terms).upload(ctx)
+    xs, w = unique_with_counts(sector_samples(n, N // 2, N // 2, 512, seed=4))
+    plan = nqs.Plan(ctx, H, 2, 512, N // 2, N // 2, "bf16x3", max_batch=len(xs), dedup="auto",
+                    chunk_samples=128)
+    params = init_params(n, 2, 512, seed=5)
+    p = torch.from_numpy(params).cuda()
+    rep = plan.autotune(p, xs, force=True)
+    cands = rep["candidates"]
+    # 2 variants x dedup on/off x chunk {128, 64}
+    assert len(cands) == 8 and not rep["from_cache"]
+    assert rep["probe_samples"] == min(len(xs), 256)
+    assert all(c["ms"] > 0 for c in cands)
+    best = cands[rep["chosen"]]
+    assert best["ms"] == min(c["ms"] for c in cands)
+    info = plan.kernel_info()
+    assert info["tuned"] and info["waves_per_block"] == best["waves_per_block"]
+    assert plan.dedup == best["dedup"] and plan.chunk_samples == best["chunk_samples"]
+    print("autotune:", [(c["waves_per_block"], c["dedup"], c["chunk_samples"], round(c["ms"], 3))
+                        for c in cands], "chosen", rep["chosen"])
+    # a second plan of the same shape takes the cached choice without timing
+    plan2 = nqs.Plan(ctx, H, 2, 512, N // 2, N // 2, "bf16x3", max_batch=len(xs), dedup="auto",
+                     chunk_samples=128)
+    rep2 = plan2.autotune(p, xs)
+    assert rep2["from_cache"] and plan2.kernel_info()["waves_per_block"] == best["waves_per_block"]
+    # the tuned plan is still correct
+    el = nqs.local_energy(plan2, p, xs).cpu().numpy()
+    net = made.Net(n=n, n_layers=2, width=512, n_up=N // 2, n_dn=N // 2)
+    el_ref = vmc.local_energy(ref, net, params, xs[:3])
+    d = np.abs(el[:3, 0] + 1j * el[:3, 1] - el_ref)
+    print("tuned |dE_loc|:", d)
+    assert np.all(d <= 1e-3)
+
+
+def test_multi_mixed_precisions_equal_single(nqs, ctx):
+    """Instances of two precisions and two widths (three launch groups)."""
+    items = []
+    specs = [(6, 0, "fp32", 256, 2, 300), (7, 1, "bf16x3", 512, 2, 200), (8, 2, "bf16x3", 512, 2, 150),
+             (5, 3, "fp64", 128, 1, 100)]
+    keep = []
+    for N, seed, prec, h, L, B in specs:
+        n = 2 * N
+        terms = hamiltonian(N, seed)
+        H = nqs.Hamiltonian.from_terms(terms).upload(ctx)
+        xs, w = unique_with_counts(sector_samples(n, N // 2, N // 2, B, seed=seed + 10))
+        plan = nqs.Plan(ctx, H, L, h, N // 2, N // 2, prec, max_batch=len(xs), chunk_samples=max(8, len(xs) // 3))
+        dev = ctx.device
+        it = dict(plan=plan, params=torch.from_numpy(init_params(n, L, h, seed=seed)).to(dev),
+                  samples=torch.from_numpy(xs.view(np.int64)).to(dev), weights=torch.from_numpy(w).to(dev),
+                  eloc=torch.empty((len(xs), 2), dtype=torch.float64, device=dev),
+                  energy=torch.empty(3, dtype=torch.float64, device=dev),
+                  grad=torch.empty(plan.n_params, dtype=torch.float64, device=dev))
+        items.append(it)
+        keep.append(H)
+    nqs.energy_grad_multi(items)
+    torch.cuda.synchronize()
+    for it in items:
+        e1, g1, l1 = nqs.energy_grad(it["plan"], it["params"], it["samples"], it["weights"])
+        assert torch.equal(l1, it["eloc"]) and torch.equal(g1, it["grad"]) and torch.equal(e1, it["energy"])
+        assert nqs.device_status(it["plan"]) == 0

@@ -60,7 +60,7 @@ def _closed_conn(N, nu, nd):
 @pytest.mark.parametrize("name,prec,tol", [
     # per-sample |dE_loc| bars: FP32 / split-BF16 carry ~1e-6 relative error in
     # log psi, the local energy sums ~1e4 terms of size ~1e-2 with random signs
-    ("c3", "bf16x3", 2e-3), ("c3", "fp32", 2e-3), ("c3", "bf16", 0.5)])
+    ("c3", "bf16w", 2e-3), ("c3", "bf16x3", 2e-3), ("c3", "fp32", 2e-3), ("c3", "bf16", 0.5)])
 def test_40_qubits_full_batch_sampled(nqs, ctx, name, prec, tol):
     terms, params, xs, w, cfg, plan, energy, grad, eloc = _run(nqs, ctx, name, prec)
     N = cfg["N"]
@@ -83,7 +83,7 @@ def test_four_instances_one_call(nqs, ctx):
     for name, B in (("c5a", 512), ("c5b", 256), ("c5c", 128), ("c5d", 64)):
         terms, params, xs, w, cfg = config_inputs(name, batch=B)
         H = nqs.Hamiltonian.from_terms(terms).upload(ctx)
-        plan = nqs.Plan(ctx, H, cfg["L"], cfg["h"], cfg["n_up"], cfg["n_dn"], "bf16x3",
+        plan = nqs.Plan(ctx, H, cfg["L"], cfg["h"], cfg["n_up"], cfg["n_dn"], cfg["precision"],
                         max_batch=len(xs), dedup=cfg["dedup"])
         plans.append((plan, H))
         dev = ctx.device
@@ -95,10 +95,7 @@ def test_four_instances_one_call(nqs, ctx):
                   grad=torch.empty(plan.n_params, dtype=torch.float64, device=dev))
         items.append(it)
         refs.append((terms, params, xs, w, cfg))
-    need = max(it["plan"].workspace_size(it["samples"].numel()) for it in items)
-    raw = torch.empty(need + 256, dtype=torch.uint8, device=ctx.device)
-    import ctypes as C
-    ws = (C.c_void_p((raw.data_ptr() + 255) & ~255), need)
+    ws = nqs.multi_workspace(items)
     nqs.energy_grad_multi(items, ws)
     torch.cuda.synchronize()
     for it, (terms, params, xs, w, cfg) in zip(items, refs):
