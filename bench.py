@@ -42,6 +42,36 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("paper_2208_05637_amd/csrc/kernels_forward.hip", "paper_2208_05637_amd/csrc/nqs_internal.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, prec, waves):
+    """HBM bytes per connected-configuration forward launch from the committed
+    counter summary of this workload, or None when there is none or it was
+    taken on another kernel source or workgroup shape."""
+    path = os.path.join(ROOT, "profiles", f"fused_forward_{workload}_{prec}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("|"):
+                k, v = line.split(":", 1)
+                kv[k.strip().strip("-* `")] = v.strip().strip("` ")
+    try:
+        if kv.get("kernel_source_sha256") != kernel_source_hash() or int(kv.get("waves_per_block", -1)) != waves:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,7 +246,7 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": measured_traffic(args.workload, prec, kinfo["waves_per_block"]),
             "mfma_issued_tflops": issued,
             "mfma_issued_frac": issued / peak,
             "ms_per_launch": fwd_ms_launch,
