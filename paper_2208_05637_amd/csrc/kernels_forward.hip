@@ -80,16 +80,16 @@ constexpr int variant_waves() {
 }
 
 // Head k slices (one LDS staging plane each) when the head has fewer
-// (block, m-block) tiles than waves.
-// At most 4 slices, and no more than the planes that fit in 128 KB.
+// (block, m-block) tiles than waves: a power of two, at most 8, and no more
+// than the planes that fit in 128 KB.
+constexpr int pow2_floor(int v) { return v >= 8 ? 8 : v >= 4 ? 4 : v >= 2 ? 2 : 1; }
 template <int P, int H, int NW>
 constexpr int head_ksplit_max() {
   constexpr int M = rows_per_block<P, H>();
   constexpr int MB = M / Tr<P>::TB;
   constexpr int SP = ((68 + Tr<P>::TB - 1) / Tr<P>::TB) * Tr<P>::TB + 1;
-  constexpr int fit = (131072 / (M * SP * (int)sizeof(typename Tr<P>::S))) > 0
-                          ? 131072 / (M * SP * (int)sizeof(typename Tr<P>::S)) : 1;
-  constexpr int want = MB >= NW ? 1 : (NW / MB < 4 ? NW / MB : 4);
+  constexpr int fit = pow2_floor(131072 / (M * SP * (int)sizeof(typename Tr<P>::S)));
+  constexpr int want = MB >= NW ? 1 : pow2_floor(NW / MB);
   return want < fit ? want : fit;
 }
 
@@ -464,12 +464,24 @@ __device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict_
   wbuf.plane_bytes = (int)(g.nfrag * 1024);
   wbuf.voff = lane * 16;
 
-  for (int t = tid; t < M; t += NT) {
-    const long long row = row0 + t;
-    uint64_t x = xs[row < count ? row : row0];
-    uint64_t y = 0;
-    for (int p = 0; p < g.n; ++p) y |= ((x >> g.order[p]) & 1ull) << p;
-    ylds[t] = y;
+  static_assert(M <= NT, "one configuration per thread");
+  if (tid < M) {
+    const long long row = row0 + tid;
+    const uint64_t x = xs[row < count ? row : row0];
+    // bits into sampling order: y bit p = x bit order[p]
+    uint64_t y;
+    if (g.order_kind == 2) {
+      y = __builtin_bitreverse64(x) >> (64 - g.n);
+    } else if (g.order_kind == 1) {
+      y = x;
+    } else {
+      // unrolled with constant indices, so the order bytes are scalar loads
+      y = 0;
+#pragma unroll
+      for (int p = 0; p < 64; ++p)
+        if (p < g.n) y |= ((x >> g.order[p]) & 1ull) << p;
+    }
+    ylds[tid] = y;
   }
   for (int t = tid; t < H; t += NT) blds[t] = biases[t];
   __syncthreads();
@@ -621,16 +633,18 @@ __device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict_
     };
     double sum = 0.0;
     int bad = 0;
+    const uint64_t sp0 = g.spin_pos[0], sp1 = g.spin_pos[1];
     for (int t = sub; t < g.n; t += TPR) {
       const S o = head_out(t);
-      const int sp = g.order[t] & 1;
+      const int sp = (int)((sp1 >> t) & 1ull);   // spin of the qubit at position t
+      const uint64_t spm = sp ? sp1 : sp0;
       const int bit = (int)((y >> t) & 1ull);
       bool fr = true;
       if (constrained) {
         const uint64_t low = t == 0 ? 0ull : (~0ull >> (64 - t));
         const uint64_t high = t >= 63 ? 0ull : (~0ull << (t + 1));
-        const int c = __popcll(y & g.spin_pos[sp] & low);
-        const int rem = __popcll(g.spin_pos[sp] & high);
+        const int c = __popcll(y & spm & low);
+        const int rem = __popcll(spm & high);
         const int ns = sp ? g.n_dn : g.n_up;
         const bool f0 = c >= ns, f1 = c + rem < ns;
         bad |= (f0 && bit) || (f1 && !bit);

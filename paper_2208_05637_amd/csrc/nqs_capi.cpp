@@ -373,11 +373,15 @@ static nqs_status build_geom(const nqs_net_desc* nd, Geom& g) {
     if (order[t] < 0 || order[t] >= n || seen[order[t]]++)
       return fail(NQS_ERR_INVALID_ARGUMENT, "order is not a permutation of the qubits");
   }
+  bool ident = true, rev = true;
   for (int t = 0; t < n; ++t) {
     g.order[t] = (int8_t)order[t];
     g.pos[order[t]] = (int8_t)t;
     g.spin_pos[order[t] & 1] |= 1ull << t;
+    ident = ident && order[t] == t;
+    rev = rev && order[t] == n - 1 - t;
   }
+  g.order_kind = ident ? 1 : (rev ? 2 : 0);
   g.TB = g.prec == P_F64 ? 16 : 32;
   g.KSTEP = (g.prec == P_BF16 || g.prec == P_BF16X3 || g.prec == P_BF16W) ? 16 : 8;
   g.NB = h / g.TB;

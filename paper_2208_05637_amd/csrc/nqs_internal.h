@@ -29,6 +29,7 @@ struct Geom {
   int q, r;                 // h = q (n-1) + r units per degree class (see class_of)
   int planes;               // 2 for split bf16 (hi, lo), else 1
   int acc_bytes;            // 8 for the FP64 path, else 4
+  int order_kind;           // 1: order is the identity, 2: the reverse (n-1, ..., 0), 0: other
   uint64_t spin_pos[2];     // positions whose qubit has spin 0 (even) / 1 (odd)
   int8_t order[64];         // position -> qubit
   int8_t pos[64];           // qubit -> position

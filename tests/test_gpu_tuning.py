@@ -165,3 +165,27 @@ def test_multi_mixed_precisions_equal_single(nqs, ctx):
         e1, g1, l1 = nqs.energy_grad(it["plan"], it["params"], it["samples"], it["weights"])
         assert torch.equal(l1, it["eloc"]) and torch.equal(g1, it["grad"]) and torch.equal(e1, it["energy"])
         assert nqs.device_status(it["plan"]) == 0
+
+
+@pytest.mark.parametrize("N,B,order_seed", [(22, 24, None), (32, 12, None), (20, 24, 5)])
+def test_forward_launch_grouping_invariance(nqs, ctx, N, B, order_seed):
+    """The connected-configuration rows give bit-identical log psi whether one
+    launch evaluates all of them or several launches evaluate slices (every
+    row's arithmetic is independent of the others and of the grid)."""
+    n = 2 * N
+    terms = hamiltonian(N, 3)
+    H = nqs.Hamiltonian.from_terms(terms).upload(ctx)
+    order = None if order_seed is None else np.random.default_rng(order_seed).permutation(n)
+    xs = sector_samples(n, N // 2, N // 2, B, seed=8)
+    for prec, h in (("bf16w", 512), ("bf16x3", 512), ("fp32", 256)):
+        plan = nqs.Plan(ctx, H, 3, h, N // 2, N // 2, prec, max_batch=B, order=order)
+        p = torch.from_numpy(init_params(n, 3, h, seed=2, dtype="bf16" if prec == "bf16w" else "fp32")).cuda()
+        con = nqs.connected(plan, xs)
+        ne = int(con["n_entries"].item())
+        ent = con["x"][:ne].contiguous()
+        M = plan.kernel_info()["rows_per_block"]
+        whole = nqs.log_psi(plan, p, ent)
+        step = 37 * M + 5          # ragged slices: tile boundaries shift between launches
+        parts = torch.cat([nqs.log_psi(plan, p, ent[i:i + step]) for i in range(0, ne, step)])
+        torch.cuda.synchronize()
+        assert torch.equal(whole, parts), (prec, N)
