@@ -105,34 +105,123 @@ void launch_count(const HamDev& H, const uint64_t* x, long long S, int R, int gp
   else hipLaunchKernelGGL(count_kernel<false>, grid, dim3(256), 0, s, H, x, S, R, gper, cnt);
 }
 
-// Exclusive scan of n counts into off[0..n] (off[n] = total), one workgroup.
-__global__ __launch_bounds__(1024) void scan_kernel(const int* __restrict__ cnt, long long n,
-                                                    long long* __restrict__ off) {
-  __shared__ long long part[1024];
-  const int t = threadIdx.x;
-  const long long per = (n + 1023) / 1024;
-  const long long a = t * per;
-  const long long b = a + per < n ? a + per : n;
-  long long s = 0;
-  for (long long i = a; i < b; ++i) s += cnt[i];
-  part[t] = s;
+// Exclusive scan of n counts into off[0..n] (off[n] = total) in three
+// passes over tiles of kScanTile counts: tile sums, an exclusive scan of the
+// tile sums (one workgroup), then each tile's local scan plus its offset.
+// Loads and stores are coalesced; tmp holds scan_tiles(n) + 1 values.
+constexpr int kScanThreads = 1024, kScanItems = 4, kScanTile = kScanThreads * kScanItems;
+
+long long scan_tiles(long long n) { return (n + kScanTile - 1) / kScanTile; }
+
+__device__ __forceinline__ long long block_sum_1024(long long v, long long* sh) {
+  // sum over the 1024 threads of the block, result in every thread
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  if (lane == 0) sh[w] = v;
   __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {
-    long long v = t >= d ? part[t - d] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  long long run = t ? part[t - 1] : 0;
-  for (long long i = a; i < b; ++i) {
-    off[i] = run;
-    run += cnt[i];
-  }
-  if (t == 1023) off[n] = part[1023];
+  long long tot = 0;
+  for (int k = 0; k < kScanThreads / 64; ++k) tot += sh[k];
+  __syncthreads();
+  return tot;
 }
 
-void launch_scan(const int* cnt, long long n, long long* off, hipStream_t s) {
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, cnt, n, off);
+__global__ __launch_bounds__(kScanThreads) void scan_tile_sums(const int* __restrict__ cnt, long long n,
+                                                               long long* __restrict__ tmp) {
+  __shared__ long long sh[kScanThreads / 64];
+  const long long base = (long long)blockIdx.x * kScanTile;
+  long long v = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const long long i = base + k * kScanThreads + threadIdx.x;
+    if (i < n) v += cnt[i];
+  }
+  const long long tot = block_sum_1024(v, sh);
+  if (threadIdx.x == 0) tmp[blockIdx.x] = tot;
+}
+
+// Exclusive scan of m tile sums in place (tmp[m] = total), one workgroup.
+__global__ __launch_bounds__(kScanThreads) void scan_tile_offsets(long long* __restrict__ tmp, long long m) {
+  __shared__ long long part[kScanThreads];
+  const int t = threadIdx.x;
+  long long carry = 0;
+  for (long long c0 = 0; c0 < m; c0 += kScanThreads) {
+    const long long i = c0 + t;
+    const long long v = i < m ? tmp[i] : 0;
+    part[t] = v;
+    __syncthreads();
+    for (int d = 1; d < kScanThreads; d <<= 1) {
+      const long long u = t >= d ? part[t - d] : 0;
+      __syncthreads();
+      part[t] += u;
+      __syncthreads();
+    }
+    if (i < m) tmp[i] = carry + part[t] - v;
+    carry += part[kScanThreads - 1];
+    __syncthreads();
+  }
+  if (t == 0) tmp[m] = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_tile_apply(const int* __restrict__ cnt, long long n,
+                                                                const long long* __restrict__ tmp,
+                                                                long long* __restrict__ off) {
+  __shared__ int vals[kScanTile];
+  __shared__ long long part[kScanThreads];
+  const int t = threadIdx.x;
+  const long long base = (long long)blockIdx.x * kScanTile;
+  // coalesced load of the tile, then each thread scans kScanItems consecutive counts
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const long long i = base + k * kScanThreads + t;
+    vals[k * kScanThreads + t] = i < n ? cnt[i] : 0;
+  }
+  __syncthreads();
+  long long loc[kScanItems];
+  long long run = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    loc[k] = run;
+    run += vals[t * kScanItems + k];
+  }
+  part[t] = run;
+  __syncthreads();
+  for (int d = 1; d < kScanThreads; d <<= 1) {
+    const long long u = t >= d ? part[t - d] : 0;
+    __syncthreads();
+    part[t] += u;
+    __syncthreads();
+  }
+  const long long pre = tmp[blockIdx.x] + part[t] - run;
+  __syncthreads();
+  // back through LDS so the stores are coalesced too
+  long long* outv = (long long*)vals;   // kScanTile ints reused as kScanTile / 2 longs: two halves
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      const int j = t * kScanItems + k;
+      if ((j >> 11) == half) outv[j & 2047] = pre + loc[k];
+    }
+    __syncthreads();
+    for (int j = t; j < 2048; j += kScanThreads) {
+      const long long i = base + half * 2048 + j;
+      if (i < n) off[i] = outv[j];
+    }
+    __syncthreads();
+  }
+  if (blockIdx.x == gridDim.x - 1 && t == 0) off[n] = tmp[gridDim.x];
+}
+
+void launch_scan(const int* cnt, long long n, long long* off, long long* tmp, hipStream_t s) {
+  const long long m = scan_tiles(n);
+  if (m == 0) {
+    launch_fill_u64(off, 0ull, 1, s);
+    return;
+  }
+  hipLaunchKernelGGL(scan_tile_sums, dim3((unsigned)m), dim3(kScanThreads), 0, s, cnt, n, tmp);
+  hipLaunchKernelGGL(scan_tile_offsets, dim3(1), dim3(kScanThreads), 0, s, tmp, m);
+  hipLaunchKernelGGL(scan_tile_apply, dim3((unsigned)m), dim3(kScanThreads), 0, s, cnt, n,
+                     (const long long*)tmp, off);
 }
 
 template <bool IMAG>
@@ -355,24 +444,34 @@ struct Comp {
   __device__ double value() const { return s + c; }
 };
 
-// One block per sample: E_loc(x_i) = diag_i + sum_e h_e exp(lp(x'_e) - lp(x_i)).
-__global__ __launch_bounds__(256) void reduce_kernel(long long S, int R, const long long* __restrict__ off,
-                                                     long long cap, const double* __restrict__ diag,
-                                                     const double* __restrict__ he, int hstride,
-                                                     const int* __restrict__ eu,
-                                                     const double2* __restrict__ lpe,
-                                                     const double2* __restrict__ lps,
-                                                     double* __restrict__ eloc, unsigned* err) {
+// E_loc(x_i) = diag_i + sum_e h_e exp(lp(x'_e) - lp(x_i)).  Each sample's
+// entries are cut into kReduceSlices equal slices, one workgroup each
+// (enough workgroups to keep every CU streaming); a slice is summed with
+// per-thread compensation and a fixed tree, and the slices are then added to
+// the diagonal in slice order.  The cut depends only on the sample's own
+// entry range, so the result does not depend on scheduling or chunking.
+constexpr int kReduceSlices = 8;
+
+__global__ __launch_bounds__(256) void reduce_part_kernel(long long S, int R, const long long* __restrict__ off,
+                                                          long long cap, const double* __restrict__ he,
+                                                          int hstride, const int* __restrict__ eu,
+                                                          const double2* __restrict__ lpe,
+                                                          const double2* __restrict__ lps,
+                                                          double* __restrict__ partials) {
   __shared__ double red[4][256];
-  const long long i = blockIdx.x;
+  const long long i = blockIdx.x / kReduceSlices;
+  const int part = (int)(blockIdx.x % kReduceSlices);
   if (i >= S) return;
   long long a = off[i * R];
   long long b = off[(i + 1) * R];
   if (a > cap) a = cap;
   if (b > cap) b = cap;
+  const long long per = (b - a + kReduceSlices - 1) / kReduceSlices;
+  const long long pa = a + part * per;
+  const long long pb = pa + per < b ? pa + per : b;
   const double2 ls = lps[i];
   Comp cr{0.0, 0.0}, ci{0.0, 0.0};
-  for (long long e = a + threadIdx.x; e < b; e += 256) {
+  for (long long e = pa + threadIdx.x; e < pb; e += 256) {
     const int u = eu ? eu[e] : (int)0;
     const double2 lp = eu ? (u >= 0 ? lpe[u] : make_double2(-INFINITY, 0.0)) : lpe[e];
     if (lp.x == -INFINITY) continue;
@@ -402,27 +501,40 @@ __global__ __launch_bounds__(256) void reduce_kernel(long long S, int R, const l
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    Comp tr{diag[2 * i], 0.0}, ti{diag[2 * i + 1], 0.0};
-    tr.merge(Comp{red[0][0], red[1][0]});
-    ti.merge(Comp{red[2][0], red[3][0]});
-    if (ls.x == -INFINITY) {
-      atomicOr(err, kErrZeroAmp);
-      eloc[2 * i] = NAN;
-      eloc[2 * i + 1] = NAN;
-    } else {
-      eloc[2 * i] = tr.value();
-      eloc[2 * i + 1] = ti.value();
-    }
+  if (threadIdx.x < 4) partials[(i * kReduceSlices + part) * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void reduce_combine_kernel(long long S, const double* __restrict__ diag,
+                                      const double2* __restrict__ lps, const double* __restrict__ partials,
+                                      double* __restrict__ eloc, unsigned* err) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S) return;
+  Comp tr{diag[2 * i], 0.0}, ti{diag[2 * i + 1], 0.0};
+  for (int k = 0; k < kReduceSlices; ++k) {
+    const double* q = partials + (i * kReduceSlices + k) * 4;
+    tr.merge(Comp{q[0], q[1]});
+    ti.merge(Comp{q[2], q[3]});
+  }
+  if (lps[i].x == -INFINITY) {
+    atomicOr(err, kErrZeroAmp);
+    eloc[2 * i] = NAN;
+    eloc[2 * i + 1] = NAN;
+  } else {
+    eloc[2 * i] = tr.value();
+    eloc[2 * i + 1] = ti.value();
   }
 }
 
+long long reduce_partials_elems(long long S) { return S * kReduceSlices * 4; }
+
 void launch_reduce(long long S, int R, const long long* off, long long cap, const double* diag,
-                     const double* he, int hstride, const int* eu, const double* lpe,
-                     const double* lps, double* eloc, unsigned* err, hipStream_t s) {
+                   const double* he, int hstride, const int* eu, const double* lpe,
+                   const double* lps, double* eloc, double* partials, unsigned* err, hipStream_t s) {
   if (S <= 0) return;
-  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)S), dim3(256), 0, s, S, R, off, cap, diag, he,
-                     hstride, eu, (const double2*)lpe, (const double2*)lps, eloc, err);
+  hipLaunchKernelGGL(reduce_part_kernel, dim3((unsigned)(S * kReduceSlices)), dim3(256), 0, s, S, R, off, cap,
+                     he, hstride, eu, (const double2*)lpe, (const double2*)lps, partials);
+  hipLaunchKernelGGL(reduce_combine_kernel, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, s, S, diag,
+                     (const double2*)lps, (const double*)partials, eloc, err);
 }
 
 // Weighted energy: W = sum w, E = sum w Re(l) / W, I = sum w Im(l) / W.

@@ -112,8 +112,8 @@ struct nqs_plan {
 constexpr int kProfSlots = 8192;
 
 struct WsLayout {
-  size_t err, prof, geom, packed, wm, lps, eloc, energy, cnt, off, diag, xe, he, lpe, hkeys, hslot, eu, xu,
-      nu, bscratch, total;
+  size_t err, prof, geom, packed, wm, lps, eloc, energy, cnt, off, stmp, rpart, diag, xe, he, lpe, hkeys, hslot,
+      eu, xu, nu, bscratch, total;
 };
 
 // Enumeration grid for chunks of S samples: R ranges of gper flip groups.
@@ -140,6 +140,8 @@ static WsLayout layout(const nqs_plan* p, int64_t B) {
   L.energy = take(3 * 8);
   L.cnt = take((size_t)p->SRcap * 4);
   L.off = take(((size_t)p->SRcap + 1) * 8);
+  L.stmp = take(((size_t)scan_tiles(p->SRcap) + 1) * 8);
+  L.rpart = take((size_t)reduce_partials_elems(std::max<int64_t>(p->S0, 1)) * 8);
   L.diag = take((size_t)p->S0 * 16);
   L.xe = take((size_t)p->EC * 8);
   L.he = take((size_t)p->EC * 8 * hs);
@@ -668,7 +670,7 @@ static ChunkFwd enum_chunk(nqs_plan* p, const uint64_t* x, int64_t c0, int64_t S
   uint64_t* xe = at<uint64_t>(ws, L.xe);
   launch_diag(H, xc, Sc, at<double>(ws, L.diag), s);
   launch_count(H, xc, Sc, p->R, p->gper, cnt, s);
-  launch_scan(cnt, Sc * p->R, off, s);
+  launch_scan(cnt, Sc * p->R, off, at<long long>(ws, L.stmp), s);
   launch_write(H, xc, Sc, p->R, p->gper, off, p->EC, xe, at<double>(ws, L.he), nullptr, hs, err, s);
   const long long* d_total = off + Sc * p->R;
   const int64_t bound = std::min<int64_t>(Sc * p->Emax, p->EC);
@@ -687,7 +689,7 @@ static void reduce_chunk(nqs_plan* p, int64_t c0, int64_t Sc, void* ws, const Ws
   const int hs = p->ham->has_imag ? 2 : 1;
   launch_reduce(Sc, p->R, at<long long>(ws, L.off), p->EC, at<double>(ws, L.diag), at<double>(ws, L.he), hs,
                 p->dedup ? at<int>(ws, L.eu) : nullptr, at<double>(ws, L.lpe), at<double>(ws, L.lps) + 2 * c0,
-                eloc + 2 * c0, at<unsigned>(ws, L.err), p->ctx->stream);
+                eloc + 2 * c0, at<double>(ws, L.rpart), at<unsigned>(ws, L.err), p->ctx->stream);
 }
 
 // local energies of B samples into eloc; lps (sample log psi) computed first.
@@ -1064,7 +1066,7 @@ nqs_status nqs_connected(nqs_plan* p, const uint64_t* x, int64_t B, int64_t capa
   long long* off = at<long long>(ws, L.off);
   launch_diag(H, x, B, d_diag, s);
   launch_count(H, x, B, p->R, p->gper, cnt, s);
-  launch_scan(cnt, B * p->R, off, s);
+  launch_scan(cnt, B * p->R, off, at<long long>(ws, L.stmp), s);
   launch_write(H, x, B, p->R, p->gper, off, capacity, d_ex, d_eh, d_esample, 2, err, s);
   launch_copy_i64(off + B * p->R, (long long*)d_n_entries, s);
   if (p->dedup) {
@@ -1091,7 +1093,7 @@ nqs_status nqs_reduce_table(nqs_plan* p, int64_t B, const double* lps, const dou
   if (B == 0) return launch_check("reduce");
   long long* off = at<long long>(ws, L.off);
   launch_seg_offsets(esample, n_entries, B, off, s);
-  launch_reduce(B, 1, off, n_entries, diag, eh, 2, nullptr, lpe, lps, eloc, err, s);
+  launch_reduce(B, 1, off, n_entries, diag, eh, 2, nullptr, lpe, lps, eloc, at<double>(ws, L.rpart), err, s);
   return launch_check("reduce");
 }
 

@@ -117,7 +117,9 @@ int forward_variant_waves(int prec, int h, int variant);
 void launch_diag(const HamDev& H, const uint64_t* x, long long S, double* diag, hipStream_t s);
 void launch_count(const HamDev& H, const uint64_t* x, long long S, int R, int gper, int* cnt,
                   hipStream_t s);
-void launch_scan(const int* cnt, long long n, long long* off, hipStream_t s);
+// exclusive scan; tmp holds scan_tiles(n) + 1 values
+long long scan_tiles(long long n);
+void launch_scan(const int* cnt, long long n, long long* off, long long* tmp, hipStream_t s);
 void launch_write(const HamDev& H, const uint64_t* x, long long S, int R, int gper,
                   const long long* off, long long cap, uint64_t* xe, double* he, int* esample,
                   int hstride, unsigned* err, hipStream_t s);
@@ -126,9 +128,11 @@ void launch_dedup(const uint64_t* xe, const long long* d_count, long long cap, u
                   int* hslot_id, long long HT, int* eu, uint64_t* xu, long long* d_nu,
                   unsigned* err, hipStream_t s);
 
+// partials holds reduce_partials_elems(S) doubles
+long long reduce_partials_elems(long long S);
 void launch_reduce(long long S, int R, const long long* off, long long cap, const double* diag,
                    const double* he, int hstride, const int* eu, const double* lpe,
-                   const double* lps, double* eloc, unsigned* err, hipStream_t s);
+                   const double* lps, double* eloc, double* partials, unsigned* err, hipStream_t s);
 void launch_energy(const double* eloc, const double* w, long long B, double* energy,
                    unsigned* err, hipStream_t s);
 
