@@ -330,44 +330,58 @@ constexpr bool act_prefetch() {
   return acc * NBW * MBW + 8 * PLW * NBW + 8 * PL * MBW + 40 + 4 * MBW <= 2048 / NW;
 }
 
-template <int P, int NBW, int MBW, int NW, bool AX, class ActFn>
-__device__ __forceinline__ void kloop(typename Tr<P>::Acc (&acc)[NBW][MBW], const WBuf& wbuf,
-                                      const int (&fragi)[NBW], const int (&ksi)[NBW], int ks0,
-                                      ActFn act) {
-  constexpr int PL = Tr<P>::PL, PLW = Tr<P>::PLW;
-  uint4 wa[NBW][PLW], wb[NBW][PLW];
+// The first two k steps' weight fragments of a layer, requested ahead of
+// the k loop (before the barrier that precedes the layer, so their L2
+// latency overlaps the barrier wait).  Loads are clamped into each block's
+// range (a block without fragments reads a neighbour's, never used).
+template <int P, int NBW>
+struct WPre {
+  uint4 wa[NBW][Tr<P>::PLW], wb[NBW][Tr<P>::PLW];
   int kend[NBW], wbase[NBW];
+};
+
+template <int P, int NBW>
+__device__ __forceinline__ void kloop_pre(WPre<P, NBW>& pre, const WBuf& wbuf, const int (&fragi)[NBW],
+                                          const int (&ksi)[NBW]) {
+  constexpr int PLW = Tr<P>::PLW;
 #pragma unroll
   for (int i = 0; i < NBW; ++i) {
-    kend[i] = __builtin_amdgcn_readfirstlane(ksi[i]);
-    wbase[i] = __builtin_amdgcn_readfirstlane(fragi[i] * 1024);
+    pre.kend[i] = __builtin_amdgcn_readfirstlane(ksi[i]);
+    pre.wbase[i] = __builtin_amdgcn_readfirstlane(fragi[i] * 1024);
   }
-  ks0 = __builtin_amdgcn_readfirstlane(ks0);
-  // every block has at least two k steps and the extents ascend, so after
-  // this test phase 0 (all blocks active) is non-empty
-  if (kend[NBW - 1] <= ks0 || kend[0] <= ks0) return;
   // same issue order as the loop body (all of wa, then all of wb) so the
   // outstanding-load state is identical on loop entry and on the back edge
 #pragma unroll
   for (int i = 0; i < NBW; ++i) {
-    const int k0 = max(0, ks0 < kend[i] ? ks0 : kend[i] - 1);
-    wa[i][0] = wload(wbuf, wbase[i] + k0 * 1024);
-    if constexpr (PLW == 2) wa[i][1] = wload(wbuf, wbase[i] + k0 * 1024 + wbuf.plane_bytes);
+    const int k0 = max(0, 0 < pre.kend[i] ? 0 : pre.kend[i] - 1);
+    pre.wa[i][0] = wload(wbuf, pre.wbase[i] + k0 * 1024);
+    if constexpr (PLW == 2) pre.wa[i][1] = wload(wbuf, pre.wbase[i] + k0 * 1024 + wbuf.plane_bytes);
   }
 #pragma unroll
   for (int i = 0; i < NBW; ++i) {
-    const int k1 = max(0, ks0 + 1 < kend[i] ? ks0 + 1 : kend[i] - 1);
-    wb[i][0] = wload(wbuf, wbase[i] + k1 * 1024);
-    if constexpr (PLW == 2) wb[i][1] = wload(wbuf, wbase[i] + k1 * 1024 + wbuf.plane_bytes);
+    const int k1 = max(0, 1 < pre.kend[i] ? 1 : pre.kend[i] - 1);
+    pre.wb[i][0] = wload(wbuf, pre.wbase[i] + k1 * 1024);
+    if constexpr (PLW == 2) pre.wb[i][1] = wload(wbuf, pre.wbase[i] + k1 * 1024 + wbuf.plane_bytes);
   }
+}
+
+// K loop of one layer from k step 0, its first fragments already requested
+// by kloop_pre.
+template <int P, int NBW, int MBW, int NW, bool AX, class ActFn>
+__device__ __forceinline__ void kloop(typename Tr<P>::Acc (&acc)[NBW][MBW], const WBuf& wbuf,
+                                      WPre<P, NBW>& pre, ActFn act) {
+  constexpr int PL = Tr<P>::PL;
+  // every block has at least two k steps and the extents ascend, so after
+  // this test phase 0 (all blocks active) is non-empty
+  if (pre.kend[NBW - 1] <= 0 || pre.kend[0] <= 0) return;
   constexpr bool PF = act_prefetch<P, NBW, MBW, NW>();
   uint4 afa[MBW][PL], afb[MBW][PL];
   if constexpr (PF) {
 #pragma unroll
-    for (int j = 0; j < MBW; ++j) act(j, ks0, afa[j]);
+    for (int j = 0; j < MBW; ++j) act(j, 0, afa[j]);
   }
   __builtin_amdgcn_sched_barrier(0);
-  kphase<P, NBW, MBW, 0, AX, PF>(acc, wbuf, wbase, kend, ks0, wa, wb, afa, afb, act);
+  kphase<P, NBW, MBW, 0, AX, PF>(acc, wbuf, pre.wbase, pre.kend, 0, pre.wa, pre.wb, afa, afb, act);
 }
 
 // Head k loop for one (block, m-block) tile over [k0, k1) (multiples of 8):
@@ -465,27 +479,6 @@ __device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict_
   wbuf.voff = lane * 16;
 
   static_assert(M <= NT, "one configuration per thread");
-  if (tid < M) {
-    const long long row = row0 + tid;
-    const uint64_t x = xs[row < count ? row : row0];
-    // bits into sampling order: y bit p = x bit order[p]
-    uint64_t y;
-    if (g.order_kind == 2) {
-      y = __builtin_bitreverse64(x) >> (64 - g.n);
-    } else if (g.order_kind == 1) {
-      y = x;
-    } else {
-      // unrolled with constant indices, so the order bytes are scalar loads
-      y = 0;
-#pragma unroll
-      for (int p = 0; p < 64; ++p)
-        if (p < g.n) y |= ((x >> g.order[p]) & 1ull) << p;
-    }
-    ylds[tid] = y;
-  }
-  for (int t = tid; t < H; t += NT) blds[t] = biases[t];
-  __syncthreads();
-
   // n-blocks of this wave.  The masked k extent grows with the block index,
   // so blocks are dealt in mirrored pairs (p, NB-1-p): every wave then runs
   // the same number of k steps and all waves of a SIMD stay busy until the
@@ -509,6 +502,49 @@ __device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict_
 #pragma unroll
   for (int j = 0; j < MBW; ++j) mbl[j] = j * WM + wm;
 
+  // fragments of a layer's first k steps: 1 = layer 1, 2..L = hidden layers.
+  // They are requested before the barrier that ends the previous layer,
+  // except where four accumulator tiles per wave leave no registers for them
+  // during the epilogue.
+  constexpr bool EARLY = !(P == P_BF16 && MBW >= 4);
+  WPre<P, NBW> pre;
+  auto preload = [&](int l) {
+    int ksi[NBW], fragi[NBW];
+    const int lbase = l == 1 ? 0 : (int)(g.frag_h + (long long)(l - 2) * g.offh[NB]);
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) {
+      ksi[i] = l == 1 ? g.ks1[nbl[i]] : g.ksh[nbl[i]];
+      fragi[i] = l == 1 ? g.off1[nbl[i]] : lbase + g.offh[nbl[i]];
+    }
+    kloop_pre<P, NBW>(pre, wbuf, fragi, ksi);
+  };
+
+  uint64_t x = 0;
+  if (tid < M) {
+    const long long row = row0 + tid;
+    x = xs[row < count ? row : row0];
+  }
+  if (EARLY) preload(1);   // overlaps the configuration load
+  if (tid < M) {
+    // bits into sampling order: y bit p = x bit order[p]
+    uint64_t y;
+    if (g.order_kind == 2) {
+      y = __builtin_bitreverse64(x) >> (64 - g.n);
+    } else if (g.order_kind == 1) {
+      y = x;
+    } else {
+      // unrolled with constant indices, so the order bytes are scalar loads
+      y = 0;
+#pragma unroll
+      for (int p = 0; p < 64; ++p)
+        if (p < g.n) y |= ((x >> g.order[p]) & 1ull) << p;
+    }
+    ylds[tid] = y;
+  }
+  for (int t = tid; t < H; t += NT) blds[t] = biases[t];
+  __syncthreads();
+  if (!EARLY) preload(1);
+
   Acc acc[NBW][MBW];
   auto lds_act = [&](int j, int ks, uint4 (&f)[PL]) {
     const uint4* a = (const uint4*)act + ((long)(ks * MB + mbl[j])) * 64 + lane;
@@ -522,20 +558,16 @@ __device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict_
     for (int i = 0; i < NBW; ++i)
 #pragma unroll
       for (int j = 0; j < MBW; ++j) acc[i][j] = Acc{};
-    int ksi[NBW], fragi[NBW];
-#pragma unroll
-    for (int i = 0; i < NBW; ++i) {
-      ksi[i] = g.ks1[nbl[i]];
-      fragi[i] = g.off1[nbl[i]];
-    }
     // the +-1 inputs are exact in BF16
-    kloop<P, NBW, MBW, Sh::NW, true>(acc, wbuf, fragi, ksi, 0,
-                             [&](int j, int ks, uint4 (&f)[PL]) { input_frag<P>(ylds, mbl[j], ks, lane, g.n, f); });
+    kloop<P, NBW, MBW, Sh::NW, true>(acc, wbuf, pre,
+                                     [&](int j, int ks, uint4 (&f)[PL]) { input_frag<P>(ylds, mbl[j], ks, lane, g.n, f); });
 #pragma unroll
     for (int i = 0; i < NBW; ++i)
 #pragma unroll
       for (int j = 0; j < MBW; ++j) store_act<P, MB>(act, acc[i][j], blds, nbl[i], mbl[j], lane, KSH);
+    if (EARLY && g.L >= 2) preload(2);
     __syncthreads();
+    if (!EARLY && g.L >= 2) preload(2);
   }
 
   // ----------------------------------------------------------- hidden layers
@@ -544,20 +576,13 @@ __device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict_
     for (int i = 0; i < NBW; ++i)
 #pragma unroll
       for (int j = 0; j < MBW; ++j) acc[i][j] = Acc{};
-    const int lbase = (int)(g.frag_h + (long long)(l - 2) * g.offh[NB]);
-    int ksi[NBW], fragi[NBW];
-#pragma unroll
-    for (int i = 0; i < NBW; ++i) {
-      ksi[i] = g.ksh[nbl[i]];
-      fragi[i] = lbase + g.offh[nbl[i]];
-    }
     // this layer's bias is requested before the k loop and parked in LDS
     // after it, so the epilogue reads it without waiting on L2
     S breg[BPT];
     const S* bsrc = biases + (long)(l - 1) * H;
 #pragma unroll
     for (int e = 0; e < BPT; ++e) breg[e] = (tid + e * NT < H) ? bsrc[tid + e * NT] : S(0);
-    kloop<P, NBW, MBW, Sh::NW, false>(acc, wbuf, fragi, ksi, 0, lds_act);
+    kloop<P, NBW, MBW, Sh::NW, false>(acc, wbuf, pre, lds_act);
 #pragma unroll
     for (int e = 0; e < BPT; ++e)
       if (tid + e * NT < H) blds[tid + e * NT] = breg[e];
@@ -566,7 +591,9 @@ __device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict_
     for (int i = 0; i < NBW; ++i)
 #pragma unroll
       for (int j = 0; j < MBW; ++j) store_act<P, MB>(act, acc[i][j], blds, nbl[i], mbl[j], lane, KSH);
+    if (EARLY && l < g.L) preload(l + 1);
     __syncthreads();
+    if (!EARLY && l < g.L) preload(l + 1);
   }
 
   // -------------------------------------------------------------------- head
