@@ -111,13 +111,16 @@ def bits(net: Net, samples):
     return ((s[:, None] >> j[None, :]) & np.uint64(1)).astype(np.int64)
 
 
-def constraint(net: Net, xb):
-    """Per-sample, per-qubit (free, violated) flags of the modifier (Eq. modifier)."""
+def constraint(net: Net, xb, forced_values=False):
+    """Per-sample, per-qubit (free, violated) flags of the modifier (Eq. modifier);
+    with forced_values also the value each forced qubit is forced to (True = 1).
+    The flags of the qubit at position t depend only on the bits before t."""
     B, n = xb.shape
     free = np.ones((B, n), dtype=bool)
     bad = np.zeros(B, dtype=bool)
+    one = np.zeros((B, n), dtype=bool)
     if not net.constrained:
-        return free, bad
+        return (free, bad, one) if forced_values else (free, bad)
     target = (net.n_up, net.n_dn)
     placed = np.zeros((B, 2), dtype=np.int64)
     spin_of = np.arange(n) % 2
@@ -132,8 +135,9 @@ def constraint(net: Net, xb):
         xj = xb[:, j]
         bad |= (force0 & (xj == 1)) | (force1 & (xj == 0))
         free[:, j] = ~(force0 | force1)
+        one[:, j] = force1
         placed[:, s] += xj
-    return free, bad
+    return (free, bad, one) if forced_values else (free, bad)
 
 
 def _softplus(z):
