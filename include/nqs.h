@@ -279,6 +279,30 @@ typedef struct {
 nqs_status nqs_multi_workspace_size(int n_inst, const nqs_instance* inst, size_t* bytes);
 nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* d_ws, size_t ws_bytes);
 
+/* ---------------------------------------------------------------- sampler
+ * Unique-sample autoregressive sampling of the plan's network (Sec. 4,
+ * Sampling; Eq. modifier for the Hamming-weight constraint).  A buffer of
+ * distinct configurations with draw counts starts as the all-zero
+ * configuration holding n_draws draws; at each sampling position t (qubit
+ * order[t]) every entry is doubled into x = 0 / x = 1 children, its draws
+ * are split by a binomial draw with the network's conditional probability
+ * (0 or 1 where the modifier forces the value), empty children are dropped,
+ * and beyond max_unique entries those with the fewest draws are eliminated
+ * (ties: earlier buffer entries kept; the buffer is ordered by the bits in
+ * sampling order).  Random numbers: Philox4x64-10, counter (parent
+ * configuration, t, 0, 0), key (seed, 0); Bin(c, p) by inversion from 0 when
+ * c min(p, 1-p) < 32, else the normal approximation with continuity
+ * correction (Box-Muller), reflected for p > 1/2.
+ * Outputs (device): d_x[u] configurations (uint64, bit j = qubit j), d_w[u]
+ * their draw counts as f64 weights, d_n_unique[0] = U <= max_unique, for
+ * u < U in buffer order.  d_x and d_w hold max_unique entries.  The network
+ * arithmetic is the plan's precision.  d_ws: nqs_sample_workspace_size
+ * bytes, 256-byte aligned.  Stream-ordered, no host synchronisation. */
+nqs_status nqs_sample_workspace_size(const nqs_plan* plan, int64_t max_unique, size_t* bytes);
+nqs_status nqs_sample(nqs_plan* plan, const float* d_params, int64_t n_draws, uint64_t seed,
+                      int64_t max_unique, uint64_t* d_x, double* d_w, int64_t* d_n_unique,
+                      void* d_ws, size_t ws_bytes);
+
 /* ------------------------------------------------------ test / table path
  * nqs_connected enumerates, for samples [0, B), the diagonal element
  * d_diag[2*i..] (group with empty flip) and the compacted connected entries

@@ -26,7 +26,8 @@ Random numbers: Philox4x64-10 (Salmon, Moraes, Dror and Shaw, "Parallel random
 numbers: as easy as 1, 2, 3", SC 2011), counter (x_parent, t, 0, 0), key
 (seed, 0).  Binomial draw Bin(c, p) from the counter's first two outputs:
 with q = min(p, 1 - p), inversion of the distribution function summed from
-k = 0 when c q < 32, otherwise the normal approximation
+k = 0 when c q < 32 (stopping where the terms underflow to zero, which bounds
+the search when u lies above the rounded total), otherwise the normal approximation
 floor(c q + z sqrt(c q (1 - q)) + 1/2) clamped to [0, c] with z from the
 Box-Muller transform; reflected (c - k) when p > 1/2.
 """
@@ -74,7 +75,7 @@ def binomial(c, p, u1, u2):
         pk = math.exp(c * math.log1p(-q))
         F = pk
         k = 0
-        while u1 > F and k < c:
+        while u1 > F and k < c and pk > 0.0:   # past the underflowing tail every term is 0
             pk *= r * (c - k) / (k + 1)
             k += 1
             F += pk

@@ -86,6 +86,8 @@ SIGNATURES = {
     "nqs_energy_grad": (C.c_int, [_P, _P, _P, _P, _I64, _P, _P, _P, _P, _SZ]),
     "nqs_multi_workspace_size": (C.c_int, [C.c_int, C.POINTER(Instance), C.POINTER(_SZ)]),
     "nqs_energy_grad_multi": (C.c_int, [C.c_int, C.POINTER(Instance), _P, _SZ]),
+    "nqs_sample_workspace_size": (C.c_int, [_P, _I64, C.POINTER(_SZ)]),
+    "nqs_sample": (C.c_int, [_P, _P, _I64, C.c_uint64, _I64, _P, _P, _P, _P, _SZ]),
     "nqs_connected": (C.c_int, [_P, _P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ]),
     "nqs_reduce_table": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _I64, _P, _P, _SZ]),
     "nqs_device_status": (C.c_int, [_P, _P, C.POINTER(C.c_uint32)]),

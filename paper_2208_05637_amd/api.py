@@ -283,6 +283,24 @@ def energy_grad_multi(items, workspace=None):
     L.check(lib.nqs_energy_grad_multi(len(items), _instances(items), ws, nb), "nqs_energy_grad_multi")
 
 
+def sample(plan, params, n_draws, seed, max_unique):
+    """Unique-sample autoregressive sampling (Sec. 4): (x int64 [U], weights f64 [U])."""
+    params = _params(plan, params)
+    dev = plan.ctx.device
+    need = C.c_size_t()
+    L.check(plan.lib.nqs_sample_workspace_size(plan.handle, int(max_unique), C.byref(need)),
+            "nqs_sample_workspace_size")
+    raw = torch.empty(need.value + 256, dtype=torch.uint8, device=dev)
+    ws = C.c_void_p((raw.data_ptr() + 255) & ~255)
+    x = torch.empty(int(max_unique), dtype=torch.int64, device=dev)
+    w = torch.empty(int(max_unique), dtype=torch.float64, device=dev)
+    nu = torch.zeros(1, dtype=torch.int64, device=dev)
+    L.check(plan.lib.nqs_sample(plan.handle, _ptr(params), int(n_draws), int(seed) & (2**64 - 1),
+                                int(max_unique), _ptr(x), _ptr(w), _ptr(nu), ws, need.value), "nqs_sample")
+    U = int(nu.item())
+    return x[:U], w[:U]
+
+
 def connected(plan, samples, capacity=None):
     dev = plan.ctx.device
     x = _as_u64_tensor(samples, dev)

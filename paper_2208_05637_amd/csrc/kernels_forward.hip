@@ -454,7 +454,7 @@ struct Shape {
 template <int P, int H, int NW>
 __device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict__ wpk,
                                          const uint64_t* __restrict__ xs, long long row0, long long count,
-                                         double2* __restrict__ out, char* act) {
+                                         double2* __restrict__ out, char* act, int cond) {
   using Sh = Shape<P, H, NW>;
   using T = Tr<P>;
   using Acc = typename T::Acc;
@@ -661,6 +661,27 @@ __device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict_
     double sum = 0.0;
     int bad = 0;
     const uint64_t sp0 = g.spin_pos[0], sp1 = g.spin_pos[1];
+    const long long grow = row0 + row;
+    if (cond >= 0) {
+      // sampler: the conditional logit at position cond and its forcing,
+      // from the bits before it (later bits do not enter)
+      if (sub == 0 && grow < count) {
+        const int t = cond;
+        int code = 0;
+        if (constrained) {
+          const int sp = (int)((sp1 >> t) & 1ull);
+          const uint64_t spm = sp ? sp1 : sp0;
+          const uint64_t low = t == 0 ? 0ull : (~0ull >> (64 - t));
+          const uint64_t high = t >= 63 ? 0ull : (~0ull << (t + 1));
+          const int c = __popcll(y & spm & low);
+          const int rem = __popcll(spm & high);
+          const int ns = sp ? g.n_dn : g.n_up;
+          code = (c + rem < ns) ? 2 : (c >= ns ? 1 : 0);
+        }
+        out[grow] = make_double2((double)head_out(t), (double)code);
+      }
+      return;
+    }
     for (int t = sub; t < g.n; t += TPR) {
       const S o = head_out(t);
       const int sp = (int)((sp1 >> t) & 1ull);   // spin of the qubit at position t
@@ -684,7 +705,6 @@ __device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict_
       sum += __shfl_xor(sum, off);
       bad |= __shfl_xor(bad, off);
     }
-    const long long grow = row0 + row;
     if (sub == 0 && grow < count) {
       const int sel = (int)(2 * ((y >> (g.n - 2)) & 1ull) + ((y >> (g.n - 1)) & 1ull));
       const double phi = (double)head_out(g.n + sel);
@@ -719,7 +739,8 @@ __global__ __launch_bounds__(64 * NW) void fused_forward(Geom g0, FwdLaunch la) 
   if constexpr (!MULTI) {
     const FwdSeg& sg = la.seg[0];
     const long long rows = seg_rows(sg);
-    if (t * M < rows) fwd_tile<P, H, NW>(g0, (const uint4*)sg.packed, sg.x, t * M, rows, (double2*)sg.out, act);
+    if (t * M < rows)
+      fwd_tile<P, H, NW>(g0, (const uint4*)sg.packed, sg.x, t * M, rows, (double2*)sg.out, act, la.cond_pos);
   } else {
     int k = 0;
     for (int j = 1; j < la.nseg; ++j)
@@ -729,7 +750,8 @@ __global__ __launch_bounds__(64 * NW) void fused_forward(Geom g0, FwdLaunch la) 
     const long long row0 = (t - sg.tile0) * M;
     // the geometry is read in place: nothing in this kernel writes global
     // memory before the tile's outputs, so its loads stay scalar
-    if (row0 < rows) fwd_tile<P, H, NW>(*sg.geom, (const uint4*)sg.packed, sg.x, row0, rows, (double2*)sg.out, act);
+    if (row0 < rows)
+      fwd_tile<P, H, NW>(*sg.geom, (const uint4*)sg.packed, sg.x, row0, rows, (double2*)sg.out, act, la.cond_pos);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     for (int k = 0; k < la.nseg; ++k)
@@ -819,12 +841,24 @@ void launch_forward(const Geom& g, int variant, const void* packed, const uint64
                     const long long* d_count, double* out, long long* prof_slot, hipStream_t s) {
   FwdLaunch la{};
   la.nseg = 1;
+  la.cond_pos = -1;
   la.seg[0] = FwdSeg{nullptr, packed, x, d_count, out, rows_bound, 0, prof_slot};
+  dispatch<false>(g, g.prec, g.h, variant, la, s);
+}
+
+void launch_forward_cond(const Geom& g, int variant, const void* packed, const uint64_t* x,
+                         long long rows_bound, const long long* d_count, double* out, int t,
+                         hipStream_t s) {
+  FwdLaunch la{};
+  la.nseg = 1;
+  la.cond_pos = t;
+  la.seg[0] = FwdSeg{nullptr, packed, x, d_count, out, rows_bound, 0, nullptr};
   dispatch<false>(g, g.prec, g.h, variant, la, s);
 }
 
 void launch_forward_multi(int prec, int h, int variant, FwdLaunch la, hipStream_t s) {
   if (la.nseg < 1 || la.nseg > kMaxSeg) return;
+  la.cond_pos = -1;
   Geom unused{};
   dispatch<true>(unused, prec, h, variant, la, s);
 }

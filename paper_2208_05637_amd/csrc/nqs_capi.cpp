@@ -1032,6 +1032,81 @@ nqs_status nqs_plan_kernel_info(const nqs_plan* p, int* waves_per_block, int* ro
   return NQS_OK;
 }
 
+// ---------------------------------------------------------------- sampler
+namespace {
+struct SampleLayout {
+  size_t err, packed, cond, x, cnt, kx, kc, eq, keep, eqoff, koff, stmp, sel, du, dnk, total;
+};
+
+SampleLayout sample_layout(const nqs_plan* p, int64_t U) {
+  SampleLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+  const size_t U2 = 2 * (size_t)U;
+  L.err = take(256);
+  L.packed = take(p->packed_bytes);
+  L.cond = take((size_t)U * 16);
+  L.x = take((size_t)U * 8);
+  L.cnt = take((size_t)U * 8);
+  L.kx = take(U2 * 8);
+  L.kc = take(U2 * 8);
+  L.eq = take(U2 * 4);
+  L.keep = take(U2 * 4);
+  L.eqoff = take((U2 + 1) * 8);
+  L.koff = take((U2 + 1) * 8);
+  L.stmp = take(((size_t)scan_tiles((long long)U2) + 1) * 8);
+  L.sel = take(16);
+  L.du = take(8);
+  L.dnk = take(8);
+  L.total = o;
+  return L;
+}
+}  // namespace
+
+nqs_status nqs_sample_workspace_size(const nqs_plan* p, int64_t max_unique, size_t* bytes) {
+  if (!p || !bytes) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (max_unique < 1 || max_unique > (1LL << 30))
+    return fail(NQS_ERR_INVALID_ARGUMENT, "max_unique %lld outside 1..2^30", (long long)max_unique);
+  *bytes = sample_layout(p, max_unique).total;
+  return NQS_OK;
+}
+
+nqs_status nqs_sample(nqs_plan* p, const float* params, int64_t n_draws, uint64_t seed, int64_t max_unique,
+                      uint64_t* d_x, double* d_w, int64_t* d_n_unique, void* ws, size_t ws_bytes) {
+  if (!p || !params || !d_x || !d_w || !d_n_unique) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (n_draws < 1 || n_draws > (1LL << 62)) return fail(NQS_ERR_INVALID_ARGUMENT, "n_draws outside 1..2^62");
+  if (max_unique < 1 || max_unique > (1LL << 30))
+    return fail(NQS_ERR_INVALID_ARGUMENT, "max_unique %lld outside 1..2^30", (long long)max_unique);
+  if (!ws) return fail(NQS_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (((uintptr_t)ws) & 255) return fail(NQS_ERR_INVALID_ARGUMENT, "workspace not 256-byte aligned");
+  const SampleLayout L = sample_layout(p, max_unique);
+  if (ws_bytes < L.total) return fail(NQS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, L.total);
+  hipStream_t s = p->ctx->stream;
+  SampleBufs b{};
+  b.x = at<uint64_t>(ws, L.x);
+  b.cnt = at<long long>(ws, L.cnt);
+  b.cond = at<double>(ws, L.cond);
+  b.kx = at<uint64_t>(ws, L.kx);
+  b.kc = at<long long>(ws, L.kc);
+  b.eq = at<int>(ws, L.eq);
+  b.keep = at<int>(ws, L.keep);
+  b.eqoff = at<long long>(ws, L.eqoff);
+  b.koff = at<long long>(ws, L.koff);
+  b.stmp = at<long long>(ws, L.stmp);
+  b.sel = at<long long>(ws, L.sel);
+  b.d_u = at<long long>(ws, L.du);
+  b.d_nk = at<long long>(ws, L.dnk);
+  void* packed = at<void>(ws, L.packed);
+  launch_pack_fused(p->g, params, packed, s);
+  launch_sample_init(b.x, b.cnt, n_draws, b.d_u, s);
+  for (int t = 0; t < p->g.n; ++t) {
+    launch_forward_cond(p->g, p->variant, packed, b.x, max_unique, b.d_u, b.cond, t, s);
+    launch_sample_step(b, max_unique, t, (int)p->g.order[t], seed, s);
+  }
+  launch_sample_finish(b, max_unique, d_x, d_w, (long long*)d_n_unique, s);
+  return launch_check("sample");
+}
+
 }  // extern "C"
 
 namespace nqs {

@@ -96,6 +96,7 @@ struct FwdSeg {
 };
 struct FwdLaunch {
   int nseg;
+  int cond_pos;   // -1: (log|psi|, phi); >= 0: (logit at that sampling position, forcing code)
   long long ntiles;
   FwdSeg seg[kMaxSeg];
 };
@@ -110,6 +111,12 @@ void launch_forward(const Geom& g, int variant, const void* packed, const uint64
 // geometry is read from seg.geom, a device copy written by launch_store_geom.
 // la.seg[*].tile0 and la.ntiles are filled in here.
 void launch_forward_multi(int prec, int h, int variant, FwdLaunch la, hipStream_t s);
+// Conditional form for the sampler: out[row] = (o_t, code) with o_t the
+// conditional logit at sampling position t and code 0 (free), 1 (forced to
+// 0) or 2 (forced to 1) by the Hamming-weight modifier.
+void launch_forward_cond(const Geom& g, int variant, const void* packed, const uint64_t* x,
+                         long long rows_bound, const long long* d_count, double* out, int t,
+                         hipStream_t s);
 void launch_store_geom(const Geom& g, Geom* dst, hipStream_t s);
 int forward_variants(int prec, int h);
 int forward_variant_waves(int prec, int h, int variant);
@@ -144,6 +151,27 @@ long long backward_scratch_elems(const Geom& g, long long S);
 void launch_backward(const Geom& g, const void* wm, const uint64_t* x, long long S,
                      const double* eloc, const double* w, const double* energy, void* scratch,
                      double* grad, hipStream_t s);
+
+// Sampler buffers (kernels_sample.hip); capacity umax entries, children 2 umax.
+struct SampleBufs {
+  uint64_t* x;       // [umax] configurations, in buffer order
+  long long* cnt;    // [umax] draws
+  double* cond;      // [umax][2] conditional logit and forcing code
+  uint64_t* kx;      // [2 umax] children
+  long long* kc;     // [2 umax]
+  int* eq;           // [2 umax] tie flags
+  int* keep;         // [2 umax]
+  long long* eqoff;  // [2 umax + 1]
+  long long* koff;   // [2 umax + 1]
+  long long* stmp;   // scan_tiles(2 umax) + 1
+  long long* sel;    // [2] threshold, quota
+  long long* d_u;    // entries in the buffer
+  long long* d_nk;   // children
+};
+void launch_sample_init(uint64_t* x, long long* cnt, long long n_draws, long long* d_u, hipStream_t s);
+void launch_sample_step(const SampleBufs& b, long long umax, int t, int q, uint64_t seed, hipStream_t s);
+void launch_sample_finish(const SampleBufs& b, long long umax, uint64_t* ox, double* ow, long long* on,
+                          hipStream_t s);
 
 int forward_rows_per_block(int prec, int h);
 bool forward_supported(int prec, int h);
