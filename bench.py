@@ -8,9 +8,10 @@ Prints one JSON line; diagnostics go to stderr.
 
 Default workload: 60 qubits (30 spatial orbitals, 15 up + 15 down electrons),
 Jordan-Wigner Hamiltonian of the seeded molecular-like integral generator
-(1,189,663 merged Pauli strings), 65536 sector-uniform samples reduced to
-unique samples with count weights, a BF16 masked network L = 4, h = 1024
-(BF16-valued parameters).  The timed path multiplies BF16 weights with
+(1,189,663 merged Pauli strings), a batch of 65,536 unique configurations
+drawn from |psi|^2 by the GPU unique-sample sampler (10^12 draws, counts as
+weights; --samples sector uses uniform sector draws instead), a BF16 masked
+network L = 4, h = 1024 (BF16-valued parameters).  The timed path multiplies BF16 weights with
 activations carried as two BF16 terms (two BF16 MFMAs, FP32 accumulation),
 with FP64 matrix elements, sums and energy; the value is its local-energy
 throughput B*K/t.  The whole step is also replayed from a HIP graph.
@@ -87,6 +88,9 @@ def main():
     ap.add_argument("--chunk", type=int, default=0, help="samples per chunk (0 = plan default)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (plan defaults)")
     ap.add_argument("--waves", type=int, default=0, help="force the forward's waves per workgroup")
+    ap.add_argument("--samples", default="psi", choices=["psi", "sector"],
+                    help="psi: the batch is drawn from the network with the GPU unique-sample sampler "
+                         "(1e12 draws, the batch size as buffer capacity); sector: uniform sector draws")
     ap.add_argument("--graph-steps", type=int, default=1,
                     help="replays of the HIP-graph-captured step after the timed steps (0 = none)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -123,18 +127,35 @@ def main():
     t = time.time()
     terms, params_np, samples, weights, cfg = config_inputs(args.workload, batch=args.batch)
     prec = args.precision or cfg["precision"]
-    log(f"inputs: n={cfg['n']} B={len(samples)} unique samples, {time.time() - t:.1f}s")
+    log(f"inputs: n={cfg['n']} K terms generated, {time.time() - t:.1f}s")
     ctx = nqs.Context(0)
     H = nqs.Hamiltonian.from_terms(terms).upload(ctx)
     K = H.K
-    B = len(samples)
+    dev = ctx.device
+    params = torch.from_numpy(params_np).to(dev)
     mk = lambda p, mb: nqs.Plan(ctx, H, cfg["L"], cfg["h"], cfg["n_up"], cfg["n_dn"], p, max_batch=mb,
                                 dedup=cfg["dedup"], chunk_samples=args.chunk)
+    sampling = None
+    if args.samples == "psi":
+        # the batch: unique configurations drawn from |psi|^2 with their counts (Sec. 4, Sampling)
+        want = cfg["B"] if args.batch is None else int(args.batch)
+        splan = mk(prec, 16)
+        nqs.sample(splan, params, 10**6, seed=1, max_unique=min(want, 1024))    # warm
+        torch.cuda.synchronize()
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record(ctx.stream)
+        xs_t, ws_t = nqs.sample(splan, params, 10**12, seed=2, max_unique=want)
+        s1.record(ctx.stream)
+        torch.cuda.synchronize()
+        samples = xs_t.cpu().numpy().view(np.uint64).copy()
+        weights = ws_t.cpu().numpy().copy()
+        sampling = {"draws": 10**12, "unique": len(samples), "ms": s0.elapsed_time(s1), "seed": 2}
+        log(f"sampler: {len(samples)} unique of 1e12 draws in {sampling['ms']:.1f} ms")
+        del splan
+    B = len(samples)
     plan = mk(prec, B)
     log(f"K={K} G={H.G} entries/sample={plan.entries_per_sample} chunk={plan.chunk_samples} "
         f"dedup={plan.dedup} workspace={plan.workspace_size(B) / 2**30:.2f} GiB")
-    dev = ctx.device
-    params = torch.from_numpy(params_np).to(dev)
     x = torch.from_numpy(samples.view(np.int64)).to(dev)
     w = torch.from_numpy(weights).to(dev)
     eloc = torch.empty((B, 2), dtype=torch.float64, device=dev)
@@ -227,7 +248,7 @@ def main():
         "config": {
             "workload": f"{args.workload}: {cfg['n']} qubits ({cfg['N']} orbitals, {cfg['n_up']}+{cfg['n_dn']} "
                         f"electrons), K={K} Pauli strings, G={H.G} flips, B={B} unique samples "
-                        f"(count weights), masked MLP L={cfg['L']} h={cfg['h']} with {cfg['params'].upper()} "
+                        f"(count weights, {'drawn from the network' if sampling else 'uniform in the sector'}), masked MLP L={cfg['L']} h={cfg['h']} with {cfg['params'].upper()} "
                         f"parameters, {ARITH[prec]}; FP64 matrix elements, sums and energy",
             "global_batch": B,
             "entries_per_sample": plan.entries_per_sample,
@@ -255,6 +276,10 @@ def main():
         },
     }
 
+    out["config"]["samples"] = ("drawn from |psi|^2 by the GPU unique-sample sampler" if sampling
+                                else "uniform over the spin sector, merged into counts")
+    if sampling is not None:
+        out["sampler"] = sampling
     if tune is not None:
         out["autotune"] = {"probe_samples": tune["probe_samples"], "from_cache": tune["from_cache"],
                            "candidates": tune["candidates"], "chosen": tune["chosen"]}
