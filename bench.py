@@ -19,8 +19,9 @@ throughput B*K/t.  The whole step is also replayed from a HIP graph.
 Beside it, on the first --prefix samples of the same batch and the same
 network: the timed path again, the split-BF16, plain BF16 and FP32 GPU paths
 (throughput + energy) and the FP64 GPU path (the energy reference of the
-prefix); and the FP64 CPU oracle on --cpu-samples samples (CPU baseline, and
-the per-sample check of every GPU path).
+prefix); one Adam step (Sec. 6) on the network's parameters; and the FP64 CPU
+oracle on --cpu-samples samples (CPU baseline, and the per-sample check of
+every GPU path).
 """
 import argparse
 import json
@@ -231,6 +232,26 @@ def main():
                  "equal_to_eager": same}
         log(f"graph-captured step: {graph['ms_per_step']:.1f} ms, equal to eager: {same}")
         del g
+    adam = None
+    if not args.no_side:
+        # one Adam step (Sec. 6) on this network's parameters with the step's gradient, timed on its own
+        pa = params.clone()
+        opt = nqs.Adam(ctx, pa, lr=1e-3, betas=(0.9, 0.99))
+        opt.step(grad)
+        torch.cuda.synchronize()
+        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        a0.record(ctx.stream)
+        for i in range(reps):
+            opt.step(grad)
+        a1.record(ctx.stream)
+        torch.cuda.synchronize()
+        ams = a0.elapsed_time(a1) / reps
+        nb = 48 * pa.numel()       # p f32, g, m, v f64 read; p, m, v written
+        adam = {"ms": ams, "params": pa.numel(), "alg_bytes": nb, "GB/s": nb / (ams / 1e3) / 1e9,
+                "frac_of_hbm_peak": nb / (ams / 1e3) / 8e12}
+        log(f"adam step: {ams * 1e3:.1f} us for {pa.numel()} parameters, {adam['GB/s']:.0f} GB/s")
+        del opt, pa
     kinfo = plan.kernel_info()
     out = {
         "metric": METRIC,
@@ -285,6 +306,8 @@ def main():
                            "candidates": tune["candidates"], "chosen": tune["chosen"]}
     if graph is not None:
         out["graph_step"] = graph
+    if adam is not None:
+        out["adam_step"] = adam
 
     side = {}
     P = min(args.prefix, B)

@@ -303,6 +303,22 @@ nqs_status nqs_sample(nqs_plan* plan, const float* d_params, int64_t n_draws, ui
                       int64_t max_unique, uint64_t* d_x, double* d_w, int64_t* d_n_unique,
                       void* d_ws, size_t ws_bytes);
 
+/* -------------------------------------------------------------- optimizer
+ * One Adam step (Kingma and Ba, ICLR 2015; the paper trains with Adam, Sec. 6,
+ * learning rate 1e-3, betas (0.9, 0.99)) on the FP32 parameters with the FP64
+ * gradient of nqs_energy_grad, for every i < n:
+ *   m_i <- b1 m_i + (1 - b1) g_i
+ *   v_i <- b2 v_i + (1 - b2) g_i g_i
+ *   p_i <- p_i - lr (m_i / (1 - b1^t)) / (sqrt(v_i / (1 - b2^t)) + eps)
+ * with t = step >= 1, the number of this step.  d_m and d_v are FP64 [n],
+ * caller-owned, zero before step 1.  The update is FP64, evaluated in the
+ * order written (no fused multiply-adds), and the parameter is rounded to the
+ * nearest FP32.  Errors: NULL pointers with n > 0, step < 1, lr < 0,
+ * betas outside [0, 1) or eps < 0 give NQS_ERR_INVALID_ARGUMENT, nothing is
+ * enqueued.  Stream-ordered on the context's stream, capture-safe. */
+nqs_status nqs_adam_step(nqs_ctx* ctx, int64_t n, float* d_params, const double* d_grad, double* d_m,
+                         double* d_v, int64_t step, double lr, double beta1, double beta2, double eps);
+
 /* ------------------------------------------------------ test / table path
  * nqs_connected enumerates, for samples [0, B), the diagonal element
  * d_diag[2*i..] (group with empty flip) and the compacted connected entries

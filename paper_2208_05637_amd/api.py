@@ -346,6 +346,28 @@ def device_status(plan):
     return flags.value
 
 
+class Adam:
+    """Adam on the flat FP32 parameter tensor (Sec. 6), one nqs_adam_step per
+    call; the FP64 moments are torch tensors owned by this object."""
+
+    def __init__(self, ctx, params, lr=1e-3, betas=(0.9, 0.99), eps=1e-8):
+        if params.dtype != torch.float32 or not params.is_contiguous():
+            raise TypeError("params must be a contiguous float32 tensor")
+        self.ctx, self.params = ctx, params
+        self.lr, self.betas, self.eps = float(lr), (float(betas[0]), float(betas[1])), float(eps)
+        self.m = torch.zeros(params.numel(), dtype=torch.float64, device=params.device)
+        self.v = torch.zeros_like(self.m)
+        self.t = 0
+
+    def step(self, grad):
+        if grad.dtype != torch.float64 or grad.numel() != self.params.numel() or not grad.is_contiguous():
+            raise TypeError("grad must be a contiguous float64 tensor of the parameters' size")
+        self.t += 1
+        L.check(self.ctx.lib.nqs_adam_step(self.ctx.handle, self.params.numel(), _ptr(self.params), _ptr(grad),
+                                           _ptr(self.m), _ptr(self.v), self.t, self.lr, self.betas[0],
+                                           self.betas[1], self.eps), "nqs_adam_step")
+
+
 class EnergyFn(torch.autograd.Function):
     """(E, eloc) = EnergyFn.apply(params, samples, weights, plan).
 

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnqs.so")
 
-SOURCES = ["nqs_capi.cpp", "kernels_forward.hip", "kernels_ham.hip", "kernels_backward.hip", "kernels_sample.hip"]
+SOURCES = ["nqs_capi.cpp", "kernels_forward.hip", "kernels_ham.hip", "kernels_backward.hip", "kernels_sample.hip",
+           "kernels_optim.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -1172,6 +1172,29 @@ nqs_status nqs_reduce_table(nqs_plan* p, int64_t B, const double* lps, const dou
   return launch_check("reduce");
 }
 
+nqs_status nqs_adam_step(nqs_ctx* ctx, int64_t n, float* d_params, const double* d_grad, double* d_m,
+                         double* d_v, int64_t step, double lr, double beta1, double beta2, double eps) {
+  if (!ctx) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL context");
+  if (n < 0) return fail(NQS_ERR_INVALID_ARGUMENT, "n < 0");
+  if (n > 0 && (!d_params || !d_grad || !d_m || !d_v)) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL buffer");
+  if (step < 1) return fail(NQS_ERR_INVALID_ARGUMENT, "step must be >= 1");
+  if (!(lr >= 0.0) || !(eps >= 0.0)) return fail(NQS_ERR_INVALID_ARGUMENT, "lr and eps must be >= 0");
+  if (!(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0))
+    return fail(NQS_ERR_INVALID_ARGUMENT, "betas must lie in [0, 1)");
+  nqs::AdamCoef k;
+  k.lr = lr;
+  k.b1 = beta1;
+  k.b2 = beta2;
+  k.one_m_b1 = 1.0 - beta1;
+  k.one_m_b2 = 1.0 - beta2;
+  k.bc1 = 1.0 - std::pow(beta1, (double)step);
+  k.bc2 = 1.0 - std::pow(beta2, (double)step);
+  k.eps = eps;
+  if (!(k.bc1 > 0.0) || !(k.bc2 > 0.0)) return fail(NQS_ERR_INVALID_ARGUMENT, "bias correction is zero");
+  nqs::launch_adam(n, d_params, d_grad, d_m, d_v, k, ctx->cu_count, ctx->stream);
+  return launch_check("nqs_adam_step");
+}
+
 nqs_status nqs_device_status(nqs_ctx* ctx, void* ws, uint32_t* flags) {
   if (!ctx || !ws || !flags) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
   HIP_TRY(hipStreamSynchronize(ctx->stream));

@@ -173,6 +173,13 @@ void launch_sample_step(const SampleBufs& b, long long umax, int t, int q, uint6
 void launch_sample_finish(const SampleBufs& b, long long umax, uint64_t* ox, double* ow, long long* on,
                           hipStream_t s);
 
+// Adam coefficients, formed on the host: bc1 = 1 - b1^t, bc2 = 1 - b2^t.
+struct AdamCoef {
+  double lr, b1, b2, one_m_b1, one_m_b2, bc1, bc2, eps;
+};
+void launch_adam(long long n, float* p, const double* g, double* m, double* v, const AdamCoef& k, int cu_count,
+                 hipStream_t s);
+
 int forward_rows_per_block(int prec, int h);
 bool forward_supported(int prec, int h);
 

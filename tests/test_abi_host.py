@@ -98,3 +98,9 @@ def test_unsupported_width_rejected(lib):
     from paper_2208_05637_amd import param_count, NQSError
     with pytest.raises(NQSError):
         param_count(12, 1, 100, "bf16")
+
+
+def test_adam_rejects_arguments_on_the_host(lib):
+    import ctypes as C
+    z = C.c_void_p(0)
+    assert lib.nqs_adam_step(z, 0, z, z, z, z, 1, 1e-3, 0.9, 0.99, 1e-8) == 1     # NULL context
