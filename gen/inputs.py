@@ -3,7 +3,9 @@
 The parameter layout is the library's flat FP32 layout: for each hidden layer
 l = 1..L the weight W_l (row-major [h][in_l], in_1 = n, else h) then its bias
 b_l [h]; then the conditional head W_o [n][h], b_o [n]; then the phase head
-W_phi [4][h], b_phi [4].  All entries are drawn i.i.d. N(0, 0.1^2) in float32;
+W_phi [4][h], b_phi [4]; with a separate phase network (phase_mode 1) its
+layers V_1 [h][n-2], e_1 [h], ..., V_L [h][h], e_L [h] sit between the
+conditional head and W_phi.  All entries are drawn i.i.d. N(0, 0.1^2) in float32;
 for the workloads whose network is BF16, every entry is then rounded to the
 nearest BF16 value (the parameters of that network are BF16 values, held in
 float32 storage).
@@ -31,12 +33,14 @@ def hamiltonian(n_orb: int, seed: int = 0, drop_tol: float = 1e-10) -> PauliTerm
     return _hamiltonian_cached(int(n_orb), int(seed), float(drop_tol))
 
 
-def param_count(n: int, n_layers: int, width: int) -> int:
+def param_count(n: int, n_layers: int, width: int, phase_mode: int = 0) -> int:
     h = width
     total = h * n + h
     total += (n_layers - 1) * (h * h + h)
     total += n * h + n
     total += 4 * h + 4
+    if phase_mode == 1:             # separate phase network: V_1 [h][n-2], e_1, then (L-1) x [h][h], [h]
+        total += h * (n - 2) + h + (n_layers - 1) * (h * h + h)
     return total
 
 
@@ -47,10 +51,11 @@ def round_bf16(a):
     return u.astype(np.uint32).view(np.float32)
 
 
-def init_params(n: int, n_layers: int, width: int, seed: int = 1, std: float = 0.1, dtype: str = "fp32"):
+def init_params(n: int, n_layers: int, width: int, seed: int = 1, std: float = 0.1, dtype: str = "fp32",
+                phase_mode: int = 0):
     """N(0, std^2) parameters in float32; dtype "bf16" rounds them to BF16 values."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    p = (std * rng.standard_normal(param_count(n, n_layers, width))).astype(np.float32)
+    p = (std * rng.standard_normal(param_count(n, n_layers, width, phase_mode))).astype(np.float32)
     if dtype == "bf16":
         p = round_bf16(p)
     elif dtype != "fp32":

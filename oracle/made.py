@@ -25,8 +25,19 @@ Definition (readings of Sec. 4, Architecture and Constraints):
     c_s >= n_s and forced to 1 when c_s + r_s < n_s;
   * phi = p[2 x_{order[n-2]} + x_{order[n-1]}], used as a real angle.
 
-Parameters are the flat layout W_1, b_1, ..., W_L, b_L, W_o, b_o, W_phi,
-b_phi with weights row-major [out][in].
+Two readings of the phase network (Sec. 4, Architecture):
+  * phase_mode 0: the phase head above reads the shared masked trunk;
+  * phase_mode 1: the paper's separate phase sub-model, a plain MLP whose
+    input is the first n-2 entries in sampling order, v_t = s_{order[t]}
+    for t < n-2, with the same depth L and width h as the modulus network:
+    c_1 = ReLU(V_1 v + e_1), c_l = ReLU(V_l c_{l-1} + e_l), p = W_phi c_L +
+    b_phi.  Its input already excludes the last two positions, so its layers
+    carry no masks; the modulus network keeps the trunk and the conditional
+    head and has no phase head.
+
+Parameters are the flat layout W_1, b_1, ..., W_L, b_L, W_o, b_o, then (mode
+1 only) V_1, e_1, ..., V_L, e_L, then W_phi, b_phi, with weights row-major
+[out][in] (V_1 is [h][n-2]).
 
 The forward runs in float64 or complex128 (complex-step derivative checks);
 the reverse pass is written out by hand.
@@ -44,6 +55,7 @@ class Net:
     n_up: int = -1
     n_dn: int = -1
     order: np.ndarray = field(default=None)
+    phase_mode: int = 0
 
     def __post_init__(self):
         if self.order is None:
@@ -53,6 +65,8 @@ class Net:
             raise ValueError("order must be a permutation of the qubits")
         if self.n < 2:
             raise ValueError("need at least two qubits")
+        if self.phase_mode not in (0, 1):
+            raise ValueError("phase_mode is 0 (shared trunk) or 1 (separate sub-model)")
 
     @property
     def constrained(self):
@@ -60,35 +74,35 @@ class Net:
 
 
 def unpack(net: Net, params):
-    """Split the flat parameter vector into (W_l, b_l)*L, W_o, b_o, W_phi, b_phi."""
+    """Split the flat parameter vector into
+    ([(W_l, b_l)] * L, (W_o, b_o), (W_phi, b_phi), [(V_l, e_l)] * L or [])."""
     p = np.asarray(params)
     n, h, L = net.n, net.width, net.n_layers
-    out = []
     off = 0
-    fan_in = n
-    for _ in range(L):
-        W = p[off:off + h * fan_in].reshape(h, fan_in)
-        off += h * fan_in
-        b = p[off:off + h]
-        off += h
-        out.append((W, b))
-        fan_in = h
-    Wo = p[off:off + n * h].reshape(n, h)
-    off += n * h
-    bo = p[off:off + n]
-    off += n
-    Wp = p[off:off + 4 * h].reshape(4, h)
-    off += 4 * h
-    bp = p[off:off + 4]
-    off += 4
+
+    def take(rows, cols):
+        nonlocal off
+        W = p[off:off + rows * cols].reshape(rows, cols)
+        off += rows * cols
+        b = p[off:off + rows]
+        off += rows
+        return W, b
+
+    layers = [take(h, n if l == 0 else h) for l in range(L)]
+    head_o = take(n, h)
+    phase_layers = [take(h, n - 2 if l == 0 else h) for l in range(L)] if net.phase_mode == 1 else []
+    head_p = take(4, h)
     if off != p.shape[0]:
         raise ValueError(f"parameter vector has {p.shape[0]} entries, layout needs {off}")
-    return out, (Wo, bo), (Wp, bp)
+    return layers, head_o, head_p, phase_layers
 
 
 def n_params(net: Net):
     n, h, L = net.n, net.width, net.n_layers
-    return h * n + h + (L - 1) * (h * h + h) + n * h + n + 4 * h + 4
+    total = h * n + h + (L - 1) * (h * h + h) + n * h + n + 4 * h + 4
+    if net.phase_mode == 1:
+        total += h * (n - 2) + h + (L - 1) * (h * h + h)
+    return total
 
 
 def masks(net: Net):
@@ -101,7 +115,10 @@ def masks(net: Net):
     M1 = (m[:, None] >= d[None, :]).astype(np.float64)
     Mh = (m[:, None] >= m[None, :]).astype(np.float64)
     Mo = (d[:, None] > m[None, :]).astype(np.float64)
-    Mp = np.repeat((m <= n - 2)[None, :], 4, axis=0).astype(np.float64)
+    if net.phase_mode == 1:
+        Mp = np.ones((4, h))                      # the sub-model's head reads all its units
+    else:
+        Mp = np.repeat((m <= n - 2)[None, :], 4, axis=0).astype(np.float64)
     return M1, Mh, Mo, Mp
 
 
@@ -157,7 +174,7 @@ def _relu(z):
 
 def forward(net: Net, params, samples, dtype=np.float64):
     """log|psi| (float64, -inf off-sector), phi, and the activations for backward."""
-    layers, (Wo, bo), (Wp, bp) = unpack(net, np.asarray(params).astype(dtype))
+    layers, (Wo, bo), (Wp, bp), phase_layers = unpack(net, np.asarray(params).astype(dtype))
     M1, Mh, Mo, Mp = masks(net)
     xb = bits(net, samples)
     s = (2 * xb - 1).astype(dtype)
@@ -171,7 +188,18 @@ def forward(net: Net, params, samples, dtype=np.float64):
         a = _relu(z)
         acts.append(a)
     o = a @ (Mo * Wo).T + bo
-    p = a @ (Mp * Wp).T + bp
+    pacts, ppre = [], []
+    if net.phase_mode == 1:
+        c = s[:, net.order[:net.n - 2]]             # first n-2 entries in sampling order
+        pacts.append(c)
+        for V, e in phase_layers:
+            z = c @ V.T + e
+            ppre.append(z)
+            c = _relu(z)
+            pacts.append(c)
+        p = c @ (Mp * Wp).T + bp
+    else:
+        p = a @ (Mp * Wp).T + bp
     free, bad = constraint(net, xb)
     # log pi_j(x_j) = -softplus(-o) if x_j = 1 else -softplus(o)
     lp = np.where(xb == 1, -_softplus(-o), -_softplus(o))
@@ -180,7 +208,7 @@ def forward(net: Net, params, samples, dtype=np.float64):
     phi = p[np.arange(len(sel)), sel]
     if np.issubdtype(np.dtype(dtype), np.floating):
         logabs = np.where(bad, -np.inf, logabs)
-    cache = dict(acts=acts, pre=pre, o=o, p=p, xb=xb, free=free, bad=bad, sel=sel)
+    cache = dict(acts=acts, pre=pre, o=o, p=p, xb=xb, free=free, bad=bad, sel=sel, pacts=pacts, ppre=ppre)
     return logabs, phi, cache
 
 
@@ -190,7 +218,7 @@ def backward(net: Net, params, cache, g_logabs, g_phi):
     d log|psi| / d o_j = 1/2 [j free] (x_j - sigmoid(o_j)); d phi / d p_c = [c == sel].
     ReLU'(0) = 0; masked-out weights receive zero gradient.
     """
-    layers, (Wo, bo), (Wp, bp) = unpack(net, np.asarray(params, dtype=np.float64))
+    layers, (Wo, bo), (Wp, bp), phase_layers = unpack(net, np.asarray(params, dtype=np.float64))
     M1, Mh, Mo, Mp = masks(net)
     acts, pre, o, xb, free, sel = (cache[k] for k in ("acts", "pre", "o", "xb", "free", "sel"))
     if np.any(cache["bad"]):
@@ -202,22 +230,35 @@ def backward(net: Net, params, cache, g_logabs, g_phi):
     d_p = np.zeros((len(sel), 4))
     d_p[np.arange(len(sel)), sel] = g_phi
     aL = acts[-1]
-    grads_rev = []
-    gWp = (d_p.T @ aL) * Mp
+    phase_in = cache["pacts"][-1] if net.phase_mode == 1 else aL
+    gWp = (d_p.T @ phase_in) * Mp
     gbp = d_p.sum(axis=0)
     gWo = (d_o.T @ aL) * Mo
     gbo = d_o.sum(axis=0)
-    d_a = d_o @ (Mo * Wo) + d_p @ (Mp * Wp)
-    for li in reversed(range(net.n_layers)):
-        W, b = layers[li]
-        M = M1 if li == 0 else Mh
-        d_z = d_a * (pre[li] > 0)
-        gW = (d_z.T @ acts[li]) * M
-        gb = d_z.sum(axis=0)
-        grads_rev.append((gW, gb))
-        d_a = d_z @ (M * W)
+
+    def through(stack, inputs, pres, d_a, mask_of):
+        """Reverse pass through ReLU layers; returns [(gW, gb)] in forward order."""
+        out = []
+        for li in reversed(range(len(stack))):
+            W, _ = stack[li]
+            M = mask_of(li)
+            d_z = d_a * (pres[li] > 0)
+            out.append(((d_z.T @ inputs[li]) * M, d_z.sum(axis=0)))
+            d_a = d_z @ (M * W)
+        return out[::-1]
+
+    d_a = d_o @ (Mo * Wo)
+    if net.phase_mode == 0:
+        d_a = d_a + d_p @ (Mp * Wp)
+    trunk = through(layers, acts, pre, d_a, lambda li: M1 if li == 0 else Mh)
     flat = []
-    for gW, gb in reversed(grads_rev):
+    for gW, gb in trunk:
         flat += [gW.ravel(), gb]
-    flat += [gWo.ravel(), gbo, gWp.ravel(), gbp]
+    flat += [gWo.ravel(), gbo]
+    if net.phase_mode == 1:
+        ones = lambda li: 1.0
+        sub = through(phase_layers, cache["pacts"], cache["ppre"], d_p @ Wp, ones)
+        for gW, gb in sub:
+            flat += [gW.ravel(), gb]
+    flat += [gWp.ravel(), gbp]
     return np.concatenate(flat)

@@ -106,3 +106,80 @@ def test_backward_matches_complex_step(L, constrained):
     M1 = made.masks(net)[0]
     gW1 = g[:h * n].reshape(h, n)
     assert np.all(gW1[M1 == 0] == 0)
+
+
+def test_phase_submodel_single_layer_is_paper_mlp():
+    """phase_mode 1, L = 1: the phase is Input[n-2] -> FC1 -> ReLU -> FC2 -> [4] on the
+    first n-2 entries in sampling order (Sec. 4 Architecture), and the modulus is the
+    shared-trunk network's with the same trunk and conditional head."""
+    n, h = 7, 9
+    order = np.random.default_rng(5).permutation(n)
+    net = made.Net(n=n, n_layers=1, width=h, order=order, phase_mode=1)
+    params = init_params(n, 1, h, seed=3, std=0.5, phase_mode=1).astype(np.float64)
+    assert len(params) == made.n_params(net)
+    off = h * n + h + n * h + n                 # trunk and conditional head
+    V1 = params[off:off + h * (n - 2)].reshape(h, n - 2)
+    e1 = params[off + h * (n - 2):off + h * (n - 2) + h]
+    o2 = off + h * (n - 2) + h
+    Wp = params[o2:o2 + 4 * h].reshape(4, h)
+    bp = params[o2 + 4 * h:o2 + 4 * h + 4]
+    assert o2 + 4 * h + 4 == len(params)
+    xs = np.random.default_rng(6).integers(0, 1 << n, 20).astype(np.uint64)
+    la, ph, _ = made.forward(net, params, xs)
+    for i, x in enumerate(xs):
+        bitsx = [(int(x) >> j) & 1 for j in range(n)]
+        v = np.array([2.0 * bitsx[order[t]] - 1.0 for t in range(n - 2)])
+        c = np.maximum(V1 @ v + e1, 0.0)
+        p = Wp @ c + bp
+        sel = 2 * bitsx[order[n - 2]] + bitsx[order[n - 1]]
+        assert abs(ph[i] - p[sel]) < 1e-13
+    # modulus: the shared-trunk net with the same trunk and head gives the same log|psi|
+    net0 = made.Net(n=n, n_layers=1, width=h, order=order, phase_mode=0)
+    p0 = np.concatenate([params[:off], Wp.ravel(), bp])
+    la0, _, _ = made.forward(net0, p0, xs)
+    np.testing.assert_array_equal(la, la0)
+
+
+def test_phase_submodel_dependence():
+    """phase_mode 1: the 4-vector p depends on the first n-2 positions only, and every
+    one of them enters."""
+    n = 8
+    order = np.random.default_rng(2).permutation(n)
+    net = made.Net(n=n, n_layers=2, width=16, order=order, phase_mode=1)
+    params = init_params(n, 2, 16, seed=8, std=0.5, phase_mode=1)
+    xs = np.random.default_rng(3).integers(0, 1 << n, 40).astype(np.uint64)
+    _, _, c0 = made.forward(net, params, xs)
+    for t in range(n):
+        _, _, c1 = made.forward(net, params, xs ^ np.uint64(1 << int(order[t])))
+        if t >= n - 2:
+            np.testing.assert_array_equal(c0["p"], c1["p"])
+        else:
+            assert np.any(c0["p"] != c1["p"])
+
+
+@pytest.mark.parametrize("L,constrained", [(1, True), (2, True), (3, False)])
+def test_phase_submodel_backward_matches_complex_step(L, constrained):
+    n, h = 8, 12
+    net = made.Net(n=n, n_layers=L, width=h, n_up=2 if constrained else -1, n_dn=2 if constrained else -1,
+                   phase_mode=1)
+    params = init_params(n, L, h, seed=31, std=0.4, phase_mode=1).astype(np.float64)
+    rng = np.random.default_rng(9)
+    basis = pauli.sector_basis(n, 2, 2) if constrained else np.arange(1 << n, dtype=np.uint64)
+    xs = rng.choice(basis, 12, replace=False)
+    ga = rng.standard_normal(len(xs))
+    gp = rng.standard_normal(len(xs))
+    _, _, cache = made.forward(net, params, xs)
+    g = made.backward(net, params, cache, ga, gp)
+    nphase = h * (n - 2) + h + (L - 1) * (h * h + h) + 4 * h + 4
+    idx = np.concatenate([rng.choice(len(params) - nphase, 20, replace=False),
+                          len(params) - nphase + rng.choice(nphase, 30, replace=False)])
+    for k in idx:
+        pc = params.astype(np.complex128)
+        pc[k] += 1j * 1e-30
+        la, ph, _ = made.forward(net, pc, xs, dtype=np.complex128)
+        F = np.sum(ga * la) + np.sum(gp * ph)
+        assert abs(F.imag / 1e-30 - g[k]) <= 1e-12 * max(1.0, abs(g[k]))
+    # the trunk gets nothing from the phase: with g_logabs = 0 its gradient is zero
+    g_ph = made.backward(net, params, cache, np.zeros(len(xs)), gp)
+    ntrunk = len(params) - nphase
+    assert np.all(g_ph[:ntrunk] == 0) and np.any(g_ph[ntrunk:] != 0)

@@ -41,13 +41,14 @@ def test_eigenvector_local_energy_is_lambda_min(N, nu, nd):
     assert np.max(np.abs(el - evals[0])) < 1e-9 * scale * len(basis) ** 0.5
 
 
-@pytest.mark.parametrize("N,nu,nd,L,h", [(3, 1, 2, 1, 8), (4, 2, 2, 2, 16), (5, 2, 3, 2, 12)])
-def test_exact_mean_of_local_energy(N, nu, nd, L, h):
+@pytest.mark.parametrize("N,nu,nd,L,h,mode", [(3, 1, 2, 1, 8, 0), (4, 2, 2, 2, 16, 0), (5, 2, 3, 2, 12, 0),
+                                              (3, 1, 2, 1, 8, 1), (4, 2, 2, 2, 16, 1)])
+def test_exact_mean_of_local_energy(N, nu, nd, L, h, mode):
     """sum_x pi(x) E_loc(x) = <psi|H|psi>/<psi|psi> with zero imaginary part."""
     n = 2 * N
     terms = _terms(N)
-    net = made.Net(n=n, n_layers=L, width=h, n_up=nu, n_dn=nd)
-    params = init_params(n, L, h, seed=5, std=0.6)
+    net = made.Net(n=n, n_layers=L, width=h, n_up=nu, n_dn=nd, phase_mode=mode)
+    params = init_params(n, L, h, seed=5, std=0.6, phase_mode=mode)
     basis = pauli.sector_basis(n, nu, nd)
     la, ph, _ = made.forward(net, params, basis)
     psi = np.exp(la + 1j * ph)
@@ -150,13 +151,14 @@ def test_gradient_matches_fd_of_frozen_surrogate():
         assert abs(fd - g[k]) < 1e-6 * max(1.0, np.max(np.abs(g)))
 
 
-def test_gradient_matches_fd_of_exact_energy():
+@pytest.mark.parametrize("mode", [0, 1])
+def test_gradient_matches_fd_of_exact_energy(mode):
     """With exact weights pi over the sector, g = d/dtheta <psi|H|psi> (pins the factor 2 and the real baseline)."""
     N, L, h = 3, 2, 10
     n = 2 * N
     terms = _terms(N)
-    net = made.Net(n=n, n_layers=L, width=h, n_up=1, n_dn=2)
-    params = init_params(n, L, h, seed=17, std=0.5).astype(np.float64)
+    net = made.Net(n=n, n_layers=L, width=h, n_up=1, n_dn=2, phase_mode=mode)
+    params = init_params(n, L, h, seed=17, std=0.5, phase_mode=mode).astype(np.float64)
     basis = pauli.sector_basis(n, 1, 2)
     Hs = pauli.sector_block(terms, basis)
 
@@ -172,7 +174,10 @@ def test_gradient_matches_fd_of_exact_energy():
     assert abs(E - Eexact(params)) < 1e-12
     g = vmc.gradient(net, params, basis, pi, el, E)
     rng = np.random.default_rng(4)
-    for k in rng.choice(len(params), 25, replace=False):
+    # the last 200 parameters include every phase parameter (the head, and in mode 1 the sub-model)
+    picks = np.concatenate([rng.choice(len(params) - 200, 15, replace=False),
+                            len(params) - 200 + rng.choice(200, 15, replace=False)])
+    for k in picks:
         e = np.zeros_like(params)
         e[k] = 1e-5
         fd = (Eexact(params + e) - Eexact(params - e)) / 2e-5
