@@ -137,8 +137,9 @@ void       nqs_ham_destroy(nqs_ham* ham);
  * is forced to 0 once n_s spin-s electrons are placed, to 1 when the
  * remaining spin-s positions are all needed; forced positions contribute 0,
  * a contradicted forced value gives psi = 0).
- * Parameters: one flat FP32 buffer W_1, b_1, ..., W_L, b_L, W_o, b_o, W_p,
- * b_p, weights row-major [out][in] (in_1 = n).  Gradients use the same
+ * Parameters: one flat FP32 buffer W_1, b_1, ..., W_L, b_L, W_o, b_o,
+ * [V_1, e_1, ..., V_L, e_L with NQS_PHASE_SEPARATE,] W_p, b_p, weights
+ * row-major [out][in] (in_1 = n).  Gradients use the same
  * layout in FP64; masked-out weights receive 0.
  */
 /* Arithmetic of the network on the connected configurations:
@@ -155,6 +156,21 @@ void       nqs_ham_destroy(nqs_ham* ham);
  *              With BF16-valued parameters the rounding is the identity. */
 enum { NQS_FP64 = 0, NQS_FP32 = 1, NQS_BF16 = 2, NQS_BF16X3 = 3, NQS_BF16W = 4 };
 
+/* The phase network (Sec. 4, Architecture: modulus and phase sub-models).
+ *   NQS_PHASE_SHARED    the phase head W_p [4][h] reads the last hidden layer
+ *                       of the masked trunk, restricted to units of degree
+ *                       <= n-2;
+ *   NQS_PHASE_SEPARATE  the paper's separate phase sub-model: a plain MLP of
+ *                       the same depth L and width h whose input is the first
+ *                       n-2 entries in sampling order (2x-1), c_1 =
+ *                       ReLU(V_1 v + e_1), c_l = ReLU(V_l c_{l-1} + e_l), then
+ *                       W_p [4][h]; no masks (its input already excludes the
+ *                       last two positions).  Its layers V_1 [h][n-2], e_1,
+ *                       ..., V_L [h][h], e_L sit in the parameter layout
+ *                       between b_o and W_p.  n_qubits >= 3.
+ * In both, phi = p[2 x_{order[n-2]} + x_{order[n-1]}]. */
+enum { NQS_PHASE_SHARED = 0, NQS_PHASE_SEPARATE = 1 };
+
 typedef struct {
   int            n_qubits;   /* 2..64 */
   int            n_layers;   /* >= 1 */
@@ -164,6 +180,7 @@ typedef struct {
   int            precision;  /* NQS_FP64 | NQS_FP32 | NQS_BF16 | NQS_BF16X3 | NQS_BF16W
                                 (above); Hamiltonian sums, ratios and reductions
                                 are FP64 in every case */
+  int            phase_mode; /* NQS_PHASE_SHARED or NQS_PHASE_SEPARATE (below) */
 } nqs_net_desc;
 
 nqs_status nqs_net_param_count(const nqs_net_desc* net, int64_t* n_params);

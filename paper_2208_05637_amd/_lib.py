@@ -31,7 +31,7 @@ class PauliTerms(C.Structure):
 class NetDesc(C.Structure):
     _fields_ = [("n_qubits", C.c_int), ("n_layers", C.c_int), ("width", C.c_int),
                 ("order", C.c_void_p), ("n_up", C.c_int), ("n_dn", C.c_int),
-                ("precision", C.c_int)]
+                ("precision", C.c_int), ("phase_mode", C.c_int)]
 
 
 class Profile(C.Structure):

@@ -101,19 +101,22 @@ class Hamiltonian:
             self.handle = None
 
 
-def net_desc(n_qubits, n_layers, width, n_up=-1, n_dn=-1, precision="fp32", order=None):
+def net_desc(n_qubits, n_layers, width, n_up=-1, n_dn=-1, precision="fp32", order=None, phase_mode=0):
+    """phase_mode: 0 (or "shared") phase head on the masked trunk; 1 (or
+    "separate") the separate phase sub-model."""
     order_arr = None
     if order is not None:
         order_arr = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+    pm = {"shared": 0, "separate": 1}.get(phase_mode, phase_mode)
     d = L.NetDesc(int(n_qubits), int(n_layers), int(width),
                   None if order_arr is None else order_arr.ctypes.data, int(n_up), int(n_dn),
-                  L.PRECISIONS[precision] if isinstance(precision, str) else int(precision))
+                  L.PRECISIONS[precision] if isinstance(precision, str) else int(precision), int(pm))
     return d, order_arr
 
 
-def param_count(n_qubits, n_layers, width, precision="fp32"):
+def param_count(n_qubits, n_layers, width, precision="fp32", phase_mode=0):
     lib = L.load()
-    d, keep = net_desc(n_qubits, n_layers, width, precision=precision)
+    d, keep = net_desc(n_qubits, n_layers, width, precision=precision, phase_mode=phase_mode)
     out = C.c_int64()
     L.check(lib.nqs_net_param_count(C.byref(d), C.byref(out)), "nqs_net_param_count")
     return out.value
@@ -123,12 +126,12 @@ class Plan:
     """Kernel variants, chunking and workspace layout for one (H, network) pair."""
 
     def __init__(self, ctx, ham, n_layers, width, n_up=-1, n_dn=-1, precision="fp32",
-                 max_batch=1024, dedup=False, chunk_samples=0, order=None):
-        """dedup: True, False or "auto" (the autotuner decides)."""
+                 max_batch=1024, dedup=False, chunk_samples=0, order=None, phase_mode=0):
+        """dedup: True, False or "auto" (the autotuner decides); phase_mode as in net_desc."""
         self.lib = L.load()
         self.ctx, self.ham = ctx, ham
         self.precision = precision
-        d, self._order = net_desc(ham.n, n_layers, width, n_up, n_dn, precision, order)
+        d, self._order = net_desc(ham.n, n_layers, width, n_up, n_dn, precision, order, phase_mode)
         if dedup == "auto":
             flags = L.NQS_PLAN_DEDUP_AUTO
         else:

@@ -24,14 +24,31 @@ __device__ __forceinline__ bool mask_at(const Geom& g, int kind, int row, int co
 }
 
 // Which tensor of the flat layout holds parameter p: returns kind and
-// (row, col) for weights, or -1 kind for a bias.
+// (row, col) for weights, or -1 kind for a bias.  The layers of a separate
+// phase network and its head are dense (MK_NONE).
 __device__ __forceinline__ void locate(const Geom& g, long long p, int& tensor, int& kind, int& row,
                                        int& col, int& in) {
   const int L = g.L;
+  const int ntens = g.phase_mode ? 4 * L + 4 : 2 * L + 4;
   int t = 0;
-  while (t + 1 < 2 * L + 4 && p >= g.poff[t + 1]) ++t;
+  while (t + 1 < ntens && p >= g.poff[t + 1]) ++t;
   tensor = t;
   const long long local = p - g.poff[t];
+  if (g.phase_mode && t >= 2 * L + 2 && t < 4 * L + 2) {
+    const int l = (t - 2 * L - 2) / 2 + 1;
+    in = l == 1 ? g.n - 2 : g.h;
+    if ((t - 2 * L - 2) % 2 == 0) {
+      kind = MK_NONE;
+      row = (int)(local / in);
+      col = (int)(local % in);
+    } else {
+      kind = -1;
+      row = (int)local;
+      col = 0;
+    }
+    return;
+  }
+  if (g.phase_mode && t >= 4 * L + 2) t -= 2 * L;   // the phase head, as a head below
   if (t < 2 * L) {
     const int l = t / 2;
     in = l == 0 ? g.n : g.h;
@@ -48,7 +65,7 @@ __device__ __forceinline__ void locate(const Geom& g, long long p, int& tensor, 
     const int k = t - 2 * L;   // 0 W_o, 1 b_o, 2 W_p, 3 b_p
     in = g.h;
     if (k == 0 || k == 2) {
-      kind = k == 0 ? MK_HEAD_O : MK_HEAD_P;
+      kind = k == 0 ? MK_HEAD_O : (g.phase_mode ? MK_NONE : MK_HEAD_P);
       row = (int)(local / g.h);
       col = (int)(local % g.h);
     } else {
@@ -91,6 +108,18 @@ void launch_pack_masked(const Geom& g, const float* params, void* wm, hipStream_
 // sorted row `row` and packed column `k`, zero where masked or out of range.
 __device__ float packed_value(const Geom& g, const float* params, int part, int layer, int row, int k) {
   const int n = g.n, h = g.h;
+  if (g.net_kind == 2) {         // separate phase network: dense, units in their own order
+    if (part == 0) {             // columns: the first n-2 positions
+      if (row >= h || k >= n - 2) return 0.f;
+      return params[g.poff[poff_phase_layer(g, 1)] + (long long)row * (n - 2) + k];
+    }
+    if (part == 1) {
+      if (row >= h || k >= h) return 0.f;
+      return params[g.poff[poff_phase_layer(g, layer)] + (long long)row * h + k];
+    }
+    if (row >= 4 || k >= h) return 0.f;
+    return params[g.poff[poff_phase_head(g)] + (long long)row * h + k];
+  }
   if (part == 0) {               // layer 1: rows sorted units, cols positions
     if (row >= h || k >= n) return 0.f;
     const int deg = class_of_sorted(g, row) + 1;
@@ -109,8 +138,8 @@ __device__ float packed_value(const Geom& g, const float* params, int part, int 
     if (!(k < prefix_of_class(g, row))) return 0.f;
     return params[g.poff[2 * g.L] + (long long)g.order[row] * h + orig_of_sorted(g, k)];
   }
-  if (!(k < prefix_of_class(g, n - 2))) return 0.f;
-  return params[g.poff[2 * g.L + 2] + (long long)(row - n) * h + orig_of_sorted(g, k)];
+  if (g.net_kind == 1 || !(k < prefix_of_class(g, n - 2))) return 0.f;
+  return params[g.poff[poff_phase_head(g)] + (long long)(row - n) * h + orig_of_sorted(g, k)];
 }
 
 __global__ void pack_fused_kernel(Geom g, const float* __restrict__ params, uint4* __restrict__ out) {
@@ -177,13 +206,21 @@ __global__ void pack_bias_kernel(Geom g, const float* __restrict__ params, S* __
   const long long total = nh + (long long)g.NHB * g.TB;
   if (i >= total) return;
   S v = 0;
-  if (i < nh) {
+  if (g.net_kind == 2) {
+    if (i < nh) {
+      const int l = (int)(i / g.h), u = (int)(i % g.h);
+      v = (S)params[g.poff[poff_phase_layer(g, l + 1) + 1] + u];
+    } else {
+      const int t = (int)(i - nh);
+      if (t < 4) v = (S)params[g.poff[poff_phase_head(g) + 1] + t];
+    }
+  } else if (i < nh) {
     const int l = (int)(i / g.h), u = (int)(i % g.h);
     v = (S)params[g.poff[2 * l + 1] + orig_of_sorted(g, u)];
   } else {
     const int t = (int)(i - nh);
     if (t < g.n) v = (S)params[g.poff[2 * g.L + 1] + g.order[t]];
-    else if (t < g.n + 4) v = (S)params[g.poff[2 * g.L + 3] + (t - g.n)];
+    else if (t < g.n + 4 && g.net_kind == 0) v = (S)params[g.poff[poff_phase_head(g) + 1] + (t - g.n)];
   }
   b[i] = v;
 }
@@ -341,38 +378,105 @@ __global__ void seed_kernel(Geom g, const uint64_t* __restrict__ x, long long S,
   for (int c = 0; c < 4; ++c) dh[i * ld + n + c] = c == sel ? (T)gph : (T)0;
 }
 
+// Input of a separate phase network: the first n-2 entries in sampling order.
+template <typename T>
+__global__ void phase_input_kernel(Geom g, const T* __restrict__ s, long long S, T* __restrict__ v) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int np = g.n - 2;
+  if (e >= S * np) return;
+  const long long i = e / np;
+  const int t = (int)(e % np);
+  v[e] = s[i * g.n + g.order[t]];
+}
+
+// Forward of L ReLU layers over S rows: acts[l] = relu(in_l W_l^T + b_l), the
+// weight and bias of layer l at poff[wi(l)], poff[wi(l) + 1].
+template <typename T, class WIdx>
+static void mlp_forward(const Geom& g, const T* wm, const T* in0, int k0, long long S, T* acts, WIdx wi,
+                        hipStream_t s) {
+  const int h = g.h;
+  for (int l = 1; l <= g.L; ++l) {
+    const int K = l == 1 ? k0 : h;
+    GemmArgs a{};
+    a.Mr = (int)S; a.Nc = h; a.K = K;
+    a.A = l == 1 ? (const void*)in0 : (const void*)(acts + (long long)(l - 2) * S * h);
+    a.sa0 = K; a.sa1 = 1;
+    a.B = wm + g.poff[wi(l)]; a.sb0 = 1; a.sb1 = K;
+    a.C = acts + (long long)(l - 1) * S * h; a.ldc = h;
+    a.bias = wm + g.poff[wi(l) + 1];
+    gemm<T, E_FWD>(a, g, s);
+  }
+}
+
+// Reverse pass through those layers from d(acts[L]) in da: gradients of the
+// weights (masked by mask_of(l)) and biases; da and dz are S x h scratch.
+template <typename T, class WIdx, class MIdx>
+static void mlp_backward(const Geom& g, const T* wm, const T* in0, int k0, long long S, const T* acts, T* da,
+                         T* dz, double* grad, WIdx wi, MIdx mask_of, hipStream_t s) {
+  const int h = g.h;
+  for (int l = g.L; l >= 1; --l) {
+    const int K = l == 1 ? k0 : h;
+    const T* act = acts + (long long)(l - 1) * S * h;
+    const T* prev = l == 1 ? in0 : acts + (long long)(l - 2) * S * h;
+    const long long cnt = S * h;
+    hipLaunchKernelGGL(relu_mask_kernel<T>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, act, da, cnt);
+    GemmArgs a{};
+    a.Mr = h; a.Nc = K; a.K = (int)S;
+    a.A = da; a.sa0 = 1; a.sa1 = h;
+    a.B = prev; a.sb0 = K; a.sb1 = 1;
+    a.grad = grad; a.grad_off = g.poff[wi(l)]; a.grad_ld = K;
+    a.mask_kind = mask_of(l);
+    gemm<T, E_GRAD>(a, g, s);
+    hipLaunchKernelGGL(colsum_kernel<T>, dim3((unsigned)((h + 255) / 256)), dim3(256), 0, s, da, S, h,
+                       (long long)h, grad, g.poff[wi(l) + 1]);
+    if (l > 1) {
+      GemmArgs b{};
+      b.Mr = (int)S; b.Nc = K; b.K = h;
+      b.A = da; b.sa0 = h; b.sa1 = 1;
+      b.B = wm + g.poff[wi(l)]; b.sb0 = K; b.sb1 = 1;
+      b.C = dz; b.ldc = K;
+      gemm<T, E_STORE>(b, g, s);
+      T* t = da; da = dz; dz = t;
+    }
+  }
+}
+
 template <typename T>
 static void backward_t(const Geom& g, const T* wm, const uint64_t* x, long long S, const double* eloc,
                        const double* w, const double* energy, T* scratch, double* grad, hipStream_t s) {
   const int n = g.n, h = g.h, L = g.L, ld = n + 4;
+  const bool two = g.phase_mode == 1;
   T* sb = scratch;
   T* acts = sb + S * n;
   T* hout = acts + (long long)L * S * h;
   T* dh = hout + S * ld;
   T* da = dh + S * ld;
   T* dz = da + S * h;
+  T* pin = dz + S * h;                     // separate phase network: input and activations
+  T* pacts = pin + S * (n - 2);
   const unsigned eb = (unsigned)((S * n + 255) / 256);
   hipLaunchKernelGGL(bits_kernel<T>, dim3(eb), dim3(256), 0, s, g, x, S, sb);
   // forward recompute
-  for (int l = 1; l <= L; ++l) {
-    const int K = l == 1 ? n : h;
-    GemmArgs a{};
-    a.Mr = (int)S; a.Nc = h; a.K = K;
-    a.A = l == 1 ? (const void*)sb : (const void*)(acts + (long long)(l - 2) * S * h);
-    a.sa0 = K; a.sa1 = 1;
-    a.B = wm + g.poff[2 * (l - 1)]; a.sb0 = 1; a.sb1 = K;
-    a.C = acts + (long long)(l - 1) * S * h; a.ldc = h;
-    a.bias = wm + g.poff[2 * (l - 1) + 1];
-    gemm<T, E_FWD>(a, g, s);
-  }
+  auto trunk_w = [&](int l) { return 2 * (l - 1); };
+  auto phase_w = [&](int l) { return poff_phase_layer(g, l); };
+  mlp_forward<T>(g, wm, sb, n, S, acts, trunk_w, s);
   const T* aL = acts + (long long)(L - 1) * S * h;
+  const T* phin = aL;                      // what the phase head reads
+  if (two) {
+    const long long ne = S * (n - 2);
+    hipLaunchKernelGGL(phase_input_kernel<T>, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, g,
+                       (const T*)sb, S, pin);
+    mlp_forward<T>(g, wm, pin, n - 2, S, pacts, phase_w, s);
+    phin = pacts + (long long)(L - 1) * S * h;
+  }
+  const int hw[2] = {2 * L, poff_phase_head(g)};
   for (int part = 0; part < 2; ++part) {
     GemmArgs a{};
     a.Mr = (int)S; a.Nc = part == 0 ? n : 4; a.K = h;
-    a.A = aL; a.sa0 = h; a.sa1 = 1;
-    a.B = wm + g.poff[2 * L + 2 * part]; a.sb0 = 1; a.sb1 = h;
+    a.A = part == 0 ? aL : phin; a.sa0 = h; a.sa1 = 1;
+    a.B = wm + g.poff[hw[part]]; a.sb0 = 1; a.sb1 = h;
     a.C = hout + (part == 0 ? 0 : n); a.ldc = ld;
-    a.bias = wm + g.poff[2 * L + 2 * part + 1];
+    a.bias = wm + g.poff[hw[part] + 1];
     gemm<T, E_FWD_LIN>(a, g, s);
   }
   hipLaunchKernelGGL(seed_kernel<T>, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, s, g, x, S, eloc, w,
@@ -382,14 +486,14 @@ static void backward_t(const Geom& g, const T* wm, const uint64_t* x, long long 
     GemmArgs a{};
     a.Mr = part == 0 ? n : 4; a.Nc = h; a.K = (int)S;
     a.A = dh + (part == 0 ? 0 : n); a.sa0 = 1; a.sa1 = ld;
-    a.B = aL; a.sb0 = h; a.sb1 = 1;
-    a.grad = grad; a.grad_off = g.poff[2 * L + 2 * part]; a.grad_ld = h;
-    a.mask_kind = part == 0 ? MK_HEAD_O : MK_HEAD_P;
+    a.B = part == 0 ? aL : phin; a.sb0 = h; a.sb1 = 1;
+    a.grad = grad; a.grad_off = g.poff[hw[part]]; a.grad_ld = h;
+    a.mask_kind = part == 0 ? MK_HEAD_O : (two ? MK_NONE : MK_HEAD_P);
     gemm<T, E_GRAD>(a, g, s);
     hipLaunchKernelGGL(colsum_kernel<T>, dim3((unsigned)((a.Mr + 255) / 256)), dim3(256), 0, s,
-                       dh + (part == 0 ? 0 : n), S, a.Mr, (long long)ld, grad, g.poff[2 * L + 2 * part + 1]);
+                       dh + (part == 0 ? 0 : n), S, a.Mr, (long long)ld, grad, g.poff[hw[part] + 1]);
   }
-  // d a_L = d o (M_o W_o) + d p (M_p W_p)
+  // d a_L = d o (M_o W_o) [+ d p (M_p W_p) with the shared trunk]
   {
     GemmArgs a{};
     a.Mr = (int)S; a.Nc = h; a.K = n;
@@ -397,40 +501,31 @@ static void backward_t(const Geom& g, const T* wm, const uint64_t* x, long long 
     a.B = wm + g.poff[2 * L]; a.sb0 = h; a.sb1 = 1;
     a.C = da; a.ldc = h;
     gemm<T, E_STORE>(a, g, s);
-    a.K = 4;
-    a.A = dh + n;
-    a.B = wm + g.poff[2 * L + 2];
-    gemm<T, E_ADD>(a, g, s);
-  }
-  for (int l = L; l >= 1; --l) {
-    const int K = l == 1 ? n : h;
-    const T* act = acts + (long long)(l - 1) * S * h;
-    const T* prev = l == 1 ? sb : acts + (long long)(l - 2) * S * h;
-    const long long cnt = S * h;
-    hipLaunchKernelGGL(relu_mask_kernel<T>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, act, da, cnt);
-    GemmArgs a{};
-    a.Mr = h; a.Nc = K; a.K = (int)S;
-    a.A = da; a.sa0 = 1; a.sa1 = h;
-    a.B = prev; a.sb0 = K; a.sb1 = 1;
-    a.grad = grad; a.grad_off = g.poff[2 * (l - 1)]; a.grad_ld = K;
-    a.mask_kind = l == 1 ? MK_L1 : MK_HID;
-    gemm<T, E_GRAD>(a, g, s);
-    hipLaunchKernelGGL(colsum_kernel<T>, dim3((unsigned)((h + 255) / 256)), dim3(256), 0, s, da, S, h,
-                       (long long)h, grad, g.poff[2 * (l - 1) + 1]);
-    if (l > 1) {
-      GemmArgs b{};
-      b.Mr = (int)S; b.Nc = K; b.K = h;
-      b.A = da; b.sa0 = h; b.sa1 = 1;
-      b.B = wm + g.poff[2 * (l - 1)]; b.sb0 = K; b.sb1 = 1;
-      b.C = dz; b.ldc = K;
-      gemm<T, E_STORE>(b, g, s);
-      T* t = da; da = dz; dz = t;
+    if (!two) {
+      a.K = 4;
+      a.A = dh + n;
+      a.B = wm + g.poff[hw[1]];
+      gemm<T, E_ADD>(a, g, s);
     }
+  }
+  mlp_backward<T>(g, wm, sb, n, S, acts, da, dz, grad, trunk_w,
+                  [&](int l) { return l == 1 ? (int)MK_L1 : (int)MK_HID; }, s);
+  if (two) {
+    // d c_L = d p W_p, then through the phase network's dense layers
+    GemmArgs a{};
+    a.Mr = (int)S; a.Nc = h; a.K = 4;
+    a.A = dh + n; a.sa0 = ld; a.sa1 = 1;
+    a.B = wm + g.poff[hw[1]]; a.sb0 = h; a.sb1 = 1;
+    a.C = da; a.ldc = h;
+    gemm<T, E_STORE>(a, g, s);
+    mlp_backward<T>(g, wm, pin, n - 2, S, pacts, da, dz, grad, phase_w, [&](int) { return (int)MK_NONE; }, s);
   }
 }
 
 long long backward_scratch_elems(const Geom& g, long long S) {
-  return S * (long long)(g.n + (long long)g.L * g.h + 2 * (g.n + 4) + 2 * g.h);
+  long long e = S * (long long)(g.n + (long long)g.L * g.h + 2 * (g.n + 4) + 2 * g.h);
+  if (g.phase_mode == 1) e += S * (long long)((g.n - 2) + (long long)g.L * g.h);
+  return e;
 }
 
 void launch_backward(const Geom& g, const void* wm, const uint64_t* x, long long S,

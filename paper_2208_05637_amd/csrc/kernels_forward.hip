@@ -15,6 +15,9 @@
 //   * the head produces the n conditional logits and the 4 phases; the
 //     per-row epilogue applies the Hamming-weight modifier (Eq. modifier),
 //     sums the log-sigmoids of free positions in FP64 and selects the phase.
+// A model with a separate phase network runs the same kernel twice over the
+// same rows: the modulus network (writes log|psi|) and the phase network
+// (dense layers over the first n-2 positions, a 4-row head; writes phi).
 // Arithmetic kinds: FP64 and FP32 MFMA; plain BF16; split BF16 (weights and
 // activations as hi + lo BF16 planes, three products); BF16 weights with
 // hi + lo activations (two products).  With two activation planes a tile
@@ -600,7 +603,7 @@ __device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict_
   // Work items (head n-block, m-block, k slice) are spread over all waves;
   // k slices of one tile are summed from their staging planes in the epilogue.
   Acc hacc[HP];
-  const int nho = g.n + 4;   // head outputs: n conditionals, 4 phases
+  const int nho = g.net_kind == 2 ? 4 : g.n + 4;   // head outputs: n conditionals, 4 phases
   S hbreg = tid < nho ? biases[(long)g.L * H + tid] : S(0);
   const int npairs = g.NHB * MB;
   const int ksplit = npairs >= NW ? 1 : min(KSPLIT_MAX, NW / npairs);
@@ -662,6 +665,14 @@ __device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict_
     int bad = 0;
     const uint64_t sp0 = g.spin_pos[0], sp1 = g.spin_pos[1];
     const long long grow = row0 + row;
+    if (g.net_kind == 2) {
+      // separate phase network: the phase of the completion of the last two positions
+      if (sub == 0 && grow < count) {
+        const int sel = (int)(2 * ((y >> (g.n - 2)) & 1ull) + ((y >> (g.n - 1)) & 1ull));
+        ((double*)out)[2 * grow + 1] = (double)head_out(sel);
+      }
+      return;
+    }
     if (cond >= 0) {
       // sampler: the conditional logit at position cond and its forcing,
       // from the bits before it (later bits do not enter)
@@ -706,9 +717,14 @@ __device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict_
       bad |= __shfl_xor(bad, off);
     }
     if (sub == 0 && grow < count) {
-      const int sel = (int)(2 * ((y >> (g.n - 2)) & 1ull) + ((y >> (g.n - 1)) & 1ull));
-      const double phi = (double)head_out(g.n + sel);
-      out[grow] = make_double2(bad ? -INFINITY : 0.5 * sum, phi);
+      const double la = bad ? -INFINITY : 0.5 * sum;
+      if (g.net_kind == 1) {
+        // modulus network of a two-network model: the phase network writes phi
+        ((double*)out)[2 * grow] = la;
+      } else {
+        const int sel = (int)(2 * ((y >> (g.n - 2)) & 1ull) + ((y >> (g.n - 1)) & 1ull));
+        out[grow] = make_double2(la, (double)head_out(g.n + sel));
+      }
     }
   }
 }

@@ -100,7 +100,10 @@ struct nqs_plan {
   int64_t HT = 0;          // dedup hash slots
   int64_t Sb = 0;          // backward chunk
   int bw = 4;              // bytes per element of the backward path
-  size_t packed_bytes = 0;
+  Geom gp{};               // the separate phase network (phase_mode 1)
+  bool two = false;        // phase_mode 1: modulus network g and phase network gp
+  size_t packed_bytes = 0; // packed weights of g, then (two) of gp at packed_phase
+  size_t packed_phase = 0;
   double flops_alg_row = 0, flops_exec_row = 0;   // forward flops per configuration
   // profiling
   struct Rec { hipEvent_t a, b; int kind; int slot; };   // kind 0 call, 1 eloc, 2 forward
@@ -132,7 +135,7 @@ static WsLayout layout(const nqs_plan* p, int64_t B) {
   const int hs = p->ham->has_imag ? 2 : 1;
   L.err = take(256);
   L.prof = take((size_t)kProfSlots * 8);
-  L.geom = take(sizeof(Geom));
+  L.geom = take(2 * sizeof(Geom));
   L.packed = take(p->packed_bytes);
   L.wm = take((size_t)p->g.n_params * p->bw);
   L.lps = take((size_t)std::max<int64_t>(B, 1) * 16);
@@ -362,6 +365,10 @@ static nqs_status build_geom(const nqs_net_desc* nd, Geom& g) {
     return fail(NQS_ERR_INVALID_ARGUMENT, "unknown precision %d", nd->precision);
   if (!forward_supported(nd->precision, h))
     return fail(NQS_ERR_UNSUPPORTED, "width %d not supported for precision %d", h, nd->precision);
+  if (nd->phase_mode != 0 && nd->phase_mode != 1)
+    return fail(NQS_ERR_INVALID_ARGUMENT, "phase_mode %d is neither 0 nor 1", nd->phase_mode);
+  if (nd->phase_mode == 1 && n < 3)
+    return fail(NQS_ERR_UNSUPPORTED, "a separate phase network needs n_qubits >= 3");
   const bool cons = nd->n_up >= 0 || nd->n_dn >= 0;
   if (cons && (nd->n_up < 0 || nd->n_dn < 0 || nd->n_up > (n + 1) / 2 || nd->n_dn > n / 2))
     return fail(NQS_ERR_INVALID_ARGUMENT, "invalid sector (%d, %d)", nd->n_up, nd->n_dn);
@@ -384,6 +391,8 @@ static nqs_status build_geom(const nqs_net_desc* nd, Geom& g) {
     rev = rev && order[t] == n - 1 - t;
   }
   g.order_kind = ident ? 1 : (rev ? 2 : 0);
+  g.phase_mode = nd->phase_mode;
+  g.net_kind = nd->phase_mode == 1 ? 1 : 0;
   g.TB = g.prec == P_F64 ? 16 : 32;
   g.KSTEP = (g.prec == P_BF16 || g.prec == P_BF16X3 || g.prec == P_BF16W) ? 16 : 8;
   g.NB = h / g.TB;
@@ -410,8 +419,9 @@ static nqs_status build_geom(const nqs_net_desc* nd, Geom& g) {
   }
   for (int nb = 0; nb < g.NHB; ++nb) {
     int kend = 0;
+    // (the phase rows of the modulus network of phase_mode 1 are zero and read nothing)
     for (int t = g.TB * nb; t < std::min(g.TB * (nb + 1), g.nhead); ++t)
-      kend = std::max(kend, t < n ? prefix_of_class(g, t) : prefix_of_class(g, n - 2));
+      if (t < n || g.net_kind == 0) kend = std::max(kend, t < n ? prefix_of_class(g, t) : prefix_of_class(g, n - 2));
     g.kso[nb] = (((kend + g.KSTEP - 1) / g.KSTEP) + 7) & ~7;   // head: multiples of 8 steps
     g.offo[nb + 1] = g.offo[nb] + g.kso[nb];
   }
@@ -428,10 +438,51 @@ static nqs_status build_geom(const nqs_net_desc* nd, Geom& g) {
   }
   g.poff[2 * L] = o; o += (long long)n * h;
   g.poff[2 * L + 1] = o; o += n;
-  g.poff[2 * L + 2] = o; o += 4LL * h;
-  g.poff[2 * L + 3] = o; o += 4;
+  if (g.phase_mode == 1) {
+    for (int l = 1; l <= L; ++l) {
+      const int in = l == 1 ? n - 2 : h;
+      g.poff[poff_phase_layer(g, l)] = o; o += (long long)h * in;
+      g.poff[poff_phase_layer(g, l) + 1] = o; o += h;
+    }
+  }
+  g.poff[poff_phase_head(g)] = o; o += 4LL * h;
+  g.poff[poff_phase_head(g) + 1] = o; o += 4;
   g.n_params = o;
   return NQS_OK;
+}
+
+// Geometry of the separate phase network of a phase_mode 1 model (net_kind 2):
+// dense layers of width h over the first n-2 positions, a 4-row head, units
+// in their own order.  Same precision, tile shape and sampling order as the
+// modulus network gm, whose parameter offsets it shares.
+static void build_phase_geom(const Geom& gm, Geom& g) {
+  g = gm;
+  g.net_kind = 2;
+  g.nhead = 4;
+  g.NHB = 1;
+  const int KS = g.h / g.KSTEP;
+  const int k1 = ((((g.n - 2) + g.KSTEP - 1) / g.KSTEP) + 1) & ~1;   // even, as in the modulus network
+  const int kh = (KS + 1) & ~1;
+  g.off1[0] = g.offh[0] = g.offo[0] = 0;
+  for (int nb = 0; nb < g.NB; ++nb) {
+    g.ks1[nb] = k1;
+    g.ksh[nb] = kh;
+    g.off1[nb + 1] = g.off1[nb] + k1;
+    g.offh[nb + 1] = g.offh[nb] + kh;
+  }
+  for (int nb = g.NB; nb < kMaxNB; ++nb) g.ks1[nb] = g.ksh[nb] = 0;
+  g.kso[0] = (KS + 7) & ~7;
+  g.offo[1] = g.kso[0];
+  for (int nb = 1; nb < kMaxNHB; ++nb) g.kso[nb] = 0;
+  g.frag_h = g.off1[g.NB];
+  g.frag_head = g.frag_h + (long long)(g.L - 1) * g.offh[g.NB];
+  g.nfrag = g.frag_head + g.offo[1];
+  g.bias_byte = (long long)align256((size_t)g.nfrag * 1024 * g.planes);
+  g.head_bias_off = (long long)g.L * g.h;
+}
+
+static size_t packed_bytes_of(const Geom& g) {
+  return (size_t)g.bias_byte + ((size_t)g.L * g.h + (size_t)g.NHB * g.TB) * g.acc_bytes;
 }
 
 nqs_status nqs_net_param_count(const nqs_net_desc* nd, int64_t* n_params) {
@@ -514,7 +565,13 @@ nqs_status nqs_plan_create(nqs_ctx* ctx, const nqs_ham* ham, const nqs_net_desc*
   }
   p->Sb = std::min<int64_t>(max_batch, 4096);
   p->bw = g.prec == P_F64 ? 8 : 4;
-  p->packed_bytes = (size_t)g.bias_byte + ((size_t)g.L * g.h + (size_t)g.NHB * g.TB) * g.acc_bytes;
+  p->packed_bytes = packed_bytes_of(g);
+  if (g.phase_mode == 1) {
+    p->two = true;
+    build_phase_geom(g, p->gp);
+    p->packed_phase = align256(p->packed_bytes);
+    p->packed_bytes = p->packed_phase + packed_bytes_of(p->gp);
+  }
   {
     // unmasked weights per configuration (MADE masks) and MFMA work issued
     const int n = g.n, h = g.h;
@@ -527,10 +584,12 @@ nqs_status nqs_plan_create(nqs_ctx* ctx, const nqs_ham* ham, const nqs_net_desc*
     for (int k = 0; k < h; ++k) {
       nnz1 += std::min(m[k], n);
       nnzh += (double)cnt_le[m[k]];
-      if (m[k] <= n - 2) nnzp += 4;
+      if (m[k] <= n - 2 && !p->two) nnzp += 4;
     }
     for (int j = 0; j < n; ++j) nnzo += (double)cnt_le[j];   // d(j) = 1 + pos: units with m < d
-    p->flops_alg_row = 2.0 * (nnz1 + (g.L - 1) * nnzh + nnzo + nnzp);
+    // separate phase network: dense (n-2) x h, (L-1) h x h, 4 x h
+    const double nnz_phase = p->two ? (double)(n - 2) * h + (double)(g.L - 1) * h * h + 4.0 * h : 0.0;
+    p->flops_alg_row = 2.0 * (nnz1 + (g.L - 1) * nnzh + nnzo + nnzp + nnz_phase);
     // fragments issued per configuration; split BF16 multiplies each with
     // three BF16 MFMAs, BF16 weights with two; one fewer in layer 1 (its +-1
     // inputs have no low part)
@@ -540,6 +599,14 @@ nqs_status nqs_plan_create(nqs_ctx* ctx, const nqs_ham* ham, const nqs_net_desc*
       fr += (long long)(g.L - 1) * g.ksh[nb];
     }
     for (int nb = 0; nb < g.NHB; ++nb) fr += g.kso[nb];
+    if (p->two) {
+      const Geom& q = p->gp;
+      for (int nb = 0; nb < q.NB; ++nb) {
+        fr1 += q.ks1[nb];
+        fr += (long long)(q.L - 1) * q.ksh[nb];
+      }
+      fr += q.kso[0];
+    }
     const double mult = g.prec == P_BF16X3 ? 3.0 : (g.prec == P_BF16W ? 2.0 : 1.0);
     const double mult1 = mult > 1.0 ? mult - 1.0 : 1.0;
     p->flops_exec_row = 2.0 * g.TB * g.KSTEP * (mult1 * (double)fr1 + mult * (double)fr);
@@ -636,6 +703,21 @@ static void prof_close(nqs_plan* p, hipEvent_t a, int kind, int slot) {
   if (b) p->recs.push_back({a, b, kind, slot});
 }
 
+// Packed weights of the plan's network(s) into the packed region.
+static void pack_net(const nqs_plan* p, const float* params, void* packed, hipStream_t s) {
+  launch_pack_fused(p->g, params, packed, s);
+  if (p->two) launch_pack_fused(p->gp, params, (char*)packed + p->packed_phase, s);
+}
+
+// log psi of rows [0, min(*d_count, bound)) of x: one launch, or two (modulus
+// network, then phase network over the same rows) for a separate phase network.
+static void forward_net(const nqs_plan* p, const void* packed, const uint64_t* x, long long bound,
+                        const long long* d_count, double* out, long long* slot, hipStream_t s) {
+  launch_forward(p->g, p->variant, packed, x, bound, d_count, out, slot, s);
+  if (p->two)
+    launch_forward(p->gp, p->variant, (const char*)packed + p->packed_phase, x, bound, d_count, out, nullptr, s);
+}
+
 static void forward_profiled(nqs_plan* p, void* ws, const WsLayout& L, const void* packed,
                              const uint64_t* x, long long bound, const long long* d_count, double* out) {
   hipEvent_t a = prof_mark(p);
@@ -645,7 +727,7 @@ static void forward_profiled(nqs_plan* p, void* ws, const WsLayout& L, const voi
     si = p->next_slot++;
     slot = at<long long>(ws, L.prof) + si;
   }
-  launch_forward(p->g, p->variant, packed, x, bound, d_count, out, slot, p->ctx->stream);
+  forward_net(p, packed, x, bound, d_count, out, slot, p->ctx->stream);
   prof_close(p, a, 2, si);
 }
 
@@ -696,7 +778,7 @@ static void reduce_chunk(nqs_plan* p, int64_t c0, int64_t Sc, void* ws, const Ws
 static nqs_status run_local_energy(nqs_plan* p, const float* params, const uint64_t* x, int64_t B,
                                    double* eloc, void* ws, const WsLayout& L) {
   void* packed = at<void>(ws, L.packed);
-  launch_pack_fused(p->g, params, packed, p->ctx->stream);
+  pack_net(p, params, packed, p->ctx->stream);
   forward_profiled(p, ws, L, packed, x, B, nullptr, at<double>(ws, L.lps));
   for (int64_t c0 = 0; c0 < B; c0 += p->S) {
     const int64_t Sc = std::min<int64_t>(p->S, B - c0);
@@ -736,8 +818,8 @@ nqs_status nqs_log_psi(nqs_plan* p, const float* params, const uint64_t* x, int6
   if (n == 0) return NQS_OK;
   hipStream_t s = p->ctx->stream;
   void* packed = at<void>(ws, L.packed);
-  launch_pack_fused(p->g, params, packed, s);
-  launch_forward(p->g, p->variant, packed, x, n, nullptr, out, nullptr, s);
+  pack_net(p, params, packed, s);
+  forward_net(p, packed, x, n, nullptr, out, nullptr, s);
   return launch_check("log psi");
 }
 
@@ -834,8 +916,23 @@ nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* ws,
     EL[i] = inst[i].d_eloc ? inst[i].d_eloc : at<double>(W[i], L[i].eloc);
     launch_fill_u32(at<void>(W[i], L[i].err), 0u, 1, s);
     launch_store_geom(p->g, at<Geom>(W[i], L[i].geom), s);
-    launch_pack_fused(p->g, inst[i].d_params, at<void>(W[i], L[i].packed), s);
+    if (p->two) launch_store_geom(p->gp, at<Geom>(W[i], L[i].geom) + 1, s);
+    pack_net(p, inst[i].d_params, at<void>(W[i], L[i].packed), s);
   }
+  // the forward segments of instance i's rows: its network, and with a
+  // separate phase network a second segment that writes the phases
+  auto add_segs = [&](int i, const uint64_t* x, const long long* d_count, double* out, long long bound,
+                      std::vector<int>& ids, std::vector<FwdSeg>& segs) {
+    const nqs_plan* p = inst[i].plan;
+    ids.push_back(i);
+    segs.push_back(FwdSeg{at<Geom>(W[i], L[i].geom), at<void>(W[i], L[i].packed), x, d_count, out, bound, 0,
+                          nullptr});
+    if (p->two) {
+      ids.push_back(i);
+      segs.push_back(FwdSeg{at<Geom>(W[i], L[i].geom) + 1, at<char>(W[i], L[i].packed) + p->packed_phase, x,
+                            d_count, out, bound, 0, nullptr});
+    }
+  };
   // One forward launch per group of segments whose networks share
   // (precision, width, variant): the segments' tiles form one work list.
   auto launch_groups = [&](const std::vector<int>& ids, const std::vector<FwdSeg>& segs) {
@@ -860,16 +957,14 @@ nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* ws,
   };
   std::vector<int> ids;
   std::vector<FwdSeg> segs;
-  for (int i = 0; i < n_inst; ++i) {
-    ids.push_back(i);
-    segs.push_back(FwdSeg{at<Geom>(W[i], L[i].geom), at<void>(W[i], L[i].packed), inst[i].d_samples, nullptr,
-                          at<double>(W[i], L[i].lps), inst[i].B, 0, nullptr});
-  }
+  for (int i = 0; i < n_inst; ++i)
+    add_segs(i, inst[i].d_samples, nullptr, at<double>(W[i], L[i].lps), inst[i].B, ids, segs);
   launch_groups(ids, segs);
   // chunk rounds: round r takes chunk r of every instance that still has one
   for (int64_t r = 0;; ++r) {
     ids.clear();
     segs.clear();
+    std::vector<int> rid;
     std::vector<int64_t> c0s, scs;
     for (int i = 0; i < n_inst; ++i) {
       nqs_plan* p = inst[i].plan;
@@ -877,15 +972,14 @@ nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* ws,
       if (c0 >= inst[i].B) continue;
       const int64_t Sc = std::min<int64_t>(p->S, inst[i].B - c0);
       const ChunkFwd cf = enum_chunk(p, inst[i].d_samples, c0, Sc, W[i], L[i]);
-      ids.push_back(i);
+      rid.push_back(i);
       c0s.push_back(c0);
       scs.push_back(Sc);
-      segs.push_back(FwdSeg{at<Geom>(W[i], L[i].geom), at<void>(W[i], L[i].packed), cf.x, cf.d_count, cf.out,
-                            cf.bound, 0, nullptr});
+      add_segs(i, cf.x, cf.d_count, cf.out, cf.bound, ids, segs);
     }
     if (ids.empty()) break;
     launch_groups(ids, segs);
-    for (size_t k = 0; k < ids.size(); ++k) reduce_chunk(inst[ids[k]].plan, c0s[k], scs[k], W[ids[k]], L[ids[k]], EL[ids[k]]);
+    for (size_t k = 0; k < rid.size(); ++k) reduce_chunk(inst[rid[k]].plan, c0s[k], scs[k], W[rid[k]], L[rid[k]], EL[rid[k]]);
   }
   for (int i = 0; i < n_inst; ++i) {
     const nqs_instance& I = inst[i];
@@ -900,14 +994,14 @@ nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* ws,
 
 // ------------------------------------------------------------- autotuner
 namespace {
-using TuneKey = std::tuple<int, int, int, int, int64_t, int64_t, int64_t, int64_t, int, int>;
+using TuneKey = std::tuple<int, int, int, int, int64_t, int64_t, int64_t, int64_t, int, int, int>;
 struct TuneVal { int variant; bool dedup; int64_t S; double ms; };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune_cache;
 
 TuneKey tune_key(const nqs_plan* p) {
   return TuneKey{p->g.n, p->g.L, p->g.h, p->g.prec, (int64_t)p->ham->tz.size(), (int64_t)p->ham->gx.size(),
-                 p->Emax, p->S0, p->dedup_auto ? 1 : 0, p->ctx->device};
+                 p->Emax, p->S0, p->dedup_auto ? 1 : 0, p->ctx->device, p->g.phase_mode};
 }
 
 void set_chunk(nqs_plan* p, int64_t S) {

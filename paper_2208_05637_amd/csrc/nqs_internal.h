@@ -30,6 +30,11 @@ struct Geom {
   int planes;               // 2 for split bf16 (hi, lo), else 1
   int acc_bytes;            // 8 for the FP64 path, else 4
   int order_kind;           // 1: order is the identity, 2: the reverse (n-1, ..., 0), 0: other
+  int phase_mode;           // 0: phase head on the shared trunk; 1: separate phase network
+  int net_kind;             // what this geometry evaluates: 0 the shared-trunk network (log|psi|
+                            // and phi), 1 the modulus network of phase_mode 1 (log|psi| only),
+                            // 2 the phase network of phase_mode 1 (phi only; dense layers, units
+                            // in their own order, inputs = the first n-2 positions)
   uint64_t spin_pos[2];     // positions whose qubit has spin 0 (even) / 1 (odd)
   int8_t order[64];         // position -> qubit
   int8_t pos[64];           // qubit -> position
@@ -41,9 +46,15 @@ struct Geom {
   long long nfrag;          // fragments per plane
   long long bias_byte;      // byte offset of the biases inside the packed buffer
   long long head_bias_off;  // element offset of the head bias inside the bias array
-  long long poff[2 * kMaxLayers + 4];  // offsets of W_1, b_1, ..., W_o, b_o, W_p, b_p
+  long long poff[4 * kMaxLayers + 4];  // offsets of W_1, b_1, ..., W_L, b_L, W_o, b_o, then
+                                       // (phase_mode 1) V_1, e_1, ..., V_L, e_L, then W_p, b_p
   long long n_params;
 };
+
+// Index into poff of the phase network's layer-l weight (l = 1..L; its bias
+// follows) and of the phase head's weight (its bias follows).
+__host__ __device__ inline int poff_phase_layer(const Geom& g, int l) { return 2 * g.L + 2 + 2 * (l - 1); }
+__host__ __device__ inline int poff_phase_head(const Geom& g) { return g.phase_mode ? 4 * g.L + 2 : 2 * g.L + 2; }
 
 // Unit-class helpers on the sorted hidden units.
 __host__ __device__ inline int prefix_of_class(const Geom& g, int c) {

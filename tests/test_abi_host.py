@@ -86,12 +86,21 @@ def test_error_statuses(lib):
         _ham(3, [1], [0], [float("nan")])
 
 
-@pytest.mark.parametrize("n,L,h,prec", [(12, 1, 64, "fp64"), (24, 2, 256, "fp32"),
-                                        (60, 4, 1024, "bf16"), (64, 3, 512, "bf16x3")])
-def test_param_layout(lib, n, L, h, prec):
+@pytest.mark.parametrize("n,L,h,prec,mode", [(12, 1, 64, "fp64", 0), (24, 2, 256, "fp32", 0),
+                                             (60, 4, 1024, "bf16", 0), (64, 3, 512, "bf16x3", 0),
+                                             (12, 1, 64, "fp64", 1), (60, 4, 1024, "bf16w", 1)])
+def test_param_layout(lib, n, L, h, prec, mode):
     from paper_2208_05637_amd import param_count
-    want = made.n_params(made.Net(n=n, n_layers=L, width=h))
-    assert param_count(n, L, h, prec) == want == gen_param_count(n, L, h)
+    want = made.n_params(made.Net(n=n, n_layers=L, width=h, phase_mode=mode))
+    assert param_count(n, L, h, prec, phase_mode=mode) == want == gen_param_count(n, L, h, mode)
+
+
+def test_phase_mode_rejected_values(lib):
+    from paper_2208_05637_amd import param_count, NQSError
+    with pytest.raises(NQSError):
+        param_count(12, 1, 64, "fp64", phase_mode=2)
+    with pytest.raises(NQSError):
+        param_count(2, 1, 64, "fp64", phase_mode=1)     # no first n-2 entries
 
 
 def test_unsupported_width_rejected(lib):
