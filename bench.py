@@ -19,7 +19,9 @@ throughput B*K/t.  The whole step is also replayed from a HIP graph.
 Beside it, on the first --prefix samples of the same batch and the same
 network: the timed path again, the split-BF16, plain BF16 and FP32 GPU paths
 (throughput + energy) and the FP64 GPU path (the energy reference of the
-prefix); one Adam step (Sec. 6) on the network's parameters; and the FP64 CPU
+prefix); the timed path with the paper's separate phase sub-model and with
+the forward and a random sampling order; one Adam step (Sec. 6) on the
+network's parameters; and the FP64 CPU
 oracle on --cpu-samples samples (CPU baseline, and the per-sample check of
 every GPU path).
 """
@@ -280,6 +282,11 @@ def main():
             "forward_rows_per_block": kinfo["rows_per_block"],
             "autotuned": kinfo["tuned"],
             "energy": energy[0].item(),
+            # every configuration of the spin sector has the same number of connected configurations
+            # besides itself (the plan's per-sample entry bound is exact for these Hamiltonians)
+            "connected_configs_per_s": B * plan.entries_per_sample / (eloc_ms / 1e3),
+            "dedup_ratio": (B * plan.entries_per_sample / max(prof["forward_rows"] - B * args.steps, 1) * args.steps
+                            if plan.dedup else 1.0),
         },
         "roofline": {
             "kernel": f"fused_forward<{prec},{cfg['h']}>",
@@ -347,6 +354,37 @@ def main():
         if ref is not None:
             out["abs_dE_prefix_vs_fp64"] = abs(Ep[prec] - ref)
         log("prefix energies: " + ", ".join(f"{p}={Ep[p]:.10f}" for p in Ep))
+
+        # network variants on the same prefix, timed precision and workgroup shape: the paper's
+        # separate phase sub-model, and the forward and a random sampling order
+        from gen import init_params
+        var = {}
+        vspecs = [("separate_phase_network", dict(phase_mode=1)),
+                  ("forward_order", dict(order=np.arange(cfg["n"]))),
+                  ("random_order", dict(order=np.random.default_rng(5).permutation(cfg["n"])))]
+        for name, kw in vspecs:
+            vp = params
+            if "phase_mode" in kw:
+                vp = torch.from_numpy(init_params(cfg["n"], cfg["L"], cfg["h"], seed=1, dtype=cfg["params"],
+                                                  phase_mode=1)).to(dev)
+            pl = nqs.Plan(ctx, H, cfg["L"], cfg["h"], cfg["n_up"], cfg["n_dn"], prec, max_batch=P,
+                          dedup=plan.dedup, chunk_samples=min(plan.chunk_samples, P), **kw)
+            pl.configure(waves_per_block=kinfo["waves_per_block"])
+            nqs.local_energy(pl, vp, xp)      # warm
+            torch.cuda.synchronize()
+            pl.profile(True)
+            el = nqs.local_energy(pl, vp, xp)
+            pr = pl.profile_read()
+            pl.profile(False)
+            ev = math.fsum(wp * el[:, 0].cpu().numpy()) / math.fsum(wp)
+            var[name] = {"samples_terms_per_s": P * K / (pr["eloc_ms"] / 1e3),
+                         "forward_tflops": pr["forward_flops"] / (pr["forward_ms"] / 1e3) / 1e12,
+                         "alg_flop_per_row": pr["forward_flops"] / max(pr["forward_rows"], 1),
+                         "energy_prefix": ev}
+            log(f"variant {name}: {var[name]['samples_terms_per_s']:.3e} samples*terms/s, "
+                f"{var[name]['forward_tflops']:.1f} TFLOP/s, E = {ev:.8f}")
+            del pl
+        out["variants_on_prefix"] = {"prefix_samples": P, "precision": prec, **var}
 
     if not args.no_cpu:
         from threadpoolctl import threadpool_info
