@@ -234,6 +234,17 @@ def main():
                  "equal_to_eager": same}
         log(f"graph-captured step: {graph['ms_per_step']:.1f} ms, equal to eager: {same}")
         del g
+    # duplicates among the connected configurations: entries / distinct configurations of the
+    # first chunk (what dedup would save; the autotuner decides whether the timed path uses it)
+    dedup_ratio = None
+    if not args.no_side and cfg["n"] < 64:
+        dp = nqs.Plan(ctx, H, cfg["L"], cfg["h"], cfg["n_up"], cfg["n_dn"], prec, max_batch=plan.chunk_samples,
+                      dedup=True, chunk_samples=plan.chunk_samples)
+        con = nqs.connected(dp, x[:plan.chunk_samples])
+        ne, nu = int(con["n_entries"].item()), int(con["n_unique"].item())
+        dedup_ratio = ne / max(nu, 1)
+        log(f"first chunk: {ne} connected configurations, {nu} distinct (ratio {dedup_ratio:.4f})")
+        del con, dp
     adam = None
     if not args.no_side:
         # one Adam step (Sec. 6) on this network's parameters with the step's gradient, timed on its own
@@ -285,8 +296,7 @@ def main():
             # every configuration of the spin sector has the same number of connected configurations
             # besides itself (the plan's per-sample entry bound is exact for these Hamiltonians)
             "connected_configs_per_s": B * plan.entries_per_sample / (eloc_ms / 1e3),
-            "dedup_ratio": (B * plan.entries_per_sample / max(prof["forward_rows"] - B * args.steps, 1) * args.steps
-                            if plan.dedup else 1.0),
+            "dedup_ratio": dedup_ratio,
         },
         "roofline": {
             "kernel": f"fused_forward<{prec},{cfg['h']}>",
