@@ -96,13 +96,13 @@ constexpr int head_ksplit_max() {
   return want < fit ? want : fit;
 }
 
-__device__ __forceinline__ unsigned short bf16_rne(float f) {
-  unsigned u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ float bf16_to_f(unsigned short h) {
-  return __uint_as_float(((unsigned)h) << 16);
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+typedef __attribute__((ext_vector_type(2))) float f32x2;
+
+// Two FP32 values to BF16, rounded to nearest even (one v_cvt_pk_bf16_f32 on
+// gfx950), packed with a in the low half.
+__device__ __forceinline__ unsigned bf16x2_rne(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){a, b}, bf16x2));
 }
 
 // AX: the activation operand is exact in BF16 (its low plane is zero), so the
@@ -218,14 +218,15 @@ __device__ __forceinline__ void store_act(char* act, const typename Tr<P>::Acc& 
       } else {
         const int ks = 2 * nb + (q >> 1);
         const int lp = m + 32 * (q & 1);
-        unsigned short h0 = bf16_rne(v0), h1 = bf16_rne(v1), h2 = bf16_rne(v2), h3 = bf16_rne(v3);
+        const unsigned h01 = bf16x2_rne(v0, v1), h23 = bf16x2_rne(v2, v3);
         char* dst = act + ((long)(ks * MB + mb) * 64 + lp) * 16 + 8 * hf;
-        *(uint2*)dst = make_uint2(h0 | ((unsigned)h1 << 16), h2 | ((unsigned)h3 << 16));
+        *(uint2*)dst = make_uint2(h01, h23);
         if constexpr (T::PL == 2) {
-          unsigned short l0 = bf16_rne(v0 - bf16_to_f(h0)), l1 = bf16_rne(v1 - bf16_to_f(h1));
-          unsigned short l2 = bf16_rne(v2 - bf16_to_f(h2)), l3 = bf16_rne(v3 - bf16_to_f(h3));
+          // low term: the exact residual v - hi (Sterbenz), rounded to BF16
+          const float r0 = v0 - __uint_as_float(h01 << 16), r1 = v1 - __uint_as_float(h01 & 0xFFFF0000u);
+          const float r2 = v2 - __uint_as_float(h23 << 16), r3 = v3 - __uint_as_float(h23 & 0xFFFF0000u);
           char* dlo = dst + (long)KSH * MB * 64 * 16;
-          *(uint2*)dlo = make_uint2(l0 | ((unsigned)l1 << 16), l2 | ((unsigned)l3 << 16));
+          *(uint2*)dlo = make_uint2(bf16x2_rne(r0, r1), bf16x2_rne(r2, r3));
         }
       }
     }
