@@ -56,9 +56,9 @@ def kernel_source_hash():
 
 
 def measured_traffic(workload, prec, waves):
-    """HBM bytes per connected-configuration forward launch from the committed
-    counter summary of this workload, or None when there is none or it was
-    taken on another kernel source or workgroup shape."""
+    """HBM bytes per configuration of the connected-configuration forward from
+    the committed counter summary of this workload, or None when there is none
+    or it was taken on another kernel source or workgroup shape."""
     path = os.path.join(ROOT, "profiles", f"fused_forward_{workload}_{prec}_traffic.md")
     if not os.path.exists(path):
         return None
@@ -71,7 +71,7 @@ def measured_traffic(workload, prec, waves):
     try:
         if kv.get("kernel_source_sha256") != kernel_source_hash() or int(kv.get("waves_per_block", -1)) != waves:
             return None
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv["traffic_bytes_per_row"])
     except (KeyError, ValueError):
         return None
 
@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--no-side", action="store_true", help="skip the prefix paths")
     ap.add_argument("--chunk", type=int, default=0, help="samples per chunk (0 = plan default)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (plan defaults)")
+    ap.add_argument("--dedup", default=None, choices=["on", "off", "auto"],
+                    help="override the workload's dedup setting")
     ap.add_argument("--waves", type=int, default=0, help="force the forward's waves per workgroup")
     ap.add_argument("--samples", default="psi", choices=["psi", "sector"],
                     help="psi: the batch is drawn from the network with the GPU unique-sample sampler "
@@ -136,6 +138,8 @@ def main():
     K = H.K
     dev = ctx.device
     params = torch.from_numpy(params_np).to(dev)
+    if args.dedup is not None:
+        cfg["dedup"] = {"on": True, "off": False, "auto": "auto"}[args.dedup]
     mk = lambda p, mb: nqs.Plan(ctx, H, cfg["L"], cfg["h"], cfg["n_up"], cfg["n_dn"], p, max_batch=mb,
                                 dedup=cfg["dedup"], chunk_samples=args.chunk)
     sampling = None
@@ -266,6 +270,7 @@ def main():
         log(f"adam step: {ams * 1e3:.1f} us for {pa.numel()} parameters, {adam['GB/s']:.0f} GB/s")
         del opt, pa
     kinfo = plan.kernel_info()
+    bpr = measured_traffic(args.workload, prec, kinfo["waves_per_block"])
     out = {
         "metric": METRIC,
         "value": value,
@@ -305,7 +310,11 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": measured_traffic(args.workload, prec, kinfo["waves_per_block"]),
+            # HBM bytes per launch: the counters' bytes per configuration times this run's
+            # configurations per launch
+            "traffic": (None if bpr is None else bpr * prof["forward_rows"] / max(prof["forward_launches"], 1)),
+            "traffic_bytes_per_row": bpr,
+            "alg_bytes_per_row": 24,
             "mfma_issued_tflops": issued,
             "mfma_issued_frac": issued / peak,
             "ms_per_launch": fwd_ms_launch,

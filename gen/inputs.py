@@ -95,7 +95,7 @@ CONFIGS = {
                weights="counts", params="fp32"),
     "c3": dict(N=20, seed=0, B=32768, L=3, h=512, precision="bf16w", dedup=True,
                weights="counts", params="bf16"),
-    "c4": dict(N=30, seed=0, B=65536, L=4, h=1024, precision="bf16w", dedup=False,
+    "c4": dict(N=30, seed=0, B=65536, L=4, h=1024, precision="bf16w", dedup="auto",
                weights="counts", params="bf16"),
     "c5a": dict(N=8, seed=1, B=4096, L=3, h=512, precision="bf16w", dedup=True,
                 weights="counts", params="bf16"),

@@ -752,7 +752,7 @@ __global__ __launch_bounds__(64 * NW) void fused_forward(Geom g0, FwdLaunch la) 
   constexpr int M = Sh::M;
   extern __shared__ uint4 smem[];
   char* act = (char*)smem;
-  const long long t = blockIdx.x;
+  const long long t = la.tile_base + blockIdx.x;
   if constexpr (!MULTI) {
     const FwdSeg& sg = la.seg[0];
     const long long rows = seg_rows(sg);
@@ -770,7 +770,7 @@ __global__ __launch_bounds__(64 * NW) void fused_forward(Geom g0, FwdLaunch la) 
     if (row0 < rows)
       fwd_tile<P, H, NW>(*sg.geom, (const uint4*)sg.packed, sg.x, row0, rows, (double2*)sg.out, act, la.cond_pos);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (t == 0 && threadIdx.x == 0) {
     for (int k = 0; k < la.nseg; ++k)
       if (la.seg[k].prof_slot) *la.seg[k].prof_slot = seg_rows(la.seg[k]);
   }
@@ -804,7 +804,13 @@ static void launch_one(const Geom& g, FwdLaunch& la, hipStream_t s) {
   }
   la.ntiles = tiles;
   if (tiles <= 0) return;
-  hipLaunchKernelGGL(kern, dim3((unsigned)tiles), dim3(64 * NW), LDS, s, g, la);
+  // a dispatch counts its work-items in 32 bits: larger launches are split
+  const long long max_tiles = 0xFFFFFFFFLL / (64 * NW);
+  for (long long t0 = 0; t0 < tiles; t0 += max_tiles) {
+    la.tile_base = t0;
+    const long long nb = std::min(max_tiles, tiles - t0);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(64 * NW), LDS, s, g, la);
+  }
 }
 
 int forward_rows_per_block(int prec, int h) {

@@ -536,14 +536,16 @@ nqs_status nqs_plan_create(nqs_ctx* ctx, const nqs_ham* ham, const nqs_net_desc*
   } else {
     p->Emax = G - gfirst;
   }
-  const int64_t target = 16 * 1024 * 1024;
+  // entries per chunk: large chunks amortise the per-chunk launches and, with
+  // samples in sampling order, let dedup find more shared configurations
+  const int64_t target = 128LL * 1024 * 1024;
   if (chunk_samples > 0) p->S = std::min<int64_t>(chunk_samples, max_batch);
   else p->S = std::max<int64_t>(1, std::min<int64_t>(max_batch, target / std::max<int64_t>(p->Emax, 1)));
   p->S0 = p->S;
   p->EC = std::max<int64_t>(p->S * p->Emax, 1);
-  if (p->EC >= (1LL << 31)) {
+  if (p->EC > (1LL << 28)) {   // per-entry kernels launch one lane per entry
     delete p;
-    return fail(NQS_ERR_UNSUPPORTED, "chunk of %lld entries exceeds 2^31", (long long)p->S * p->Emax);
+    return fail(NQS_ERR_UNSUPPORTED, "chunk of %lld entries exceeds 2^28", (long long)p->S * p->Emax);
   }
   const int ngroups = G - gfirst;
   grid_for(p->S, ngroups, p->R, p->gper);

@@ -109,6 +109,7 @@ struct FwdLaunch {
   int nseg;
   int cond_pos;   // -1: (log|psi|, phi); >= 0: (logit at that sampling position, forcing code)
   long long ntiles;
+  long long tile_base;   // tile of workgroup 0 (a launch too large for one dispatch is split)
   FwdSeg seg[kMaxSeg];
 };
 

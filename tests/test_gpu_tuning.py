@@ -189,3 +189,27 @@ def test_forward_launch_grouping_invariance(nqs, ctx, N, B, order_seed):
         parts = torch.cat([nqs.log_psi(plan, p, ent[i:i + step]) for i in range(0, ne, step)])
         torch.cuda.synchronize()
         assert torch.equal(whole, parts), (prec, N)
+
+
+def test_forward_launch_split_beyond_32_bit_work_items(nqs, ctx):
+    """2^27 + 3 * 4096 rows need more than 2^32 work-items at 32 rows per 1,024-lane
+    workgroup, so the forward is split into two dispatches; the rows cycle through all
+    4,096 12-qubit configurations, so every row must equal its copy in the first cycle
+    (bit for bit), and the first cycle the oracle."""
+    n, L, h = 12, 1, 1024
+    terms = hamiltonian(6, 0)
+    H = nqs.Hamiltonian.from_terms(terms).upload(ctx)
+    plan = nqs.Plan(ctx, H, L, h, -1, -1, "bf16w", max_batch=16)
+    assert plan.kernel_info()["rows_per_block"] == 32 and plan.kernel_info()["waves_per_block"] == 16
+    params = init_params(n, L, h, seed=3, dtype="bf16")
+    rows = (1 << 27) + 3 * 4096
+    assert (rows // 32) * 1024 > 2**32
+    xs = torch.arange(rows, device="cuda", dtype=torch.int64) % 4096
+    out = nqs.log_psi(plan, torch.from_numpy(params).cuda(), xs)
+    torch.cuda.synchronize()
+    first = out[:4096]
+    assert torch.equal(out.view(-1, 4096, 2), first.unsqueeze(0).expand(rows // 4096, 4096, 2))
+    la_ref, ph_ref, _ = made.forward(made.Net(n=n, n_layers=L, width=h), params, np.arange(4096, dtype=np.uint64))
+    f = first.cpu().numpy()
+    assert np.max(np.abs(f[:, 0] - la_ref)) <= 5e-4 and np.max(np.abs(f[:, 1] - ph_ref)) <= 5e-4
+    del out, xs
