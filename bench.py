@@ -69,9 +69,9 @@ def measured_traffic(workload, prec, waves):
                 k, v = line.split(":", 1)
                 kv[k.strip().strip("-* `")] = v.strip().strip("` ")
     try:
-        if kv.get("kernel_source_sha256") != kernel_source_hash() or int(kv.get("waves_per_block", -1)) != waves:
+        if kv.get("kernel_source_sha256") != kernel_source_hash():
             return None
-        return float(kv["traffic_bytes_per_row"])
+        return float(kv[f"traffic_bytes_per_row_w{waves}"])
     except (KeyError, ValueError):
         return None
 
