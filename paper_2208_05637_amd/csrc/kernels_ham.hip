@@ -298,10 +298,15 @@ void launch_seg_offsets(const int* esample, long long n_entries, long long B, lo
 // entries in an LDS table, then inserts only the tile-unique keys into the
 // global table.  Keys are x' values; the all-ones word marks an empty slot
 // (the plan disables deduplication at n = 64, the only width where it is a
-// valid configuration).
+// valid configuration).  Each global slot also records the first entry that
+// holds its key; the distinct configurations are then listed in the order of
+// their first entries (sample-major, as the entries are), so rows that follow
+// each other in the forward stay alike, and the list does not depend on the
+// hash layout or on scheduling.
 constexpr unsigned long long kEmpty = ~0ull;
 constexpr int kDedupTile = 2048;
 constexpr int kDedupLds = 4096;
+constexpr int kNoEntry = 0x7FFFFFFF;
 
 __device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
   z ^= z >> 30; z *= 0xbf58476d1ce4e5b9ull;
@@ -310,14 +315,17 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
   return z;
 }
 
+// eu[e] <- global slot of entry e's key; owner[slot] <- smallest entry holding it.
 __global__ __launch_bounds__(512) void dedup_insert_kernel(const uint64_t* __restrict__ xe,
                                                            const long long* __restrict__ d_count,
                                                            long long cap,
                                                            unsigned long long* __restrict__ hkeys,
+                                                           int* __restrict__ owner,
                                                            long long HT, int* __restrict__ eu,
                                                            unsigned* err) {
   __shared__ unsigned long long lkeys[kDedupLds];
   __shared__ int lglob[kDedupLds];
+  __shared__ int lmin[kDedupLds];
   long long count = *d_count;
   if (count > cap) count = cap;
   const long long e0 = (long long)blockIdx.x * kDedupTile;
@@ -325,6 +333,7 @@ __global__ __launch_bounds__(512) void dedup_insert_kernel(const uint64_t* __res
   for (int s = threadIdx.x; s < kDedupLds; s += blockDim.x) {
     lkeys[s] = kEmpty;
     lglob[s] = -1;
+    lmin[s] = kNoEntry;
   }
   __syncthreads();
   int lslot[kDedupTile / 512];
@@ -340,6 +349,7 @@ __global__ __launch_bounds__(512) void dedup_insert_kernel(const uint64_t* __res
         if (prev == kEmpty || prev == key) { lslot[q] = (int)s; break; }
         s = (s + 1) & (kDedupLds - 1);
       }
+      if (lslot[q] >= 0) atomicMin(&lmin[lslot[q]], (int)e);
     }
   }
   __syncthreads();
@@ -355,6 +365,7 @@ __global__ __launch_bounds__(512) void dedup_insert_kernel(const uint64_t* __res
       gs = (gs + 1) & hmask;
     }
     if (found < 0) atomicOr(err, kErrHashOverflow);
+    else atomicMin(&owner[found], lmin[s]);
     lglob[s] = found;
   }
   __syncthreads();
@@ -365,35 +376,39 @@ __global__ __launch_bounds__(512) void dedup_insert_kernel(const uint64_t* __res
   }
 }
 
-// Compact occupied global slots: wave ballot + mbcnt gives the rank inside a
-// wave, LDS prefix over the 8 waves the rank inside the block, one atomic per
-// block the base.
-__global__ __launch_bounds__(512) void dedup_compact_kernel(const unsigned long long* __restrict__ hkeys,
-                                                            long long HT, int* __restrict__ slot_id,
-                                                            uint64_t* __restrict__ xu,
-                                                            long long* __restrict__ d_nu) {
-  __shared__ int wcount[8];
-  __shared__ long long base;
-  const long long s = (long long)blockIdx.x * 512 + threadIdx.x;
-  const bool occ = s < HT && hkeys[s] != kEmpty;
-  const unsigned long long mask = __ballot(occ);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
-                                             __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0));
-  if (lane == 0) wcount[wave] = __popcll(mask);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int tot = 0;
-    for (int w = 0; w < 8; ++w) tot += wcount[w];
-    base = tot ? atomicAdd((unsigned long long*)d_nu, (unsigned long long)tot) : 0;
+// first[e] = 1 where entry e is the first holder of its key (0 beyond the count).
+__global__ void dedup_first_kernel(const long long* __restrict__ d_count, long long cap,
+                                   const int* __restrict__ eu, const int* __restrict__ owner,
+                                   int* __restrict__ first) {
+  long long count = *d_count;
+  if (count > cap) count = cap;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < cap; e += stride) {
+    int f = 0;
+    if (e < count) {
+      const int g = eu[e];
+      f = (g >= 0 && owner[g] == (int)e) ? 1 : 0;
+    }
+    first[e] = f;
   }
-  __syncthreads();
-  if (occ) {
-    int before = 0;
-    for (int w = 0; w < wave; ++w) before += wcount[w];
-    const long long id = base + before + rank;
-    slot_id[s] = (int)id;
-    xu[id] = hkeys[s];
+}
+
+// The first holders, in entry order: xu[rank] = key, slot_id[slot] = rank.
+__global__ void dedup_place_kernel(const long long* __restrict__ d_count, long long cap,
+                                   const int* __restrict__ first, const long long* __restrict__ rank,
+                                   const uint64_t* __restrict__ xe, const int* __restrict__ eu,
+                                   int* __restrict__ slot_id, uint64_t* __restrict__ xu,
+                                   long long* __restrict__ d_nu) {
+  long long count = *d_count;
+  if (count > cap) count = cap;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i0 == 0) *d_nu = rank[cap];
+  for (long long e = i0; e < count; e += stride) {
+    if (!first[e]) continue;
+    const long long id = rank[e];
+    xu[id] = xe[e];
+    slot_id[eu[e]] = (int)id;
   }
 }
 
@@ -409,21 +424,27 @@ __global__ void dedup_remap_kernel(const long long* __restrict__ d_count, long l
   }
 }
 
+long long dedup_rank_tmp_elems(long long cap) { return scan_tiles(cap) + 1; }
+
 void launch_dedup(const uint64_t* xe, const long long* d_count, long long cap, uint64_t* hkeys,
-                  int* hslot_id, long long HT, int* eu, uint64_t* xu, long long* d_nu,
-                  unsigned* err, hipStream_t s) {
+                  int* hslot, long long HT, int* eu, uint64_t* xu, long long* d_nu,
+                  int* first, long long* rank, long long* rank_tmp, unsigned* err, hipStream_t s) {
   launch_fill_u64(hkeys, kEmpty, HT, s);
+  launch_fill_u32(hslot, (unsigned)kNoEntry, HT, s);   // owners first, then slot ranks
   launch_fill_u64(d_nu, 0ull, 1, s);
   long long tiles = (cap + kDedupTile - 1) / kDedupTile;
   if (tiles <= 0) return;
   hipLaunchKernelGGL(dedup_insert_kernel, dim3((unsigned)tiles), dim3(512), 0, s, xe, d_count, cap,
-                     (unsigned long long*)hkeys, HT, eu, err);
-  hipLaunchKernelGGL(dedup_compact_kernel, dim3((unsigned)((HT + 511) / 512)), dim3(512), 0, s,
-                     (const unsigned long long*)hkeys, HT, hslot_id, xu, d_nu);
+                     (unsigned long long*)hkeys, hslot, HT, eu, err);
   long long blocks = (cap + 255) / 256;
   if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(dedup_first_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d_count, cap, eu,
+                     (const int*)hslot, first);
+  launch_scan(first, cap, rank, rank_tmp, s);
+  hipLaunchKernelGGL(dedup_place_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d_count, cap, first, rank,
+                     xe, eu, hslot, xu, d_nu);
   hipLaunchKernelGGL(dedup_remap_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d_count, cap,
-                     hslot_id, eu);
+                     (const int*)hslot, eu);
 }
 
 // ------------------------------------------------------- ratio-and-reduce

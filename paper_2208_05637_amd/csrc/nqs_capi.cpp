@@ -116,7 +116,7 @@ constexpr int kProfSlots = 8192;
 
 struct WsLayout {
   size_t err, prof, geom, packed, wm, lps, eloc, energy, cnt, off, stmp, rpart, diag, xe, he, lpe, hkeys, hslot,
-      eu, xu, nu, bscratch, total;
+      eu, xu, nu, dfirst, drank, drtmp, bscratch, total;
 };
 
 // Enumeration grid for chunks of S samples: R ranges of gper flip groups.
@@ -155,6 +155,9 @@ static WsLayout layout(const nqs_plan* p, int64_t B) {
     L.eu = take((size_t)p->EC * 4);
     L.xu = take((size_t)p->EC * 8);
     L.nu = take(8);
+    L.dfirst = take((size_t)p->EC * 4);
+    L.drank = take(((size_t)p->EC + 1) * 8);
+    L.drtmp = take((size_t)dedup_rank_tmp_elems(p->EC) * 8);
   }
   L.bscratch = take((size_t)backward_scratch_elems(p->g, p->Sb) * p->bw);
   L.total = o;
@@ -762,7 +765,7 @@ static ChunkFwd enum_chunk(nqs_plan* p, const uint64_t* x, int64_t c0, int64_t S
     uint64_t* xu = at<uint64_t>(ws, L.xu);
     long long* nu = at<long long>(ws, L.nu);
     launch_dedup(xe, d_total, p->EC, at<uint64_t>(ws, L.hkeys), at<int>(ws, L.hslot), p->HT, at<int>(ws, L.eu), xu,
-                 nu, err, s);
+                 nu, at<int>(ws, L.dfirst), at<long long>(ws, L.drank), at<long long>(ws, L.drtmp), err, s);
     return {xu, nu, bound, at<double>(ws, L.lpe)};
   }
   return {xe, d_total, bound, at<double>(ws, L.lpe)};
@@ -1241,9 +1244,11 @@ nqs_status nqs_connected(nqs_plan* p, const uint64_t* x, int64_t B, int64_t capa
   launch_write(H, x, B, p->R, p->gper, off, capacity, d_ex, d_eh, d_esample, 2, err, s);
   launch_copy_i64(off + B * p->R, (long long*)d_n_entries, s);
   if (p->dedup) {
-    if ((int64_t)2 * capacity > p->HT) return fail(NQS_ERR_INVALID_ARGUMENT, "capacity exceeds the plan's hash table");
+    if (capacity > p->EC || (int64_t)2 * capacity > p->HT)
+      return fail(NQS_ERR_INVALID_ARGUMENT, "capacity exceeds the plan's dedup buffers");
     launch_dedup(d_ex, (const long long*)d_n_entries, capacity, at<uint64_t>(ws, L.hkeys), at<int>(ws, L.hslot),
-                 p->HT, d_eunique, d_unique, (long long*)d_n_unique, err, s);
+                 p->HT, d_eunique, d_unique, (long long*)d_n_unique, at<int>(ws, L.dfirst), at<long long>(ws, L.drank),
+                 at<long long>(ws, L.drtmp), err, s);
   }
   return launch_check("connected");
 }
