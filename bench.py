@@ -115,9 +115,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build evaluates one GPU's share of the batch on a single MI355X; "
-              "runs on several GPUs are not part of it (DESIGN.md, section 7, says how the path "
-              "would shard).", file=sys.stderr)
+        print("bench.py: the benchmark evaluates one GPU's share of the batch on a single MI355X; "
+              "runs on several GPUs are not supported (the path would shard by samples, with one "
+              "all-reduce of the gradient sums per step).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

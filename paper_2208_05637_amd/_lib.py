@@ -112,8 +112,8 @@ def load():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"HIP library {LIB_PATH} is missing; run __graft_entry__.build() "
-                          "or python -m paper_2208_05637_amd.build")
+        raise ImportError(f"HIP library {LIB_PATH} is missing; build it with "
+                          "python -m paper_2208_05637_amd.build")
     lib = C.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def lib():
     from paper_2208_05637_amd import _lib
     if not os.path.exists(_lib.LIB_PATH):
-        pytest.fail("libnqs.so not built: run __graft_entry__.build()")
+        pytest.fail("libnqs.so not built: run python -m paper_2208_05637_amd.build")
     return _lib.load()
 
 
