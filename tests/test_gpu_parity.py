@@ -159,6 +159,9 @@ def test_connected_bit_exact(nqs, ctx, N, B, filt):
     assert np.array_equal(uniq, np.unique(ex))
     eu = out["entry_unique"][:ne].cpu().numpy()
     assert np.array_equal(out["unique"][:nu].cpu().numpy().view(np.uint64)[eu], ex)
+    # the distinct configurations are listed in the order of their first entries
+    _, first = np.unique(ex, return_index=True)
+    assert np.array_equal(out["unique"][:nu].cpu().numpy().view(np.uint64), ex[np.sort(first)])
 
 
 def test_entry_bound_equals_closed_form(nqs, ctx):
