@@ -541,7 +541,7 @@ nqs_status nqs_plan_create(nqs_ctx* ctx, const nqs_ham* ham, const nqs_net_desc*
   }
   // entries per chunk: large chunks amortise the per-chunk launches and, with
   // samples in sampling order, let dedup find more shared configurations
-  const int64_t target = 128LL * 1024 * 1024;
+  const int64_t target = 256LL * 1024 * 1024;
   if (chunk_samples > 0) p->S = std::min<int64_t>(chunk_samples, max_batch);
   else p->S = std::max<int64_t>(1, std::min<int64_t>(max_batch, target / std::max<int64_t>(p->Emax, 1)));
   p->S0 = p->S;

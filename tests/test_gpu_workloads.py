@@ -123,7 +123,7 @@ def test_60_qubits_full_batch_sampled(nqs, ctx):
     plan = mk(cfg["B"])
     N = cfg["N"]
     assert plan.entries_per_sample == _closed_conn(N, N // 2, N // 2) - 1
-    assert plan.kernel_info()["waves_per_block"] == 16 and plan.chunk_samples == (128 << 20) // 73125
+    assert plan.kernel_info()["waves_per_block"] == 16 and plan.chunk_samples == (256 << 20) // 73125
     energy, grad, eloc = nqs.energy_grad(plan, p, x, w)
     torch.cuda.synchronize()
     assert nqs.device_status(plan) == 0
