@@ -25,6 +25,7 @@
 // serves half as many rows: the BF16-weight kind streams one weight plane,
 // split BF16 two.
 #include <algorithm>
+#include <atomic>
 
 #include "nqs_internal.h"
 
@@ -792,10 +793,14 @@ static void launch_one(const Geom& g, FwdLaunch& la, hipStream_t s) {
   using Sh = Shape<P, H, NW>;
   constexpr size_t LDS = Sh::LDS;
   auto kern = fused_forward<P, H, NW, MULTI>;
-  static bool attr_done = false;
-  if (!attr_done) {
+  // the LDS opt-in, once per device (one bit per device ordinal), safe across threads
+  static std::atomic<unsigned long long> attr_done{0};
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const unsigned long long bit = 1ull << (dev & 63);
+  if (!(attr_done.load(std::memory_order_acquire) & bit)) {
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS);
-    attr_done = true;
+    attr_done.fetch_or(bit, std::memory_order_release);
   }
   long long tiles = 0;
   for (int k = 0; k < la.nseg; ++k) {
