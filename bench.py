@@ -317,6 +317,9 @@ def main():
             "alg_bytes_per_row": 24,
             "mfma_issued_tflops": issued,
             "mfma_issued_frac": issued / peak,
+            # a multiply-add of two-term BF16 activations takes two BF16 MFMA products
+            "products_per_mac": {"bf16w": 2, "bf16x3": 3}.get(prec, 1),
+            "frac_of_product_peak": achieved * {"bf16w": 2, "bf16x3": 3}.get(prec, 1) / peak,
             "ms_per_launch": fwd_ms_launch,
             "rows": prof["forward_rows"],
             "alg_flop_per_row": prof["forward_flops"] / max(prof["forward_rows"], 1),
