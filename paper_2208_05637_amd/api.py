@@ -212,6 +212,17 @@ class Plan:
             self.handle = None
 
 
+def _dev_tensor(t, name, dtypes, numel, device):
+    """Reject a tensor the kernels would read or write out of bounds."""
+    if not isinstance(dtypes, tuple):
+        dtypes = (dtypes,)
+    if (not isinstance(t, torch.Tensor) or t.dtype not in dtypes or t.device != torch.device(device)
+            or not t.is_contiguous() or t.numel() != numel):
+        raise ValueError(f"{name} must be a contiguous {'/'.join(map(str, dtypes))} tensor of {numel} "
+                         f"elements on {device}")
+    return t
+
+
 def _params(plan, params):
     if params.dtype != torch.float32 or not params.is_cuda or params.numel() != plan.n_params:
         raise ValueError(f"params must be a float32 CUDA tensor of {plan.n_params} entries")
@@ -246,10 +257,14 @@ def energy_grad(plan, params, samples, weights=None, eloc=None, energy=None, gra
     B = x.numel()
     w = None
     if weights is not None:
-        w = torch.as_tensor(weights, dtype=torch.float64).to(dev).contiguous()
+        w = _dev_tensor(torch.as_tensor(weights, dtype=torch.float64).to(dev).contiguous(), "weights",
+                        torch.float64, B, dev)
     eloc = torch.empty((B, 2), dtype=torch.float64, device=dev) if eloc is None else eloc
     energy = torch.empty(3, dtype=torch.float64, device=dev) if energy is None else energy
     grad = torch.empty(plan.n_params, dtype=torch.float64, device=dev) if grad is None else grad
+    _dev_tensor(eloc, "eloc", torch.float64, 2 * B, dev)
+    _dev_tensor(energy, "energy", torch.float64, 3, dev)
+    _dev_tensor(grad, "grad", torch.float64, plan.n_params, dev)
     ws, nb = plan.workspace()
     L.check(plan.lib.nqs_energy_grad(plan.handle, _ptr(params), _ptr(x), _ptr(w), B, _ptr(eloc),
                                      _ptr(energy), _ptr(grad), ws, nb), "nqs_energy_grad")
@@ -259,6 +274,16 @@ def energy_grad(plan, params, samples, weights=None, eloc=None, energy=None, gra
 def _instances(items):
     arr = (L.Instance * len(items))()
     for i, it in enumerate(items):
+        plan, dev = it["plan"], it["plan"].ctx.device
+        B = it["samples"].numel()
+        _dev_tensor(it["params"], "params", torch.float32, plan.n_params, dev)
+        _dev_tensor(it["samples"], "samples", (torch.int64, torch.uint64), B, dev)
+        if it.get("weights") is not None:
+            _dev_tensor(it["weights"], "weights", torch.float64, B, dev)
+        if it.get("eloc") is not None:
+            _dev_tensor(it["eloc"], "eloc", torch.float64, 2 * B, dev)
+        _dev_tensor(it["energy"], "energy", torch.float64, 3, dev)
+        _dev_tensor(it["grad"], "grad", torch.float64, plan.n_params, dev)
         arr[i] = L.Instance(it["plan"].handle.value, it["params"].data_ptr(), it["samples"].data_ptr(),
                             it["weights"].data_ptr() if it.get("weights") is not None else None,
                             it["samples"].numel(),

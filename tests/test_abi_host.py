@@ -113,3 +113,15 @@ def test_adam_rejects_arguments_on_the_host(lib):
     import ctypes as C
     z = C.c_void_p(0)
     assert lib.nqs_adam_step(z, 0, z, z, z, z, 1, 1e-3, 0.9, 0.99, 1e-8) == 1     # NULL context
+
+
+def test_binding_rejects_tensors_the_kernels_would_overrun():
+    import torch
+    from paper_2208_05637_amd.api import _dev_tensor
+    ok = torch.zeros(6, dtype=torch.float64)
+    assert _dev_tensor(ok, "eloc", torch.float64, 6, "cpu") is ok
+    for bad, why in ((torch.zeros(5, dtype=torch.float64), "short"),
+                     (torch.zeros(6, dtype=torch.float32), "dtype"),
+                     (torch.zeros(12, dtype=torch.float64)[::2], "strided")):
+        with pytest.raises(ValueError):
+            _dev_tensor(bad, why, torch.float64, 6, "cpu")
