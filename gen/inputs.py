@@ -23,14 +23,26 @@ from .jw import jordan_wigner_terms, PauliTerms
 
 
 @lru_cache(maxsize=8)
-def _hamiltonian_cached(n_orb, seed, drop_tol):
+def _hamiltonian_cached(n_orb, seed, drop_tol, cutoff):
     h1, h2 = molecular_integrals(n_orb, seed)
+    if cutoff > 0.0:
+        h2 = np.where(np.abs(h2) >= cutoff, h2, 0.0)
     return jordan_wigner_terms(h1, h2, drop_tol=drop_tol)
 
 
-def hamiltonian(n_orb: int, seed: int = 0, drop_tol: float = 1e-10) -> PauliTerms:
-    """Merged Pauli-string Hamiltonian on ``2*n_orb`` qubits (cached per process)."""
-    return _hamiltonian_cached(int(n_orb), int(seed), float(drop_tol))
+def hamiltonian(n_orb: int, seed: int = 0, drop_tol: float = 1e-10, cutoff: float = 0.0) -> PauliTerms:
+    """Merged Pauli-string Hamiltonian on ``2*n_orb`` qubits (cached per process).
+
+    ``cutoff`` > 0 zeroes the two-electron integrals of magnitude below it
+    before the expansion (a sparser synthetic molecule with fewer terms; the
+    8-fold symmetry is kept, since symmetric entries are equal).
+    """
+    return _hamiltonian_cached(int(n_orb), int(seed), float(drop_tol), float(cutoff))
+
+
+def words(n: int) -> int:
+    """64-bit words per bit string of n qubits."""
+    return (int(n) + 63) // 64
 
 
 def param_count(n: int, n_layers: int, width: int, phase_mode: int = 0) -> int:
@@ -64,25 +76,38 @@ def init_params(n: int, n_layers: int, width: int, seed: int = 1, std: float = 0
 
 
 def sector_samples(n: int, n_up: int, n_dn: int, count: int, seed: int = 2):
-    """``count`` i.i.d. uniform draws from the (n_up, n_dn) sector, as uint64."""
+    """``count`` i.i.d. uniform draws from the (n_up, n_dn) sector.
+
+    uint64 [count] for n <= 64, else uint64 [count, W] words (word w holds
+    qubits 64w .. 64w+63)."""
     N = n // 2
     if not (0 <= n_up <= N and 0 <= n_dn <= N):
         raise ValueError("sector outside the orbital range")
+    W = words(n)
     rng = np.random.Generator(np.random.PCG64(seed))
-    out = np.zeros(count, dtype=np.uint64)
+    out = np.zeros((count, W), dtype=np.uint64)
     for spin, ne in ((0, n_up), (1, n_dn)):
         if ne == 0:
             continue
         keys = rng.random((count, N))
         chosen = np.argsort(keys, axis=1)[:, :ne]          # uniform ne-subset
-        qubits = (2 * chosen + spin).astype(np.uint64)
-        out |= np.bitwise_or.reduce(np.left_shift(np.uint64(1), qubits), axis=1)
-    return out
+        qubits = 2 * chosen + spin
+        for w in range(W):
+            inw = (qubits >= 64 * w) & (qubits < 64 * (w + 1))
+            bits = np.where(inw, np.left_shift(np.uint64(1), (qubits - 64 * w).clip(0, 63).astype(np.uint64)),
+                            np.uint64(0))
+            out[:, w] |= np.bitwise_or.reduce(bits, axis=1)
+    return out[:, 0].copy() if W == 1 else out
 
 
 def unique_with_counts(samples):
-    u, c = np.unique(np.asarray(samples, dtype=np.uint64), return_counts=True)
-    return u, c.astype(np.float64)
+    """Distinct samples in ascending order (as unsigned integers) and their counts."""
+    a = np.asarray(samples, dtype=np.uint64)
+    if a.ndim == 1:
+        u, c = np.unique(a, return_counts=True)
+        return u, c.astype(np.float64)
+    u, c = np.unique(a[:, ::-1], axis=0, return_counts=True)   # most significant word first
+    return np.ascontiguousarray(u[:, ::-1]), c.astype(np.float64)
 
 
 # The five workloads: spatial orbitals N (n = 2N qubits, half filling),

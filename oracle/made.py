@@ -46,6 +46,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+from .pauli import configs
+
 
 @dataclass
 class Net:
@@ -123,7 +125,15 @@ def masks(net: Net):
 
 
 def bits(net: Net, samples):
-    s = np.asarray(samples, dtype=np.uint64)
+    s = configs(samples)
+    if s.dtype == object:
+        # Python integers (any width): bits of each 64-bit word in turn
+        out = np.zeros((s.shape[0], net.n), dtype=np.int64)
+        for w in range((net.n + 63) // 64):
+            word = ((s >> (64 * w)) & ((1 << 64) - 1)).astype(np.uint64)
+            j = np.arange(min(64, net.n - 64 * w), dtype=np.uint64)
+            out[:, 64 * w:64 * w + j.shape[0]] = (word[:, None] >> j[None, :]) & np.uint64(1)
+        return out
     j = np.arange(net.n, dtype=np.uint64)
     return ((s[:, None] >> j[None, :]) & np.uint64(1)).astype(np.int64)
 

@@ -19,8 +19,39 @@ SIGMA = (
 )
 
 
+_W64 = (1 << 64) - 1
+
+
+def configs(v):
+    """Bit strings as an array: uint64 when given as uint64 (up to 64 qubits),
+    Python integers (dtype object) when given so (any width).  A uint64
+    [B, W] array of words (word w = qubits 64w .. 64w+63) becomes Python
+    integers."""
+    a = np.asarray(v)
+    if a.dtype == object:
+        return a
+    a = a.astype(np.uint64)
+    if a.ndim == 2:
+        out = np.empty(a.shape[0], dtype=object)
+        for i, row in enumerate(a.tolist()):
+            out[i] = sum(int(w) << (64 * k) for k, w in enumerate(row))
+        return out
+    return a
+
+
 def popcount(v):
-    return np.bitwise_count(np.asarray(v, dtype=np.uint64)).astype(np.int64)
+    a = np.asarray(v)
+    if a.dtype == object:
+        # Python integers: the counts of their 64-bit words, added
+        total = np.zeros(a.shape, dtype=np.int64)
+        rest = a
+        while True:
+            word = (rest & _W64).astype(np.uint64)
+            total += np.bitwise_count(word).astype(np.int64)
+            rest = rest >> 64
+            if not np.any(rest != 0):
+                return total
+    return np.bitwise_count(a.astype(np.uint64)).astype(np.int64)
 
 
 def pauli_labels(x_mask: int, z_mask: int, n: int):
@@ -52,8 +83,8 @@ def matrix_element(x, x_mask, z_mask):
     r = number of sigma_2 factors = popcount(x_mask & z_mask); the sign uses
     the row configuration x (reading: the sample is the bra).
     """
-    r = int(popcount(np.uint64(x_mask) & np.uint64(z_mask)))
-    sign = -1.0 if (int(popcount(np.uint64(x) & np.uint64(z_mask))) & 1) else 1.0
+    r = bin(int(x_mask) & int(z_mask)).count("1")
+    sign = -1.0 if (bin(int(x) & int(z_mask)).count("1") & 1) else 1.0
     return ((-1j) ** r) * sign
 
 
@@ -68,10 +99,12 @@ def canonical_terms(x_mask, z_mask, coeff, coeff_imag=None, drop_tol=1e-10):
       4. ct = c * (-i)^{popcount(x&z)} (the r-dependent factor of
          Eq. mtx_element), complex in general;
       5. sorted by (x ascending, z ascending) as unsigned integers.
-    Returns dict with uint64 arrays x, z, complex128 ct, float64 c.
+    Returns dict with arrays x, z (uint64, or Python integers when the masks
+    are given as Python integers or as [K, W] words), complex128 ct, float64 c.
     """
-    x_mask = np.asarray(x_mask, dtype=np.uint64)
-    z_mask = np.asarray(z_mask, dtype=np.uint64)
+    x_mask = configs(x_mask)
+    z_mask = configs(z_mask)
+    wide = x_mask.dtype == object
     coeff = np.asarray(coeff, dtype=np.float64)
     if coeff_imag is not None:
         coeff_imag = np.asarray(coeff_imag, dtype=np.float64)
@@ -88,8 +121,10 @@ def canonical_terms(x_mask, z_mask, coeff, coeff_imag=None, drop_tol=1e-10):
             order.append(key)
     keys = [k for k in order if abs(acc[k]) >= drop_tol]
     keys.sort()
-    x = np.array([k[0] for k in keys], dtype=np.uint64)
-    z = np.array([k[1] for k in keys], dtype=np.uint64)
+    x = np.empty(len(keys), dtype=object) if wide else np.zeros(len(keys), dtype=np.uint64)
+    z = np.empty(len(keys), dtype=object) if wide else np.zeros(len(keys), dtype=np.uint64)
+    for i, k in enumerate(keys):
+        x[i], z[i] = k
     c = np.array([acc[k] for k in keys], dtype=np.float64)
     r = popcount(x & z)
     phase = np.array([1, -1j, -1, 1j], dtype=np.complex128)[r % 4]

@@ -18,13 +18,16 @@ import math
 import numpy as np
 
 from . import made
-from .pauli import popcount, groups
+from .pauli import popcount, groups, configs
 
 UP_MASK = np.uint64(0x5555555555555555)
 DN_MASK = np.uint64(0xAAAAAAAAAAAAAAAA)
+# the same masks over 128 qubits, for bit strings held as Python integers
+UP_MASK_WIDE = int("01" * 64, 2)
+DN_MASK_WIDE = int("10" * 64, 2)
 
 
-def log_psi(net, params, configs, rows=32768):
+def log_psi(net, params, configs_in, rows=32768):
     """Complex log psi for each configuration; -inf real part off-sector.
 
     Configurations that contradict a forced value of the modifier have
@@ -32,14 +35,14 @@ def log_psi(net, params, configs, rows=32768):
     only on the others (in batches of ``rows``); the values are those of
     ``made.forward``.
     """
-    configs = np.asarray(configs, dtype=np.uint64)
-    la = np.full(len(configs), -np.inf)
-    phi = np.zeros(len(configs))
-    _, bad = made.constraint(net, made.bits(net, configs))
+    cfg = configs(configs_in)
+    la = np.full(len(cfg), -np.inf)
+    phi = np.zeros(len(cfg))
+    _, bad = made.constraint(net, made.bits(net, cfg))
     idx = np.nonzero(~bad)[0]
     for s in range(0, len(idx), rows):
         sel = idx[s:s + rows]
-        a, p, _ = made.forward(net, params, configs[sel])
+        a, p, _ = made.forward(net, params, cfg[sel])
         la[sel] = a
         phi[sel] = p
     return la, phi
@@ -55,7 +58,7 @@ def local_energy(terms, net, params, samples, batch_terms=4_000_000):
 
 def local_energy_fn(terms, logpsi, samples, batch_terms=4_000_000):
     """Eq. local_energy_auto for any amplitude given as ``logpsi(configs) -> (log|psi|, phase)``."""
-    samples = np.asarray(samples, dtype=np.uint64)
+    samples = configs(samples)
     xk, zk, ct = terms["x"], terms["z"], terms["ct"]
     la_s, ph_s = logpsi(samples)
     if np.any(~np.isfinite(la_s)):
@@ -107,10 +110,11 @@ def gradient(net, params, samples, weights, eloc, ebar):
 
 def sector_valid(x, flip):
     """Integer spin-sector test: the flip keeps the number of up and down electrons."""
-    x = np.asarray(x, dtype=np.uint64)
-    y = x ^ np.asarray(flip, dtype=np.uint64)
-    return (popcount(x & UP_MASK) == popcount(y & UP_MASK)) & \
-           (popcount(x & DN_MASK) == popcount(y & DN_MASK))
+    x = configs(x)
+    y = x ^ configs(flip)
+    up, dn = (UP_MASK_WIDE, DN_MASK_WIDE) if y.dtype == object else (UP_MASK, DN_MASK)
+    return (popcount(x & up) == popcount(y & up)) & \
+           (popcount(x & dn) == popcount(y & dn))
 
 
 def connected(terms, samples, sector_filter=True):
@@ -128,7 +132,7 @@ def connected(terms, samples, sector_filter=True):
     """
     gx, goff = groups(terms)
     zk, ct = terms["z"], terms["ct"]
-    samples = np.asarray(samples, dtype=np.uint64)
+    samples = configs(samples)
     B = len(samples)
     G = len(gx)
     H = np.zeros((B, G), dtype=np.complex128)
@@ -148,7 +152,7 @@ def connected(terms, samples, sector_filter=True):
     for i in range(B):
         gi = np.arange(gstart, G)
         if sector_filter:
-            keep = sector_valid(np.full(len(gi), samples[i]), gx[gi])
+            keep = sector_valid(np.full(len(gi), samples[i], dtype=samples.dtype), gx[gi])
         else:
             keep = H[i, gi] != 0
         gi = gi[keep]
