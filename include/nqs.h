@@ -17,7 +17,12 @@
  *                  L = <H>/2).
  *
  * Conventions shared by every call
- *   - Qubit j is bit j of a uint64 (the paper's x_{j+1}); n_qubits <= 64.
+ *   - A bit string (a sample, a configuration, a mask) of n qubits is W =
+ *     ceil(n / 64) uint64 words, W = 1 for n <= 64 and W = 2 for
+ *     64 < n <= 128 (the paper's largest system has 76 qubits, Sec. 6):
+ *     qubit j is bit (j mod 64) of word j / 64 (qubit j is the paper's
+ *     x_{j+1}).  Arrays of bit strings are word-major per string: string i
+ *     occupies words [i*W, i*W + W).
  *   - A Pauli string is (x_mask, z_mask): factor on qubit j is I, X, Z, Y for
  *     (x_j, z_j) = (0,0), (1,0), (0,1), (1,1) (Sec. 3, Eq. 1).
  *   - Even qubits carry spin up, odd qubits spin down (Sec. 4, Constraints).
@@ -48,7 +53,7 @@ extern "C" {
 typedef enum {
   NQS_OK = 0,
   NQS_ERR_INVALID_ARGUMENT = 1,
-  NQS_ERR_UNSUPPORTED = 2,          /* n_qubits > 64, width, device not gfx950 */
+  NQS_ERR_UNSUPPORTED = 2,          /* n_qubits > 128, width, device not gfx950 */
   NQS_ERR_NOT_HERMITIAN = 3,        /* nonzero imaginary Pauli coefficient    */
   NQS_ERR_WORKSPACE_TOO_SMALL = 4,
   NQS_ERR_HIP = 5,                  /* a HIP runtime call failed              */
@@ -89,15 +94,17 @@ void       nqs_ctx_destroy(nqs_ctx* ctx);
  *      coefficient: ct_k = alpha_k (-i)^{r_k}, stored as (re, im) planes;
  *   5. terms are sorted by (x_mask, z_mask) ascending and grouped by x_mask
  *      (one group per distinct flip; group 0 is the empty flip if present).
- * Device layout (structure of arrays, written by nqs_ham_upload into caller
- * storage of nqs_ham_info's `bytes`): gx[G] u64 flips, goff[G+1] i64 term
- * offsets, tz[K] u64 z masks, tc_re[K] f64, tc_im[K] f64 (only if has_imag).
+ * Masks are ordered as unsigned integers of n bits (the last word most
+ * significant).  Device layout (structure of arrays, written by
+ * nqs_ham_upload into caller storage of nqs_ham_info's `bytes`): gx[G][W]
+ * u64 flips, goff[G+1] i64 term offsets, tz[K][W] u64 z masks, tc_re[K] f64,
+ * tc_im[K] f64 (only if has_imag).
  */
 typedef struct {
-  int            n_qubits;     /* 1..64 */
+  int            n_qubits;     /* 1..128 */
   int64_t        n_terms;      /* input terms, >= 0 */
-  const uint64_t* x_mask;      /* host [n_terms] */
-  const uint64_t* z_mask;      /* host [n_terms] */
+  const uint64_t* x_mask;      /* host [n_terms][W] */
+  const uint64_t* z_mask;      /* host [n_terms][W] */
   const double*   coeff;       /* host [n_terms], real part */
   const double*   coeff_imag;  /* host [n_terms] or NULL; must be all zero */
   double          drop_tol;    /* merged |alpha| < drop_tol removed (e.g. 1e-10) */
@@ -119,7 +126,8 @@ nqs_status nqs_ham_info(const nqs_ham* ham, int64_t* K, int64_t* G, size_t* byte
    context's stream and records the pointer; the storage must outlive every
    plan built on this Hamiltonian.  This call synchronises the stream. */
 nqs_status nqs_ham_upload(nqs_ham* ham, nqs_ctx* ctx, void* d_storage, size_t bytes);
-/* Host copy of the canonical tensor (any pointer may be NULL to skip). */
+/* Host copy of the canonical tensor (any pointer may be NULL to skip):
+   gx [G][W], goff [G+1], tz [K][W], tc_re [K], tc_im [K]. */
 nqs_status nqs_ham_export(const nqs_ham* ham, uint64_t* gx, int64_t* goff, uint64_t* tz,
                           double* tc_re, double* tc_im);
 void       nqs_ham_destroy(nqs_ham* ham);
@@ -172,9 +180,10 @@ enum { NQS_FP64 = 0, NQS_FP32 = 1, NQS_BF16 = 2, NQS_BF16X3 = 3, NQS_BF16W = 4 }
 enum { NQS_PHASE_SHARED = 0, NQS_PHASE_SEPARATE = 1 };
 
 typedef struct {
-  int            n_qubits;   /* 2..64 */
+  int            n_qubits;   /* 2..128 */
   int            n_layers;   /* >= 1 */
-  int            width;      /* 64, 128, 256, 512 or 1024 (precision dependent) */
+  int            width;      /* 64, 128, 256, 512 or 1024 (precision dependent; above
+                                64 qubits not FP32 at 128 nor BF16 at 256) */
   const int32_t* order;      /* host [n_qubits] sampling order, NULL = n-1, ..., 0 */
   int            n_up, n_dn; /* electrons per spin; both -1 = unconstrained */
   int            precision;  /* NQS_FP64 | NQS_FP32 | NQS_BF16 | NQS_BF16X3 | NQS_BF16W
@@ -186,6 +195,8 @@ typedef struct {
 nqs_status nqs_net_param_count(const nqs_net_desc* net, int64_t* n_params);
 
 /* --------------------------------------------------------------------- plan */
+/* Dedup applies to one-word strings below 64 qubits; at 64 qubits or more
+   the flags are accepted and dedup stays off. */
 #define NQS_PLAN_DEDUP_ON   1u   /* deduplicate connected configurations per chunk */
 #define NQS_PLAN_DEDUP_OFF  2u   /* never deduplicate (default when no flag is set) */
 #define NQS_PLAN_DEDUP_AUTO 4u   /* size the workspace for dedup, start with it on and
@@ -251,7 +262,7 @@ nqs_status nqs_plan_autotune(nqs_plan* plan, const float* d_params, const uint64
 /* ---------------------------------------------------------------- hot path
  * All pointers are device pointers; d_ws is a workspace of at least
  * nqs_plan_workspace_size(plan, B) bytes, 256-byte aligned.  Samples are
- * read as uint64 [B]; weights f64 [B] (NULL = all 1).
+ * read as uint64 [B][W]; weights f64 [B] (NULL = all 1).
  */
 
 /* log psi for n configurations: d_out[2*i] = log|psi|, d_out[2*i+1] = phi,
@@ -293,12 +304,14 @@ typedef struct {
   double*         d_energy;  /* [3] */
   double*         d_grad;    /* [n_params] */
 } nqs_instance;
+/* Instances of more than 64 qubits give NQS_ERR_UNSUPPORTED. */
 nqs_status nqs_multi_workspace_size(int n_inst, const nqs_instance* inst, size_t* bytes);
 nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* d_ws, size_t ws_bytes);
 
 /* ---------------------------------------------------------------- sampler
  * Unique-sample autoregressive sampling of the plan's network (Sec. 4,
- * Sampling; Eq. modifier for the Hamming-weight constraint).  A buffer of
+ * Sampling; Eq. modifier for the Hamming-weight constraint), for plans of
+ * at most 64 qubits (NQS_ERR_UNSUPPORTED above).  A buffer of
  * distinct configurations with draw counts starts as the all-zero
  * configuration holding n_draws draws; at each sampling position t (qubit
  * order[t]) every entry is doubled into x = 0 / x = 1 children, its draws
@@ -340,12 +353,12 @@ nqs_status nqs_adam_step(nqs_ctx* ctx, int64_t n, float* d_params, const double*
  * nqs_connected enumerates, for samples [0, B), the diagonal element
  * d_diag[2*i..] (group with empty flip) and the compacted connected entries
  * in sample-major, group-ascending order: d_entry_sample[e] (i32),
- * d_entry_x[e] = x_i ^ f_g (u64), d_entry_h[2*e..] = sum over the group's
+ * d_entry_x[e] = x_i ^ f_g (W u64 words), d_entry_h[2*e..] = sum over the group's
  * terms of ct_k (-1)^{popcount(x_i & z_k)} summed sequentially in canonical
  * order (FP64).  Entry buffers must hold `capacity` entries; the count is
  * written to d_n_entries[0] (if it exceeds capacity only the first
  * `capacity` are written and NQS_DEV_ENTRY_OVERFLOW is raised).  With dedup
- * (plan flag) d_unique[u] receives the distinct x' (any order), d_n_unique[0]
+ * (plan flag; one-word strings only) d_unique[u] receives the distinct x' (any order), d_n_unique[0]
  * their number and d_entry_unique[e] the index of entry e's x' in d_unique;
  * without dedup these outputs may be NULL.
  */

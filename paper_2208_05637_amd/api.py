@@ -3,7 +3,10 @@
 Argument marshalling only: every step of the path runs in the HIP library.
 PyTorch supplies device memory (tensors) and the stream
 (``torch.cuda.current_stream()``).  Samples are uint64 bit strings; as torch
-has few uint64 ops they travel as int64 tensors with the same bits.
+has few uint64 ops they travel as int64 tensors with the same bits.  A bit
+string of n qubits is W = ceil(n / 64) words: samples are [B] for n <= 64 and
+[B, 2] (word w = qubits 64w .. 64w+63) for 64 < n <= 128, and so are the
+Pauli masks ([K] or [K, 2]).
 """
 import ctypes as C
 
@@ -17,6 +20,11 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def words(n_qubits):
+    """64-bit words per bit string of n qubits."""
+    return (int(n_qubits) + 63) // 64
+
+
 def _as_u64_tensor(x, device):
     if isinstance(x, torch.Tensor):
         if x.dtype not in (torch.int64, torch.uint64):
@@ -24,6 +32,19 @@ def _as_u64_tensor(x, device):
         return x.to(device).contiguous()
     arr = np.ascontiguousarray(np.asarray(x, dtype=np.uint64)).view(np.int64)
     return torch.from_numpy(arr.copy()).to(device)
+
+
+def _strings(x, device, W):
+    """(tensor, count) of bit strings of W words: [B] for W = 1, [B, W] else."""
+    t = _as_u64_tensor(x, device)
+    if W == 1:
+        if t.dim() == 2 and t.shape[1] == 1:
+            t = t.reshape(-1)
+        if t.dim() != 1:
+            raise ValueError("bit strings of at most 64 qubits are a 1-D array")
+    elif t.dim() != 2 or t.shape[1] != W:
+        raise ValueError(f"bit strings of more than 64 qubits are a [B, {W}] array of words")
+    return t, t.shape[0]
 
 
 class Context:
@@ -56,11 +77,16 @@ class Hamiltonian:
                  conserves_spin=True):
         self.lib = L.load()
         self.n = int(n_qubits)
+        self.words = words(self.n)
         self._x = np.ascontiguousarray(np.asarray(x_mask, dtype=np.uint64))
         self._z = np.ascontiguousarray(np.asarray(z_mask, dtype=np.uint64))
+        want = 1 if self.words == 1 else 2
+        if self._x.ndim != want or self._z.shape != self._x.shape or (want == 2 and self._x.shape[1] != self.words):
+            raise ValueError(f"masks of {self.n} qubits must be uint64 arrays of shape "
+                             f"{'[K]' if want == 1 else f'[K, {self.words}]'}")
         self._c = np.ascontiguousarray(np.asarray(coeff, dtype=np.float64))
         self._ci = None if coeff_imag is None else np.ascontiguousarray(np.asarray(coeff_imag, dtype=np.float64))
-        t = L.PauliTerms(self.n, len(self._x), self._x.ctypes.data, self._z.ctypes.data,
+        t = L.PauliTerms(self.n, self._x.shape[0], self._x.ctypes.data, self._z.ctypes.data,
                          self._c.ctypes.data, None if self._ci is None else self._ci.ctypes.data,
                          float(drop_tol), L.NQS_H_CONSERVES_SPIN_SECTORS if conserves_spin else 0)
         h = C.c_void_p()
@@ -86,9 +112,10 @@ class Hamiltonian:
         return self
 
     def export(self):
-        gx = np.zeros(self.G, dtype=np.uint64)
+        shape = (lambda m: (m,)) if self.words == 1 else (lambda m: (m, self.words))
+        gx = np.zeros(shape(self.G), dtype=np.uint64)
         goff = np.zeros(self.G + 1, dtype=np.int64)
-        tz = np.zeros(self.K, dtype=np.uint64)
+        tz = np.zeros(shape(self.K), dtype=np.uint64)
         tre = np.zeros(self.K, dtype=np.float64)
         tim = np.zeros(self.K, dtype=np.float64)
         L.check(self.lib.nqs_ham_export(self.handle, gx.ctypes.data, goff.ctypes.data, tz.ctypes.data,
@@ -130,6 +157,7 @@ class Plan:
         """dedup: True, False or "auto" (the autotuner decides); phase_mode as in net_desc."""
         self.lib = L.load()
         self.ctx, self.ham = ctx, ham
+        self.words = ham.words
         self.precision = precision
         d, self._order = net_desc(ham.n, n_layers, width, n_up, n_dn, precision, order, phase_mode)
         if dedup == "auto":
@@ -169,10 +197,10 @@ class Plan:
         """Time the candidate kernel variants / dedup / chunk sizes on a prefix of
         the samples and keep the fastest; returns the timings."""
         params = _params(self, params)
-        x = _as_u64_tensor(samples, self.ctx.device)
+        x, B = _strings(samples, self.ctx.device, self.words)
         rep = L.TuneReport()
         ws, nb = self.workspace()
-        L.check(self.lib.nqs_plan_autotune(self.handle, _ptr(params), _ptr(x), x.numel(), ws, nb,
+        L.check(self.lib.nqs_plan_autotune(self.handle, _ptr(params), _ptr(x), B, ws, nb,
                                            L.NQS_TUNE_FORCE if force else 0, C.byref(rep)),
                 "nqs_plan_autotune")
         self._refresh()
@@ -231,20 +259,20 @@ def _params(plan, params):
 
 def log_psi(plan, params, x):
     params = _params(plan, params)
-    x = _as_u64_tensor(x, plan.ctx.device)
-    out = torch.empty((x.numel(), 2), dtype=torch.float64, device=plan.ctx.device)
+    x, B = _strings(x, plan.ctx.device, plan.words)
+    out = torch.empty((B, 2), dtype=torch.float64, device=plan.ctx.device)
     ws, nb = plan.workspace()
-    L.check(plan.lib.nqs_log_psi(plan.handle, _ptr(params), _ptr(x), x.numel(), _ptr(out), ws, nb),
+    L.check(plan.lib.nqs_log_psi(plan.handle, _ptr(params), _ptr(x), B, _ptr(out), ws, nb),
             "nqs_log_psi")
     return out
 
 
 def local_energy(plan, params, samples):
     params = _params(plan, params)
-    x = _as_u64_tensor(samples, plan.ctx.device)
-    out = torch.empty((x.numel(), 2), dtype=torch.float64, device=plan.ctx.device)
+    x, B = _strings(samples, plan.ctx.device, plan.words)
+    out = torch.empty((B, 2), dtype=torch.float64, device=plan.ctx.device)
     ws, nb = plan.workspace()
-    L.check(plan.lib.nqs_local_energy(plan.handle, _ptr(params), _ptr(x), x.numel(), _ptr(out), ws, nb),
+    L.check(plan.lib.nqs_local_energy(plan.handle, _ptr(params), _ptr(x), B, _ptr(out), ws, nb),
             "nqs_local_energy")
     return out
 
@@ -253,8 +281,7 @@ def energy_grad(plan, params, samples, weights=None, eloc=None, energy=None, gra
     """(energy[3] = (E, Im mean, W), grad f64 [n_params], eloc [B,2]) on the device."""
     params = _params(plan, params)
     dev = plan.ctx.device
-    x = _as_u64_tensor(samples, dev)
-    B = x.numel()
+    x, B = _strings(samples, dev, plan.words)
     w = None
     if weights is not None:
         w = _dev_tensor(torch.as_tensor(weights, dtype=torch.float64).to(dev).contiguous(), "weights",
@@ -275,9 +302,9 @@ def _instances(items):
     arr = (L.Instance * len(items))()
     for i, it in enumerate(items):
         plan, dev = it["plan"], it["plan"].ctx.device
-        B = it["samples"].numel()
+        B = it["samples"].shape[0]
         _dev_tensor(it["params"], "params", torch.float32, plan.n_params, dev)
-        _dev_tensor(it["samples"], "samples", (torch.int64, torch.uint64), B, dev)
+        _dev_tensor(it["samples"], "samples", (torch.int64, torch.uint64), B * plan.words, dev)
         if it.get("weights") is not None:
             _dev_tensor(it["weights"], "weights", torch.float64, B, dev)
         if it.get("eloc") is not None:
@@ -286,7 +313,7 @@ def _instances(items):
         _dev_tensor(it["grad"], "grad", torch.float64, plan.n_params, dev)
         arr[i] = L.Instance(it["plan"].handle.value, it["params"].data_ptr(), it["samples"].data_ptr(),
                             it["weights"].data_ptr() if it.get("weights") is not None else None,
-                            it["samples"].numel(),
+                            B,
                             it["eloc"].data_ptr() if it.get("eloc") is not None else None,
                             it["energy"].data_ptr(), it["grad"].data_ptr())
     return arr
@@ -331,13 +358,12 @@ def sample(plan, params, n_draws, seed, max_unique):
 
 def connected(plan, samples, capacity=None):
     dev = plan.ctx.device
-    x = _as_u64_tensor(samples, dev)
-    B = x.numel()
+    x, B = _strings(samples, dev, plan.words)
     cap = int(capacity if capacity is not None else max(1, B * plan.entries_per_sample))
     out = dict(
         diag=torch.empty((B, 2), dtype=torch.float64, device=dev),
         sample=torch.empty(cap, dtype=torch.int32, device=dev),
-        x=torch.empty(cap, dtype=torch.int64, device=dev),
+        x=torch.empty(cap if plan.words == 1 else (cap, plan.words), dtype=torch.int64, device=dev),
         h=torch.empty((cap, 2), dtype=torch.float64, device=dev),
         n_entries=torch.zeros(1, dtype=torch.int64, device=dev),
     )

@@ -315,13 +315,18 @@ static void gemm(const GemmArgs& a, const Geom& g, hipStream_t s) {
   hipLaunchKernelGGL((gemm_kernel<T, EPI>), grid, dim3(256), 0, s, a, g);
 }
 
+// Bit of qubit j of sample i (g.words 64-bit words per sample).
+__device__ __forceinline__ int qubit_bit(const Geom& g, const uint64_t* __restrict__ x, long long i, int j) {
+  return (int)((x[i * g.words + (j >> 6)] >> (j & 63)) & 1ull);
+}
+
 template <typename T>
 __global__ void bits_kernel(Geom g, const uint64_t* __restrict__ x, long long S, T* __restrict__ s) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= S * g.n) return;
   const long long i = e / g.n;
   const int j = (int)(e % g.n);
-  s[e] = ((x[i] >> j) & 1ull) ? (T)1 : (T)-1;
+  s[e] = qubit_bit(g, x, i, j) ? (T)1 : (T)-1;
 }
 
 template <typename T>
@@ -355,15 +360,15 @@ __global__ void seed_kernel(Geom g, const uint64_t* __restrict__ x, long long S,
   const double wi = w ? w[i] : 1.0;
   const double gla = 2.0 * (wi / W) * (eloc[2 * i] - E);
   const double gph = 2.0 * (wi / W) * eloc[2 * i + 1];
-  const uint64_t xi = x[i];
   const bool constrained = g.n_up >= 0 && g.n_dn >= 0;
   int placed[2] = {0, 0};
-  int remaining[2] = {(int)__popcll(g.spin_pos[0]), (int)__popcll(g.spin_pos[1])};
+  int remaining[2] = {(int)__popcll(g.spin_pos[0]) + (int)__popcll(g.spin_pos_hi[0]),
+                      (int)__popcll(g.spin_pos[1]) + (int)__popcll(g.spin_pos_hi[1])};
   for (int t = 0; t < n; ++t) {
     const int j = g.order[t];
     const int sp = j & 1;
     remaining[sp] -= 1;
-    const int bit = (int)((xi >> j) & 1ull);
+    const int bit = qubit_bit(g, x, i, j);
     bool fr = true;
     if (constrained) {
       const int ns = sp ? g.n_dn : g.n_up;
@@ -374,7 +379,7 @@ __global__ void seed_kernel(Geom g, const uint64_t* __restrict__ x, long long S,
     const double sig = 1.0 / (1.0 + exp(-o));
     dh[i * ld + j] = fr ? (T)(gla * 0.5 * ((double)bit - sig)) : (T)0;
   }
-  const int sel = (int)(2 * ((xi >> g.order[n - 2]) & 1ull) + ((xi >> g.order[n - 1]) & 1ull));
+  const int sel = 2 * qubit_bit(g, x, i, g.order[n - 2]) + qubit_bit(g, x, i, g.order[n - 1]);
   for (int c = 0; c < 4; ++c) dh[i * ld + n + c] = c == sel ? (T)gph : (T)0;
 }
 

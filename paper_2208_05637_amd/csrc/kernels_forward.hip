@@ -87,11 +87,15 @@ constexpr int variant_waves() {
 // (block, m-block) tiles than waves: a power of two, at most 8, and no more
 // than the planes that fit in 128 KB.
 constexpr int pow2_floor(int v) { return v >= 8 ? 8 : v >= 4 ? 4 : v >= 2 ? 2 : 1; }
-template <int P, int H, int NW>
+// Head outputs of the widest network a bit string of W words allows: n + 4
+// with n = 64 W.
+template <int W>
+constexpr int head_rows_max() { return 64 * W + 4; }
+template <int P, int H, int NW, int W>
 constexpr int head_ksplit_max() {
   constexpr int M = rows_per_block<P, H>();
   constexpr int MB = M / Tr<P>::TB;
-  constexpr int SP = ((68 + Tr<P>::TB - 1) / Tr<P>::TB) * Tr<P>::TB + 1;
+  constexpr int SP = ((head_rows_max<W>() + Tr<P>::TB - 1) / Tr<P>::TB) * Tr<P>::TB + 1;
   constexpr int fit = pow2_floor(131072 / (M * SP * (int)sizeof(typename Tr<P>::S)));
   constexpr int want = MB >= NW ? 1 : pow2_floor(NW / MB);
   return want < fit ? want : fit;
@@ -140,43 +144,58 @@ __device__ __forceinline__ void mma(typename Tr<P>::Acc& acc, const uint4* w, co
   }
 }
 
+// Word of a tile row's bit string (sampling order) that holds positions
+// k0 .. k0 + 7, and the position of its bit 0.  A fragment's positions never
+// straddle two words (k0 is a multiple of 2, 4 or 8 and the group is as long).
+template <int W>
+__device__ __forceinline__ uint64_t y_word(const uint64_t* ylds, int row, int k0, int& base) {
+  if constexpr (W == 1) {
+    base = 0;
+    return ylds[row];
+  } else {
+    base = k0 & ~63;
+    return ylds[row * W + (k0 >> 6)];
+  }
+}
+
 // +-1 input fragment of the first layer for m-block mb, k step ks.
 // Element (row m, k) is +1/-1 for occupied/empty position k < n, 0 beyond.
-template <int P>
+template <int P, int W>
 __device__ __forceinline__ void input_frag(const uint64_t* ylds, int mb, int ks, int lane, int n,
                                            uint4* out) {
   using T = Tr<P>;
+  int base;
   if constexpr (P == P_BF16 || P == P_BF16X3 || P == P_BF16W) {
-    uint64_t y = ylds[mb * 32 + (lane & 31)];
     int k0 = ks * 16 + 8 * (lane >> 5);
+    uint64_t y = y_word<W>(ylds, mb * 32 + (lane & 31), k0, base);
     unsigned short v[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       int k = k0 + j;
-      v[j] = k < n ? (((y >> k) & 1ull) ? (unsigned short)0x3F80 : (unsigned short)0xBF80)
+      v[j] = k < n ? (((y >> (k - base)) & 1ull) ? (unsigned short)0x3F80 : (unsigned short)0xBF80)
                    : (unsigned short)0;
     }
     out[0] = make_uint4(v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16),
                         v[6] | (v[7] << 16));
     if constexpr (T::PL == 2) out[1] = make_uint4(0, 0, 0, 0);
   } else if constexpr (P == P_F32) {
-    uint64_t y = ylds[mb * 32 + (lane & 31)];
     int k0 = ks * 8 + 4 * (lane >> 5);
+    uint64_t y = y_word<W>(ylds, mb * 32 + (lane & 31), k0, base);
     float v[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       int k = k0 + j;
-      v[j] = k < n ? (((y >> k) & 1ull) ? 1.f : -1.f) : 0.f;
+      v[j] = k < n ? (((y >> (k - base)) & 1ull) ? 1.f : -1.f) : 0.f;
     }
     out[0] = __builtin_bit_cast(uint4, make_float4(v[0], v[1], v[2], v[3]));
   } else {
-    uint64_t y = ylds[mb * 16 + (lane & 15)];
     int k0 = ks * 8 + 2 * (lane >> 4);
+    uint64_t y = y_word<W>(ylds, mb * 16 + (lane & 15), k0, base);
     double v[2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       int k = k0 + j;
-      v[j] = k < n ? (((y >> k) & 1ull) ? 1.0 : -1.0) : 0.0;
+      v[j] = k < n ? (((y >> (k - base)) & 1ull) ? 1.0 : -1.0) : 0.0;
     }
     out[0] = __builtin_bit_cast(uint4, make_double2(v[0], v[1]));
   }
@@ -427,7 +446,7 @@ __device__ __forceinline__ S softplus(S z) {
 }
 
 // Shape constants of one (precision, width, waves) instance of the kernel.
-template <int P, int H, int NW_>
+template <int P, int H, int NW_, int W = 1>
 struct Shape {
   using T = Tr<P>;
   using S = typename T::S;
@@ -438,29 +457,43 @@ struct Shape {
   static constexpr int WN = NB < NW ? NB : NW, WM = NW / WN;
   static constexpr int NBW = NB / WN, MBW = MB / WM;
   static constexpr int KSH = H / T::KSTEP;
-  static constexpr int NHBMAX = (68 + TB - 1) / TB;
+  static constexpr int NHBMAX = (head_rows_max<W>() + TB - 1) / TB;
   static constexpr int HP = (NHBMAX * MB + NW - 1) / NW;
   static constexpr int SP = NHBMAX * TB + 1;
-  static constexpr int KSPLIT_MAX = head_ksplit_max<P, H, NW>();
+  static constexpr int KSPLIT_MAX = head_ksplit_max<P, H, NW, W>();
   static constexpr long ACT_BYTES = (long)PL * KSH * MB * 1024;
   static constexpr long STAGE_BYTES = (long)M * SP * sizeof(S) * KSPLIT_MAX;
   static constexpr long REGION = ACT_BYTES > STAGE_BYTES ? ACT_BYTES : STAGE_BYTES;
-  // LDS: activations / head staging, then the tile's bit strings, then the
-  // bias being applied
+  // LDS: activations / head staging, then the tile's bit strings (W words
+  // each, in sampling order), then the bias being applied
   static constexpr long Y_OFF = REGION;
-  static constexpr long B_OFF = Y_OFF + (long)M * 8;
+  static constexpr long B_OFF = Y_OFF + (long)M * 8 * W;
   static constexpr long LDS = B_OFF + (long)(H + NHBMAX * TB) * sizeof(S);
+  static constexpr bool FITS = LDS <= 160 * 1024;
   static_assert(MB % WM == 0 && NB % WN == 0 && MB >= 1, "tile shape");
-  static_assert(LDS <= 160 * 1024, "LDS budget");
+  // one-word shapes always fit; a two-word shape whose head staging does
+  // not fit (256-row tiles) is reported unsupported instead
+  static_assert(W == 2 || FITS, "LDS budget");
 };
+
+// Ones among positions p < t (popc_below2) and p > t (popc_above2) of a
+// two-word string (a0: positions 0..63, a1: positions 64..127), 0 <= t < 128.
+__device__ __forceinline__ int popc_below2(uint64_t a0, uint64_t a1, int t) {
+  if (t <= 64) return t == 0 ? 0 : __popcll(a0 & (~0ull >> (64 - t)));
+  return __popcll(a0) + __popcll(a1 & (~0ull >> (128 - t)));
+}
+__device__ __forceinline__ int popc_above2(uint64_t a0, uint64_t a1, int t) {
+  if (t >= 64) return t >= 127 ? 0 : __popcll(a1 & (~0ull << (t - 63)));
+  return (t >= 63 ? 0 : __popcll(a0 & (~0ull << (t + 1)))) + __popcll(a1);
+}
 
 // Rows [row0, row0 + M) of one batch through the whole network; rows at or
 // beyond count are computed on a copy of row0 and not written.
-template <int P, int H, int NW>
+template <int P, int H, int NW, int W>
 __device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict__ wpk,
                                          const uint64_t* __restrict__ xs, long long row0, long long count,
                                          double2* __restrict__ out, char* act, int cond) {
-  using Sh = Shape<P, H, NW>;
+  using Sh = Shape<P, H, NW, W>;
   using T = Tr<P>;
   using Acc = typename T::Acc;
   using S = typename T::S;
@@ -524,27 +557,65 @@ __device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict_
     kloop_pre<P, NBW>(pre, wbuf, fragi, ksi);
   };
 
-  uint64_t x = 0;
-  if (tid < M) {
-    const long long row = row0 + tid;
-    x = xs[row < count ? row : row0];
-  }
-  if (EARLY) preload(1);   // overlaps the configuration load
-  if (tid < M) {
-    // bits into sampling order: y bit p = x bit order[p]
-    uint64_t y;
-    if (g.order_kind == 2) {
-      y = __builtin_bitreverse64(x) >> (64 - g.n);
-    } else if (g.order_kind == 1) {
-      y = x;
-    } else {
-      // unrolled with constant indices, so the order bytes are scalar loads
-      y = 0;
-#pragma unroll
-      for (int p = 0; p < 64; ++p)
-        if (p < g.n) y |= ((x >> g.order[p]) & 1ull) << p;
+  if constexpr (W == 1) {
+    uint64_t x = 0;
+    if (tid < M) {
+      const long long row = row0 + tid;
+      x = xs[row < count ? row : row0];
     }
-    ylds[tid] = y;
+    if (EARLY) preload(1);   // overlaps the configuration load
+    if (tid < M) {
+      // bits into sampling order: y bit p = x bit order[p]
+      uint64_t y;
+      if (g.order_kind == 2) {
+        y = __builtin_bitreverse64(x) >> (64 - g.n);
+      } else if (g.order_kind == 1) {
+        y = x;
+      } else {
+        // unrolled with constant indices, so the order bytes are scalar loads
+        y = 0;
+#pragma unroll
+        for (int p = 0; p < 64; ++p)
+          if (p < g.n) y |= ((x >> g.order[p]) & 1ull) << p;
+      }
+      ylds[tid] = y;
+    }
+  } else {
+    // two words: word w holds qubits (positions) 64w .. 64w+63
+    uint64_t x0 = 0, x1 = 0;
+    if (tid < M) {
+      const long long row = row0 + tid;
+      const long long r = row < count ? row : row0;
+      x0 = xs[2 * r];
+      x1 = xs[2 * r + 1];
+    }
+    if (EARLY) preload(1);
+    if (tid < M) {
+      uint64_t y0, y1;
+      if (g.order_kind == 2) {
+        // reverse the 128-bit string, then drop the 128 - n empty positions
+        const uint64_t r0 = __builtin_bitreverse64(x1), r1 = __builtin_bitreverse64(x0);
+        const int sh = 128 - g.n;   // 0 .. 63
+        y0 = sh == 0 ? r0 : ((r0 >> sh) | (r1 << (64 - sh)));
+        y1 = r1 >> sh;
+      } else if (g.order_kind == 1) {
+        y0 = x0;
+        y1 = x1;
+      } else {
+        y0 = 0;
+        y1 = 0;
+#pragma unroll
+        for (int p = 0; p < 2 * 64; ++p)
+          if (p < g.n) {
+            const int q = g.order[p];
+            const uint64_t b = ((q < 64 ? x0 : x1) >> (q & 63)) & 1ull;
+            if (p < 64) y0 |= b << p;
+            else y1 |= b << (p - 64);
+          }
+      }
+      ylds[2 * tid] = y0;
+      ylds[2 * tid + 1] = y1;
+    }
   }
   for (int t = tid; t < H; t += NT) blds[t] = biases[t];
   __syncthreads();
@@ -565,7 +636,7 @@ __device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict_
       for (int j = 0; j < MBW; ++j) acc[i][j] = Acc{};
     // the +-1 inputs are exact in BF16
     kloop<P, NBW, MBW, Sh::NW, true>(acc, wbuf, pre,
-                                     [&](int j, int ks, uint4 (&f)[PL]) { input_frag<P>(ylds, mbl[j], ks, lane, g.n, f); });
+                                     [&](int j, int ks, uint4 (&f)[PL]) { input_frag<P, W>(ylds, mbl[j], ks, lane, g.n, f); });
 #pragma unroll
     for (int i = 0; i < NBW; ++i)
 #pragma unroll
@@ -656,7 +727,8 @@ __device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict_
   const int row = tid / TPR, sub = tid % TPR;
   if (row < M) {
     const S* hb = blds;
-    const uint64_t y = ylds[row];
+    const uint64_t y = ylds[row * W];
+    const uint64_t yh = W == 2 ? ylds[row * W + 1] : 0ull;   // positions 64..127
     const bool constrained = g.n_up >= 0 && g.n_dn >= 0;
     auto head_out = [&](int col) {
       S v = stage[row * SP + col];
@@ -666,11 +738,35 @@ __device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict_
     double sum = 0.0;
     int bad = 0;
     const uint64_t sp0 = g.spin_pos[0], sp1 = g.spin_pos[1];
+    const uint64_t sp0h = W == 2 ? g.spin_pos_hi[0] : 0ull, sp1h = W == 2 ? g.spin_pos_hi[1] : 0ull;
+    // bit of position t, and the spin of the qubit there
+    auto ybit = [&](int t) -> int {
+      if constexpr (W == 1) return (int)((y >> t) & 1ull);
+      else return (int)(((t < 64 ? y : yh) >> (t & 63)) & 1ull);
+    };
+    auto spin = [&](int t) -> int {
+      if constexpr (W == 1) return (int)((sp1 >> t) & 1ull);
+      else return (int)(((t < 64 ? sp1 : sp1h) >> (t & 63)) & 1ull);
+    };
+    // c = ones among the earlier positions of spin sp, rem = later positions of spin sp
+    auto spin_counts = [&](int t, int sp, int& c, int& rem) {
+      const uint64_t spm = sp ? sp1 : sp0;
+      if constexpr (W == 1) {
+        const uint64_t low = t == 0 ? 0ull : (~0ull >> (64 - t));
+        const uint64_t high = t >= 63 ? 0ull : (~0ull << (t + 1));
+        c = __popcll(y & spm & low);
+        rem = __popcll(spm & high);
+      } else {
+        const uint64_t spmh = sp ? sp1h : sp0h;
+        c = popc_below2(y & spm, yh & spmh, t);
+        rem = popc_above2(spm, spmh, t);
+      }
+    };
     const long long grow = row0 + row;
     if (g.net_kind == 2) {
       // separate phase network: the phase of the completion of the last two positions
       if (sub == 0 && grow < count) {
-        const int sel = (int)(2 * ((y >> (g.n - 2)) & 1ull) + ((y >> (g.n - 1)) & 1ull));
+        const int sel = 2 * ybit(g.n - 2) + ybit(g.n - 1);
         ((double*)out)[2 * grow + 1] = (double)head_out(sel);
       }
       return;
@@ -682,12 +778,9 @@ __device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict_
         const int t = cond;
         int code = 0;
         if (constrained) {
-          const int sp = (int)((sp1 >> t) & 1ull);
-          const uint64_t spm = sp ? sp1 : sp0;
-          const uint64_t low = t == 0 ? 0ull : (~0ull >> (64 - t));
-          const uint64_t high = t >= 63 ? 0ull : (~0ull << (t + 1));
-          const int c = __popcll(y & spm & low);
-          const int rem = __popcll(spm & high);
+          const int sp = spin(t);
+          int c, rem;
+          spin_counts(t, sp, c, rem);
           const int ns = sp ? g.n_dn : g.n_up;
           code = (c + rem < ns) ? 2 : (c >= ns ? 1 : 0);
         }
@@ -697,15 +790,12 @@ __device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict_
     }
     for (int t = sub; t < g.n; t += TPR) {
       const S o = head_out(t);
-      const int sp = (int)((sp1 >> t) & 1ull);   // spin of the qubit at position t
-      const uint64_t spm = sp ? sp1 : sp0;
-      const int bit = (int)((y >> t) & 1ull);
+      const int sp = spin(t);   // spin of the qubit at position t
+      const int bit = ybit(t);
       bool fr = true;
       if (constrained) {
-        const uint64_t low = t == 0 ? 0ull : (~0ull >> (64 - t));
-        const uint64_t high = t >= 63 ? 0ull : (~0ull << (t + 1));
-        const int c = __popcll(y & spm & low);
-        const int rem = __popcll(spm & high);
+        int c, rem;
+        spin_counts(t, sp, c, rem);
         const int ns = sp ? g.n_dn : g.n_up;
         const bool f0 = c >= ns, f1 = c + rem < ns;
         bad |= (f0 && bit) || (f1 && !bit);
@@ -724,7 +814,7 @@ __device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict_
         // modulus network of a two-network model: the phase network writes phi
         ((double*)out)[2 * grow] = la;
       } else {
-        const int sel = (int)(2 * ((y >> (g.n - 2)) & 1ull) + ((y >> (g.n - 1)) & 1ull));
+        const int sel = 2 * ybit(g.n - 2) + ybit(g.n - 1);
         out[grow] = make_double2(la, (double)head_out(g.n + sel));
       }
     }
@@ -747,9 +837,10 @@ __device__ __forceinline__ long long seg_rows(const Seg& sg) {
 // MULTI = true: up to kMaxSeg segments (a work list of tiles from several
 // networks); a tile's segment is found from the tile index and its geometry
 // read from the segment's device copy.
-template <int P, int H, int NW, bool MULTI>
+// W: 64-bit words per bit string (2 only with MULTI = false).
+template <int P, int H, int NW, bool MULTI, int W>
 __global__ __launch_bounds__(64 * NW) void fused_forward(Geom g0, FwdLaunch la) {
-  using Sh = Shape<P, H, NW>;
+  using Sh = Shape<P, H, NW, W>;
   constexpr int M = Sh::M;
   extern __shared__ uint4 smem[];
   char* act = (char*)smem;
@@ -758,8 +849,9 @@ __global__ __launch_bounds__(64 * NW) void fused_forward(Geom g0, FwdLaunch la) 
     const FwdSeg& sg = la.seg[0];
     const long long rows = seg_rows(sg);
     if (t * M < rows)
-      fwd_tile<P, H, NW>(g0, (const uint4*)sg.packed, sg.x, t * M, rows, (double2*)sg.out, act, la.cond_pos);
+      fwd_tile<P, H, NW, W>(g0, (const uint4*)sg.packed, sg.x, t * M, rows, (double2*)sg.out, act, la.cond_pos);
   } else {
+    static_assert(W == 1, "multi-segment launches take one-word bit strings");
     int k = 0;
     for (int j = 1; j < la.nseg; ++j)
       if (t >= la.seg[j].tile0) k = j;
@@ -769,7 +861,7 @@ __global__ __launch_bounds__(64 * NW) void fused_forward(Geom g0, FwdLaunch la) 
     // the geometry is read in place: nothing in this kernel writes global
     // memory before the tile's outputs, so its loads stay scalar
     if (row0 < rows)
-      fwd_tile<P, H, NW>(*sg.geom, (const uint4*)sg.packed, sg.x, row0, rows, (double2*)sg.out, act, la.cond_pos);
+      fwd_tile<P, H, NW, W>(*sg.geom, (const uint4*)sg.packed, sg.x, row0, rows, (double2*)sg.out, act, la.cond_pos);
   }
   if (t == 0 && threadIdx.x == 0) {
     for (int k = 0; k < la.nseg; ++k)
@@ -787,12 +879,15 @@ void launch_store_geom(const Geom& g, Geom* dst, hipStream_t s) {
   hipLaunchKernelGGL(store_geom_kernel, dim3(1), dim3(256), 0, s, g, dst);
 }
 
-template <int P, int H, int V, bool MULTI>
+template <int P, int H, int V, bool MULTI, int W>
 static void launch_one(const Geom& g, FwdLaunch& la, hipStream_t s) {
   constexpr int NW = variant_waves<P, H, V>();
-  using Sh = Shape<P, H, NW>;
+  using Sh = Shape<P, H, NW, W>;
+  if constexpr (!Sh::FITS) {
+    return;   // forward_supported() rejects this shape before any launch
+  } else {
   constexpr size_t LDS = Sh::LDS;
-  auto kern = fused_forward<P, H, NW, MULTI>;
+  auto kern = fused_forward<P, H, NW, MULTI, W>;
   // the LDS opt-in, once per device (one bit per device ordinal), safe across threads
   static std::atomic<unsigned long long> attr_done{0};
   int dev = 0;
@@ -816,6 +911,7 @@ static void launch_one(const Geom& g, FwdLaunch& la, hipStream_t s) {
     const long long nb = std::min(max_tiles, tiles - t0);
     hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(64 * NW), LDS, s, g, la);
   }
+  }
 }
 
 int forward_rows_per_block(int prec, int h) {
@@ -827,7 +923,23 @@ int forward_rows_per_block(int prec, int h) {
   }
 }
 
-bool forward_supported(int prec, int h) {
+template <int P, int H>
+static constexpr bool fits_two_words() {
+  return Shape<P, H, variant_waves<P, H, 0>(), 2>::FITS &&
+         (P == P_F64 || Shape<P, H, variant_waves<P, H, 1>(), 2>::FITS);
+}
+
+bool forward_supported(int prec, int h, int words) {
+  if (words == 2) {
+    // tiles of 256 rows leave no LDS for the head staging of 132 outputs
+    static_assert(!fits_two_words<P_BF16, 256>() && !fits_two_words<P_F32, 128>(), "two-word shapes");
+    static_assert(fits_two_words<P_BF16, 512>() && fits_two_words<P_F32, 256>() && fits_two_words<P_F64, 64>() &&
+                      fits_two_words<P_BF16W, 256>() && fits_two_words<P_BF16X3, 256>(),
+                  "two-word shapes");
+    if ((prec == P_BF16 && h == 256) || (prec == P_F32 && h == 128)) return false;
+  } else if (words != 1) {
+    return false;
+  }
   switch (prec) {
     case P_BF16: case P_BF16X3: case P_BF16W: return h == 256 || h == 512 || h == 1024;
     case P_F32: return h == 128 || h == 256 || h == 512 || h == 1024;
@@ -846,14 +958,14 @@ int forward_variant_waves(int prec, int h, int v) {
   return v == 0 ? d : (d == 16 ? 8 : 16);
 }
 
-template <bool MULTI>
+template <bool MULTI, int W>
 static void dispatch(const Geom& g, int prec, int h, int v, FwdLaunch& la, hipStream_t s) {
 #define NQS_CASE(P, H)                                                  \
   if (prec == P && h == H) {                                            \
     if constexpr (P != P_F64) {                                         \
-      if (v == 1) { launch_one<P, H, 1, MULTI>(g, la, s); return; }     \
+      if (v == 1) { launch_one<P, H, 1, MULTI, W>(g, la, s); return; }  \
     }                                                                   \
-    launch_one<P, H, 0, MULTI>(g, la, s);                               \
+    launch_one<P, H, 0, MULTI, W>(g, la, s);                            \
     return;                                                             \
   }
   NQS_CASE(P_BF16, 256) NQS_CASE(P_BF16, 512) NQS_CASE(P_BF16, 1024)
@@ -871,7 +983,8 @@ void launch_forward(const Geom& g, int variant, const void* packed, const uint64
   la.nseg = 1;
   la.cond_pos = -1;
   la.seg[0] = FwdSeg{nullptr, packed, x, d_count, out, rows_bound, 0, prof_slot};
-  dispatch<false>(g, g.prec, g.h, variant, la, s);
+  if (g.words == 2) dispatch<false, 2>(g, g.prec, g.h, variant, la, s);
+  else dispatch<false, 1>(g, g.prec, g.h, variant, la, s);
 }
 
 void launch_forward_cond(const Geom& g, int variant, const void* packed, const uint64_t* x,
@@ -881,14 +994,15 @@ void launch_forward_cond(const Geom& g, int variant, const void* packed, const u
   la.nseg = 1;
   la.cond_pos = t;
   la.seg[0] = FwdSeg{nullptr, packed, x, d_count, out, rows_bound, 0, nullptr};
-  dispatch<false>(g, g.prec, g.h, variant, la, s);
+  if (g.words == 2) dispatch<false, 2>(g, g.prec, g.h, variant, la, s);
+  else dispatch<false, 1>(g, g.prec, g.h, variant, la, s);
 }
 
 void launch_forward_multi(int prec, int h, int variant, FwdLaunch la, hipStream_t s) {
   if (la.nseg < 1 || la.nseg > kMaxSeg) return;
   la.cond_pos = -1;
   Geom unused{};
-  dispatch<true>(unused, prec, h, variant, la, s);
+  dispatch<true, 1>(unused, prec, h, variant, la, s);
 }
 
 }  // namespace nqs

@@ -33,14 +33,34 @@ void launch_fill_u64(void* p, unsigned long long v, long long count, hipStream_t
                      (unsigned long long*)p, v, count);
 }
 
+// A bit string of W 64-bit words (word w = qubits 64w .. 64w+63).
+template <int W>
+struct Bits {
+  uint64_t w[W];
+};
+template <int W>
+__device__ __forceinline__ Bits<W> load_bits(const uint64_t* __restrict__ p, long long i) {
+  Bits<W> b;
+#pragma unroll
+  for (int k = 0; k < W; ++k) b.w[k] = p[i * W + k];
+  return b;
+}
+template <int W>
+__device__ __forceinline__ int popc_and(const Bits<W>& a, const uint64_t* __restrict__ m, long long i) {
+  int c = 0;
+#pragma unroll
+  for (int k = 0; k < W; ++k) c += __popcll(a.w[k] & m[i * W + k]);
+  return c;
+}
+
 // h_g(x) = sum_{k in g} ct_k (-1)^{popcount(x & z_k)}, sequential in canonical
 // order; the sign is applied by flipping the sign bit (exact).
-template <bool IMAG>
-__device__ __forceinline__ void group_h(const HamDev& H, uint64_t x, long long k0, long long k1,
+template <bool IMAG, int W>
+__device__ __forceinline__ void group_h(const HamDev& H, const Bits<W>& x, long long k0, long long k1,
                                         double& re, double& im) {
   double a = 0.0, b = 0.0;
   for (long long k = k0; k < k1; ++k) {
-    const unsigned long long par = (unsigned long long)(__popcll(x & H.tz[k]) & 1) << 63;
+    const unsigned long long par = (unsigned long long)(popc_and<W>(x, H.tz, k) & 1) << 63;
     a += __longlong_as_double(__double_as_longlong(H.tre[k]) ^ par);
     if constexpr (IMAG) b += __longlong_as_double(__double_as_longlong(H.tim[k]) ^ par);
   }
@@ -48,18 +68,27 @@ __device__ __forceinline__ void group_h(const HamDev& H, uint64_t x, long long k
   im = b;
 }
 
-__device__ __forceinline__ bool sector_ok(uint64_t x, uint64_t f) {
-  return 2 * __popcll(x & f & kUp) == __popcll(f & kUp) &&
-         2 * __popcll(x & f & kDn) == __popcll(f & kDn);
+// the flip f keeps the number of up (even qubits) and down (odd qubits) electrons
+template <int W>
+__device__ __forceinline__ bool sector_ok(const Bits<W>& x, const Bits<W>& f) {
+  int xu = 0, fu = 0, xd = 0, fd = 0;
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    xu += __popcll(x.w[k] & f.w[k] & kUp);
+    fu += __popcll(f.w[k] & kUp);
+    xd += __popcll(x.w[k] & f.w[k] & kDn);
+    fd += __popcll(f.w[k] & kDn);
+  }
+  return 2 * xu == fu && 2 * xd == fd;
 }
 
-template <bool IMAG>
+template <bool IMAG, int W>
 __global__ void diag_kernel(HamDev H, const uint64_t* __restrict__ xs, long long S,
                             double* __restrict__ diag) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S) return;
   double re = 0.0, im = 0.0;
-  if (H.gfirst) group_h<IMAG>(H, xs[i], H.goff[0], H.goff[1], re, im);
+  if (H.gfirst) group_h<IMAG, W>(H, load_bits<W>(xs, i), H.goff[0], H.goff[1], re, im);
   diag[2 * i] = re;
   diag[2 * i + 1] = im;
 }
@@ -67,29 +96,34 @@ __global__ void diag_kernel(HamDev H, const uint64_t* __restrict__ xs, long long
 void launch_diag(const HamDev& H, const uint64_t* x, long long S, double* diag, hipStream_t s) {
   if (S <= 0) return;
   unsigned blocks = (unsigned)((S + 255) / 256);
-  if (H.tim) hipLaunchKernelGGL(diag_kernel<true>, dim3(blocks), dim3(256), 0, s, H, x, S, diag);
-  else hipLaunchKernelGGL(diag_kernel<false>, dim3(blocks), dim3(256), 0, s, H, x, S, diag);
+  if (H.words == 2) {
+    if (H.tim) hipLaunchKernelGGL((diag_kernel<true, 2>), dim3(blocks), dim3(256), 0, s, H, x, S, diag);
+    else hipLaunchKernelGGL((diag_kernel<false, 2>), dim3(blocks), dim3(256), 0, s, H, x, S, diag);
+    return;
+  }
+  if (H.tim) hipLaunchKernelGGL((diag_kernel<true, 1>), dim3(blocks), dim3(256), 0, s, H, x, S, diag);
+  else hipLaunchKernelGGL((diag_kernel<false, 1>), dim3(blocks), dim3(256), 0, s, H, x, S, diag);
 }
 
 // One thread per sample, one block row per range of gper groups (excluding
 // the empty flip).  Counts the valid (sample, group) pairs.
-template <bool IMAG>
+template <bool IMAG, int W>
 __global__ void count_kernel(HamDev H, const uint64_t* __restrict__ xs, long long S, int R, int gper,
                              int* __restrict__ cnt) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   const int g0 = H.gfirst + r * gper;
   const int g1 = min(H.G, g0 + gper);
-  const uint64_t x = xs[i < S ? i : 0];
+  const Bits<W> x = load_bits<W>(xs, i < S ? i : 0);
   int c = 0;
   for (int g = g0; g < g1; ++g) {
-    const uint64_t f = H.gx[g];
+    const Bits<W> f = load_bits<W>(H.gx, g);
     bool ok;
     if (H.filter) {
-      ok = sector_ok(x, f);
+      ok = sector_ok<W>(x, f);
     } else {
       double re, im;
-      group_h<IMAG>(H, x, H.goff[g], H.goff[g + 1], re, im);
+      group_h<IMAG, W>(H, x, H.goff[g], H.goff[g + 1], re, im);
       ok = (re != 0.0) || (im != 0.0);
     }
     c += ok ? 1 : 0;
@@ -101,8 +135,13 @@ void launch_count(const HamDev& H, const uint64_t* x, long long S, int R, int gp
                   hipStream_t s) {
   if (S <= 0) return;
   dim3 grid((unsigned)((S + 255) / 256), (unsigned)R);
-  if (H.tim) hipLaunchKernelGGL(count_kernel<true>, grid, dim3(256), 0, s, H, x, S, R, gper, cnt);
-  else hipLaunchKernelGGL(count_kernel<false>, grid, dim3(256), 0, s, H, x, S, R, gper, cnt);
+  if (H.words == 2) {
+    if (H.tim) hipLaunchKernelGGL((count_kernel<true, 2>), grid, dim3(256), 0, s, H, x, S, R, gper, cnt);
+    else hipLaunchKernelGGL((count_kernel<false, 2>), grid, dim3(256), 0, s, H, x, S, R, gper, cnt);
+    return;
+  }
+  if (H.tim) hipLaunchKernelGGL((count_kernel<true, 1>), grid, dim3(256), 0, s, H, x, S, R, gper, cnt);
+  else hipLaunchKernelGGL((count_kernel<false, 1>), grid, dim3(256), 0, s, H, x, S, R, gper, cnt);
 }
 
 // Exclusive scan of n counts into off[0..n] (off[n] = total) in three
@@ -224,7 +263,7 @@ void launch_scan(const int* cnt, long long n, long long* off, long long* tmp, hi
                      (const long long*)tmp, off);
 }
 
-template <bool IMAG>
+template <bool IMAG, int W>
 __global__ void write_kernel(HamDev H, const uint64_t* __restrict__ xs, long long S, int R, int gper,
                              const long long* __restrict__ off, long long cap,
                              uint64_t* __restrict__ xe, double* __restrict__ he,
@@ -234,17 +273,18 @@ __global__ void write_kernel(HamDev H, const uint64_t* __restrict__ xs, long lon
   const int g0 = H.gfirst + r * gper;
   const int g1 = min(H.G, g0 + gper);
   const bool live = i < S;
-  const uint64_t x = xs[live ? i : 0];
+  const Bits<W> x = load_bits<W>(xs, live ? i : 0);
   long long pos = live ? off[i * R + r] : 0;
   bool over = false;
   for (int g = g0; g < g1; ++g) {
-    const uint64_t f = H.gx[g];
+    const Bits<W> f = load_bits<W>(H.gx, g);
     double re, im;
-    group_h<IMAG>(H, x, H.goff[g], H.goff[g + 1], re, im);
-    const bool ok = H.filter ? sector_ok(x, f) : ((re != 0.0) || (im != 0.0));
+    group_h<IMAG, W>(H, x, H.goff[g], H.goff[g + 1], re, im);
+    const bool ok = H.filter ? sector_ok<W>(x, f) : ((re != 0.0) || (im != 0.0));
     if (live && ok) {
       if (pos < cap) {
-        xe[pos] = x ^ f;
+#pragma unroll
+        for (int k = 0; k < W; ++k) xe[pos * W + k] = x.w[k] ^ f.w[k];
         he[pos * hstride] = re;
         if (hstride == 2) he[pos * 2 + 1] = im;
         if (esample) esample[pos] = (int)i;
@@ -257,17 +297,25 @@ __global__ void write_kernel(HamDev H, const uint64_t* __restrict__ xs, long lon
   if (over) atomicOr(err, kErrEntryOverflow);
 }
 
+template <int W>
+static void launch_write_w(const HamDev& H, const uint64_t* x, long long S, int R, int gper,
+                           const long long* off, long long cap, uint64_t* xe, double* he, int* esample,
+                           int hstride, unsigned* err, hipStream_t s) {
+  dim3 grid((unsigned)((S + 255) / 256), (unsigned)R);
+  if (H.tim)
+    hipLaunchKernelGGL((write_kernel<true, W>), grid, dim3(256), 0, s, H, x, S, R, gper, off, cap, xe, he,
+                       esample, hstride, err);
+  else
+    hipLaunchKernelGGL((write_kernel<false, W>), grid, dim3(256), 0, s, H, x, S, R, gper, off, cap, xe,
+                       he, esample, hstride, err);
+}
+
 void launch_write(const HamDev& H, const uint64_t* x, long long S, int R, int gper,
                   const long long* off, long long cap, uint64_t* xe, double* he, int* esample,
                   int hstride, unsigned* err, hipStream_t s) {
   if (S <= 0) return;
-  dim3 grid((unsigned)((S + 255) / 256), (unsigned)R);
-  if (H.tim)
-    hipLaunchKernelGGL(write_kernel<true>, grid, dim3(256), 0, s, H, x, S, R, gper, off, cap, xe, he,
-                       esample, hstride, err);
-  else
-    hipLaunchKernelGGL(write_kernel<false>, grid, dim3(256), 0, s, H, x, S, R, gper, off, cap, xe,
-                       he, esample, hstride, err);
+  if (H.words == 2) launch_write_w<2>(H, x, S, R, gper, off, cap, xe, he, esample, hstride, err, s);
+  else launch_write_w<1>(H, x, S, R, gper, off, cap, xe, he, esample, hstride, err, s);
 }
 
 __global__ void copy_i64_kernel(const long long* src, long long* dst) { *dst = *src; }

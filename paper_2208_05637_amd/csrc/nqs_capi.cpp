@@ -5,6 +5,7 @@
 #include "nqs_internal.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -67,11 +68,12 @@ struct nqs_ctx {
 
 struct nqs_ham {
   int n = 0;
+  int words = 1;           // 64-bit words per mask
   bool has_imag = false;
   uint32_t flags = 0;
-  std::vector<uint64_t> gx;
+  std::vector<uint64_t> gx;   // [G][words]
   std::vector<long long> goff;
-  std::vector<uint64_t> tz;
+  std::vector<uint64_t> tz;   // [K][words]
   std::vector<double> tre, tim;
   // census of non-empty flips by (up bits, down bits) for the entry bound
   std::map<std::pair<int, int>, long long> census;
@@ -146,7 +148,7 @@ static WsLayout layout(const nqs_plan* p, int64_t B) {
   L.stmp = take(((size_t)scan_tiles(p->SRcap) + 1) * 8);
   L.rpart = take((size_t)reduce_partials_elems(std::max<int64_t>(p->S0, 1)) * 8);
   L.diag = take((size_t)p->S0 * 16);
-  L.xe = take((size_t)p->EC * 8);
+  L.xe = take((size_t)p->EC * 8 * p->g.words);
   L.he = take((size_t)p->EC * 8 * hs);
   L.lpe = take((size_t)p->EC * 16);
   if (p->dedup_cap) {
@@ -164,6 +166,14 @@ static WsLayout layout(const nqs_plan* p, int64_t B) {
   return L;
 }
 
+// group 0 is the empty flip
+static bool ham_has_diag(const nqs_ham* h) {
+  if (h->gx.empty()) return false;
+  for (int w = 0; w < h->words; ++w)
+    if (h->gx[w] != 0) return false;
+  return true;
+}
+
 static HamDev ham_dev(const nqs_plan* p) {
   const nqs_ham* h = p->ham;
   HamDev H{};
@@ -172,9 +182,10 @@ static HamDev ham_dev(const nqs_plan* p) {
   H.tz = (const uint64_t*)(h->d_base + h->o_tz);
   H.tre = (const double*)(h->d_base + h->o_tre);
   H.tim = h->has_imag ? (const double*)(h->d_base + h->o_tim) : nullptr;
-  H.G = (int)h->gx.size();
-  H.gfirst = (!h->gx.empty() && h->gx[0] == 0) ? 1 : 0;
+  H.G = (int)(h->gx.size() / h->words);
+  H.gfirst = ham_has_diag(h) ? 1 : 0;
   H.filter = (h->flags & NQS_H_CONSERVES_SPIN_SECTORS) ? 1 : 0;
+  H.words = h->words;
   return H;
 }
 
@@ -235,32 +246,52 @@ void nqs_ctx_destroy(nqs_ctx* ctx) { delete ctx; }
 nqs_status nqs_ham_create(const nqs_pauli_terms* t, nqs_ham** out) {
   if (!t || !out) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
   *out = nullptr;
-  if (t->n_qubits < 1 || t->n_qubits > 64)
-    return fail(NQS_ERR_UNSUPPORTED, "n_qubits = %d outside 1..64", t->n_qubits);
+  if (t->n_qubits < 1 || t->n_qubits > kMaxQubits)
+    return fail(NQS_ERR_UNSUPPORTED, "n_qubits = %d outside 1..%d", t->n_qubits, kMaxQubits);
   if (t->n_terms < 0) return fail(NQS_ERR_INVALID_ARGUMENT, "n_terms < 0");
   if (t->n_terms > 0 && (!t->x_mask || !t->z_mask || !t->coeff))
     return fail(NQS_ERR_INVALID_ARGUMENT, "NULL term arrays");
   if (!(t->drop_tol >= 0.0)) return fail(NQS_ERR_INVALID_ARGUMENT, "drop_tol must be >= 0");
-  const uint64_t valid = t->n_qubits == 64 ? ~0ull : ((1ull << t->n_qubits) - 1);
+  const int W = (t->n_qubits + 63) / 64;
+  // valid bits of each word
+  uint64_t valid[2] = {0, 0};
+  for (int w = 0; w < W; ++w) {
+    const int bits = std::min(64, t->n_qubits - 64 * w);
+    valid[w] = bits == 64 ? ~0ull : ((1ull << bits) - 1);
+  }
   for (int64_t k = 0; k < t->n_terms; ++k) {
-    if ((t->x_mask[k] | t->z_mask[k]) & ~valid)
-      return fail(NQS_ERR_INVALID_ARGUMENT, "term %lld acts on a qubit >= n_qubits", (long long)k);
+    for (int w = 0; w < W; ++w)
+      if ((t->x_mask[k * W + w] | t->z_mask[k * W + w]) & ~valid[w])
+        return fail(NQS_ERR_INVALID_ARGUMENT, "term %lld acts on a qubit >= n_qubits", (long long)k);
     if (!std::isfinite(t->coeff[k])) return fail(NQS_ERR_INVALID_ARGUMENT, "term %lld: non-finite coefficient", (long long)k);
     if (t->coeff_imag && t->coeff_imag[k] != 0.0)
       return fail(NQS_ERR_NOT_HERMITIAN, "term %lld has imaginary coefficient %g", (long long)k, t->coeff_imag[k]);
   }
+  // a string as (x high, x low, z high, z low): the tuple order is the order
+  // of (x, z) as unsigned integers
+  using Key = std::array<uint64_t, 4>;
+  auto key_of = [&](int64_t k) {
+    Key key{0, 0, 0, 0};
+    for (int w = 0; w < W; ++w) {
+      key[1 - w] = t->x_mask[k * W + w];
+      key[3 - w] = t->z_mask[k * W + w];
+    }
+    return key;
+  };
   // 1. merge identical strings, sequential FP64 sums in input order
   struct KeyHash {
-    size_t operator()(const std::pair<uint64_t, uint64_t>& k) const {
-      return std::hash<uint64_t>()(k.first * 0x9E3779B97F4A7C15ull ^ k.second);
+    size_t operator()(const Key& k) const {
+      uint64_t v = 0;
+      for (uint64_t e : k) v = (v ^ e) * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+      return std::hash<uint64_t>()(v);
     }
   };
-  std::unordered_map<std::pair<uint64_t, uint64_t>, size_t, KeyHash> idx;
+  std::unordered_map<Key, size_t, KeyHash> idx;
   idx.reserve((size_t)t->n_terms * 2 + 1);
-  std::vector<std::pair<uint64_t, uint64_t>> keys;
+  std::vector<Key> keys;
   std::vector<double> vals;
   for (int64_t k = 0; k < t->n_terms; ++k) {
-    auto key = std::make_pair(t->x_mask[k], t->z_mask[k]);
+    const Key key = key_of(k);
     auto it = idx.find(key);
     if (it == idx.end()) {
       idx.emplace(key, keys.size());
@@ -277,39 +308,47 @@ nqs_status nqs_ham_create(const nqs_pauli_terms* t, nqs_ham** out) {
   std::sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return keys[a] < keys[b]; });
   nqs_ham* h = new nqs_ham;
   h->n = t->n_qubits;
+  h->words = W;
   h->flags = t->flags;
   const size_t K = ord.size();
-  h->tz.resize(K);
+  h->tz.resize(K * W);
   h->tre.resize(K);
   h->tim.resize(K);
   for (size_t j = 0; j < K; ++j) {
-    const auto& key = keys[ord[j]];
+    const Key& key = keys[ord[j]];
     const double c = vals[ord[j]];
-    h->tz[j] = key.second;
+    for (int w = 0; w < W; ++w) h->tz[j * W + w] = key[3 - w];
     // 4. fold (-i)^r, r = number of Y factors
-    switch (__builtin_popcountll(key.first & key.second) & 3) {
+    const int r = __builtin_popcountll(key[0] & key[2]) + __builtin_popcountll(key[1] & key[3]);
+    switch (r & 3) {
       case 0: h->tre[j] = c; h->tim[j] = 0.0; break;
       case 1: h->tre[j] = 0.0; h->tim[j] = -c; h->has_imag = true; break;
       case 2: h->tre[j] = -c; h->tim[j] = 0.0; break;
       default: h->tre[j] = 0.0; h->tim[j] = c; h->has_imag = true; break;
     }
-    if (j == 0 || key.first != keys[ord[j - 1]].first) {
-      h->gx.push_back(key.first);
+    if (j == 0 || key[0] != keys[ord[j - 1]][0] || key[1] != keys[ord[j - 1]][1]) {
+      for (int w = 0; w < W; ++w) h->gx.push_back(key[1 - w]);
       h->goff.push_back((long long)j);
     }
   }
   h->goff.push_back((long long)K);
-  for (size_t gi = 0; gi < h->gx.size(); ++gi) {
-    const uint64_t f = h->gx[gi];
-    if (f == 0) continue;
-    h->census[{__builtin_popcountll(f & kUpMask), __builtin_popcountll(f & kDnMask)}] += 1;
+  const size_t G = h->gx.size() / W;
+  for (size_t gi = 0; gi < G; ++gi) {
+    int up = 0, dn = 0;
+    for (int w = 0; w < W; ++w) {
+      // 64 is even, so every word has the same spin pattern
+      up += __builtin_popcountll(h->gx[gi * W + w] & kUpMask);
+      dn += __builtin_popcountll(h->gx[gi * W + w] & kDnMask);
+    }
+    if (up + dn == 0) continue;
+    h->census[{up, dn}] += 1;
   }
   // device layout
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
   h->o_gx = take(h->gx.size() * 8);
   h->o_goff = take(h->goff.size() * 8);
-  h->o_tz = take(K * 8);
+  h->o_tz = take(K * W * 8);
   h->o_tre = take(K * 8);
   h->o_tim = h->has_imag ? take(K * 8) : 0;
   h->bytes = std::max<size_t>(o, 256);
@@ -319,8 +358,8 @@ nqs_status nqs_ham_create(const nqs_pauli_terms* t, nqs_ham** out) {
 
 nqs_status nqs_ham_info(const nqs_ham* h, int64_t* K, int64_t* G, size_t* bytes, int* has_imag, int* n) {
   if (!h) return fail(NQS_ERR_INVALID_ARGUMENT, "ham is NULL");
-  if (K) *K = (int64_t)h->tz.size();
-  if (G) *G = (int64_t)h->gx.size();
+  if (K) *K = (int64_t)h->tre.size();
+  if (G) *G = (int64_t)(h->gx.size() / h->words);
   if (bytes) *bytes = h->bytes;
   if (has_imag) *has_imag = h->has_imag ? 1 : 0;
   if (n) *n = h->n;
@@ -362,12 +401,13 @@ void nqs_ham_destroy(nqs_ham* h) { delete h; }
 static nqs_status build_geom(const nqs_net_desc* nd, Geom& g) {
   if (!nd) return fail(NQS_ERR_INVALID_ARGUMENT, "net is NULL");
   const int n = nd->n_qubits, L = nd->n_layers, h = nd->width;
-  if (n < 2 || n > 64) return fail(NQS_ERR_UNSUPPORTED, "n_qubits = %d outside 2..64", n);
+  if (n < 2 || n > kMaxQubits) return fail(NQS_ERR_UNSUPPORTED, "n_qubits = %d outside 2..%d", n, kMaxQubits);
   if (L < 1 || L > kMaxLayers) return fail(NQS_ERR_UNSUPPORTED, "n_layers = %d outside 1..%d", L, kMaxLayers);
   if (nd->precision < NQS_FP64 || nd->precision > NQS_BF16W)
     return fail(NQS_ERR_INVALID_ARGUMENT, "unknown precision %d", nd->precision);
-  if (!forward_supported(nd->precision, h))
-    return fail(NQS_ERR_UNSUPPORTED, "width %d not supported for precision %d", h, nd->precision);
+  const int words = n > 64 ? 2 : 1;
+  if (!forward_supported(nd->precision, h, words))
+    return fail(NQS_ERR_UNSUPPORTED, "width %d not supported for precision %d at %d qubits", h, nd->precision, n);
   if (nd->phase_mode != 0 && nd->phase_mode != 1)
     return fail(NQS_ERR_INVALID_ARGUMENT, "phase_mode %d is neither 0 nor 1", nd->phase_mode);
   if (nd->phase_mode == 1 && n < 3)
@@ -386,10 +426,12 @@ static nqs_status build_geom(const nqs_net_desc* nd, Geom& g) {
       return fail(NQS_ERR_INVALID_ARGUMENT, "order is not a permutation of the qubits");
   }
   bool ident = true, rev = true;
+  g.words = words;
   for (int t = 0; t < n; ++t) {
     g.order[t] = (int8_t)order[t];
     g.pos[order[t]] = (int8_t)t;
-    g.spin_pos[order[t] & 1] |= 1ull << t;
+    if (t < 64) g.spin_pos[order[t] & 1] |= 1ull << t;
+    else g.spin_pos_hi[order[t] & 1] |= 1ull << (t - 64);
     ident = ident && order[t] == t;
     rev = rev && order[t] == n - 1 - t;
   }
@@ -517,8 +559,8 @@ nqs_status nqs_plan_create(nqs_ctx* ctx, const nqs_ham* ham, const nqs_net_desc*
   p->g = g;
   p->max_batch = max_batch;
   // per-sample entry bound
-  const int G = (int)ham->gx.size();
-  const int gfirst = (G > 0 && ham->gx[0] == 0) ? 1 : 0;
+  const int G = (int)(ham->gx.size() / ham->words);
+  const int gfirst = ham_has_diag(ham) ? 1 : 0;
   if (ham->flags & NQS_H_CONSERVES_SPIN_SECTORS) {
     const int Nu = (g.n + 1) / 2, Nd = g.n / 2;
     double bound = 0.0;
@@ -559,7 +601,8 @@ nqs_status nqs_plan_create(nqs_ctx* ctx, const nqs_ham* ham, const nqs_net_desc*
     grid_for(half, ngroups, r2, gp2);
     p->SRcap = std::max<int64_t>(p->S0 * p->R, half * r2);
   }
-  // all-ones is the empty-slot marker of the hash table, so no dedup at 64 qubits
+  // the hash table keys one-word strings and all-ones marks an empty slot, so
+  // there is no dedup at 64 qubits or more
   p->dedup_cap = (flags & (NQS_PLAN_DEDUP_ON | NQS_PLAN_DEDUP_AUTO)) != 0 && g.n < 64;
   p->dedup = p->dedup_cap;
   p->dedup_auto = (flags & NQS_PLAN_DEDUP_AUTO) != 0 && p->dedup_cap;
@@ -750,7 +793,7 @@ static ChunkFwd enum_chunk(nqs_plan* p, const uint64_t* x, int64_t c0, int64_t S
   hipStream_t s = p->ctx->stream;
   const HamDev H = ham_dev(p);
   const int hs = p->ham->has_imag ? 2 : 1;
-  const uint64_t* xc = x + c0;
+  const uint64_t* xc = x + c0 * p->g.words;
   unsigned* err = at<unsigned>(ws, L.err);
   int* cnt = at<int>(ws, L.cnt);
   long long* off = at<long long>(ws, L.off);
@@ -807,7 +850,7 @@ static void energy_and_grad(nqs_plan* p, const float* params, const uint64_t* x,
   void* scratch = at<void>(ws, L.bscratch);
   for (int64_t c0 = 0; c0 < B; c0 += p->Sb) {
     const int64_t Sc = std::min<int64_t>(p->Sb, B - c0);
-    launch_backward(p->g, wm, x + c0, Sc, el + 2 * c0, w ? w + c0 : nullptr, energy, scratch, grad, s);
+    launch_backward(p->g, wm, x + c0 * p->g.words, Sc, el + 2 * c0, w ? w + c0 : nullptr, energy, scratch, grad, s);
   }
 }
 
@@ -879,6 +922,8 @@ static nqs_status multi_layout(int n_inst, const nqs_instance* inst, std::vector
     const nqs_instance& I = inst[i];
     if (!I.plan) return fail(NQS_ERR_INVALID_ARGUMENT, "instance %d has no plan", i);
     if (I.plan->ctx != inst[0].plan->ctx) return fail(NQS_ERR_INVALID_ARGUMENT, "instances on different contexts");
+    if (I.plan->g.words != 1)
+      return fail(NQS_ERR_UNSUPPORTED, "instance %d: multi-instance launches take at most 64 qubits", i);
     if (I.B < 1 || I.B > I.plan->max_batch)
       return fail(NQS_ERR_INVALID_ARGUMENT, "instance %d: batch %lld outside 1..%lld", i, (long long)I.B,
                   (long long)I.plan->max_batch);
@@ -1005,13 +1050,13 @@ std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune_cache;
 
 TuneKey tune_key(const nqs_plan* p) {
-  return TuneKey{p->g.n, p->g.L, p->g.h, p->g.prec, (int64_t)p->ham->tz.size(), (int64_t)p->ham->gx.size(),
+  return TuneKey{p->g.n, p->g.L, p->g.h, p->g.prec, (int64_t)p->ham->tre.size(), (int64_t)(p->ham->gx.size() / p->ham->words),
                  p->Emax, p->S0, p->dedup_auto ? 1 : 0, p->ctx->device, p->g.phase_mode};
 }
 
 void set_chunk(nqs_plan* p, int64_t S) {
-  const int G = (int)p->ham->gx.size();
-  const int gfirst = (G > 0 && p->ham->gx[0] == 0) ? 1 : 0;
+  const int G = (int)(p->ham->gx.size() / p->ham->words);
+  const int gfirst = ham_has_diag(p->ham) ? 1 : 0;
   p->S = S;
   grid_for(S, G - gfirst, p->R, p->gper);
 }
@@ -1164,6 +1209,7 @@ SampleLayout sample_layout(const nqs_plan* p, int64_t U) {
 
 nqs_status nqs_sample_workspace_size(const nqs_plan* p, int64_t max_unique, size_t* bytes) {
   if (!p || !bytes) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (p->g.words != 1) return fail(NQS_ERR_UNSUPPORTED, "the sampler takes at most 64 qubits");
   if (max_unique < 1 || max_unique > (1LL << 30))
     return fail(NQS_ERR_INVALID_ARGUMENT, "max_unique %lld outside 1..2^30", (long long)max_unique);
   *bytes = sample_layout(p, max_unique).total;
@@ -1173,6 +1219,7 @@ nqs_status nqs_sample_workspace_size(const nqs_plan* p, int64_t max_unique, size
 nqs_status nqs_sample(nqs_plan* p, const float* params, int64_t n_draws, uint64_t seed, int64_t max_unique,
                       uint64_t* d_x, double* d_w, int64_t* d_n_unique, void* ws, size_t ws_bytes) {
   if (!p || !params || !d_x || !d_w || !d_n_unique) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (p->g.words != 1) return fail(NQS_ERR_UNSUPPORTED, "the sampler takes at most 64 qubits");
   if (n_draws < 1 || n_draws > (1LL << 62)) return fail(NQS_ERR_INVALID_ARGUMENT, "n_draws outside 1..2^62");
   if (max_unique < 1 || max_unique > (1LL << 30))
     return fail(NQS_ERR_INVALID_ARGUMENT, "max_unique %lld outside 1..2^30", (long long)max_unique);

@@ -8,8 +8,9 @@
 namespace nqs {
 
 constexpr int kMaxLayers = 16;
+constexpr int kMaxQubits = 128;   // bit strings of up to two 64-bit words
 constexpr int kMaxNB = 64;        // n-blocks of the fused kernel (h / TB)
-constexpr int kMaxNHB = 8;        // head n-blocks ((n + 4) / TB rounded up)
+constexpr int kMaxNHB = 9;        // head n-blocks ((n + 4) / TB rounded up)
 constexpr int kMaxSeg = 8;        // segments of one multi-segment forward launch
 
 enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3, P_BF16W = 4 };
@@ -35,9 +36,11 @@ struct Geom {
                             // and phi), 1 the modulus network of phase_mode 1 (log|psi| only),
                             // 2 the phase network of phase_mode 1 (phi only; dense layers, units
                             // in their own order, inputs = the first n-2 positions)
-  uint64_t spin_pos[2];     // positions whose qubit has spin 0 (even) / 1 (odd)
-  int8_t order[64];         // position -> qubit
-  int8_t pos[64];           // qubit -> position
+  int words;                // 64-bit words per bit string: 1 (n <= 64) or 2
+  uint64_t spin_pos[2];     // positions 0..63 whose qubit has spin 0 (even) / 1 (odd)
+  uint64_t spin_pos_hi[2];  // the same for positions 64..127
+  int8_t order[kMaxQubits]; // position -> qubit
+  int8_t pos[kMaxQubits];   // qubit -> position
   int ks1[kMaxNB];  int off1[kMaxNB + 1];
   int ksh[kMaxNB];  int offh[kMaxNB + 1];
   int kso[kMaxNHB]; int offo[kMaxNHB + 1];
@@ -74,7 +77,8 @@ __host__ __device__ inline int orig_of_sorted(const Geom& g, int u) {
   return c + (u - prefix_of_class(g, c)) * (g.n - 1);
 }
 
-// Tensor of the Hamiltonian on the device.
+// Tensor of the Hamiltonian on the device.  Masks and bit strings take
+// `words` 64-bit words each (word w = qubits 64w .. 64w+63).
 struct HamDev {
   const uint64_t* gx;
   const long long* goff;
@@ -84,6 +88,7 @@ struct HamDev {
   int G;
   int gfirst;          // 1 if group 0 is the empty flip
   int filter;          // spin-sector filter on
+  int words;           // 1 or 2
 };
 
 // ---- launchers (kernels_*.hip) -------------------------------------------
@@ -197,6 +202,7 @@ void launch_adam(long long n, float* p, const double* g, double* m, double* v, c
                  hipStream_t s);
 
 int forward_rows_per_block(int prec, int h);
-bool forward_supported(int prec, int h);
+// (prec, width) has a fused forward for bit strings of `words` 64-bit words
+bool forward_supported(int prec, int h, int words);
 
 }  // namespace nqs

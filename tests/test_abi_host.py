@@ -59,6 +59,50 @@ def test_canonical_tensor_bit_exact_vs_oracle(lib, N):
     assert np.array_equal(ex["tim"], ref["ct"].imag)
 
 
+def _words_to_ints(a):
+    return [int(r[0]) | (int(r[1]) << 64) for r in np.asarray(a).tolist()]
+
+
+@pytest.mark.parametrize("cutoff", [0.05])
+def test_two_word_canonical_tensor_bit_exact_vs_oracle(lib, cutoff):
+    """76 qubits: masks of two words, merged, folded, sorted as 128-bit
+    unsigned integers and grouped exactly as the oracle does with Python
+    integers."""
+    from gen.inputs import hamiltonian
+    t = hamiltonian(38, 0, cutoff=cutoff)
+    rng = np.random.default_rng(76)
+    perm = rng.permutation(len(t))
+    x = np.concatenate([t.x_mask[perm], t.x_mask[perm[: len(perm) // 3]]])
+    z = np.concatenate([t.z_mask[perm], t.z_mask[perm[: len(perm) // 3]]])
+    c = np.concatenate([t.coeff[perm], 0.25 * t.coeff[perm[: len(perm) // 3]]])
+    ref = pauli.canonical_terms(x, z, c)
+    assert ref["x"].dtype == object
+    gx, goff = pauli.groups(ref)
+    H = _ham(76, x, z, c)
+    ex = H.export()
+    assert H.K == len(ref["x"]) and H.G == len(gx)
+    assert ex["gx"].shape == (H.G, 2) and ex["tz"].shape == (H.K, 2)
+    assert _words_to_ints(ex["gx"]) == [int(v) for v in gx]
+    np.testing.assert_array_equal(ex["goff"], goff)
+    assert _words_to_ints(ex["tz"]) == [int(v) for v in ref["z"]]
+    assert np.array_equal(ex["tre"], ref["ct"].real)
+    assert np.array_equal(ex["tim"], ref["ct"].imag)
+    assert any(int(v) >> 64 for v in gx) and H.G > 1000
+
+
+def test_two_word_odd_y_fold(lib):
+    """A Y on qubit 100 and one on qubit 3: (-i)^2 = -1; a lone Y on qubit 70: -i."""
+    x = np.array([[1 << 3, 1 << 36], [0, 1 << 6]], dtype=np.uint64)
+    z = np.array([[1 << 3, 1 << 36], [0, 1 << 6]], dtype=np.uint64)
+    c = np.array([0.5, 0.25])
+    H = _ham(101, x, z, c)
+    ref = pauli.canonical_terms(x, z, c)
+    ex = H.export()
+    assert H.has_imag
+    assert np.array_equal(ex["tre"], ref["ct"].real) and np.array_equal(ex["tim"], ref["ct"].imag)
+    assert sorted(ref["ct"].tolist(), key=abs) == [-0.25j, -0.5 + 0j]
+
+
 def test_odd_y_terms_fold_into_imaginary_plane(lib):
     x = np.array([0b10, 0b11, 0b1], dtype=np.uint64)
     z = np.array([0b10, 0b01, 0b1], dtype=np.uint64)
@@ -77,8 +121,13 @@ def test_error_statuses(lib):
         _ham(3, [1], [0], [1.0], ci=[1e-3])
     assert e.value.status == 3            # NQS_ERR_NOT_HERMITIAN
     with pytest.raises(NQSError) as e:
-        _ham(65, [1], [0], [1.0])
+        _ham(129, np.array([[1, 0, 0]], dtype=np.uint64), np.zeros((1, 3), dtype=np.uint64), [1.0])
     assert e.value.status == 2            # NQS_ERR_UNSUPPORTED
+    with pytest.raises(NQSError) as e:   # acts on qubit 70 of a 70-qubit system
+        _ham(70, np.array([[0, 1 << 6]], dtype=np.uint64), np.zeros((1, 2), dtype=np.uint64), [1.0])
+    assert e.value.status == 1
+    with pytest.raises(ValueError):       # 70 qubits take two words per mask
+        _ham(70, [1], [0], [1.0])
     with pytest.raises(NQSError) as e:
         _ham(3, [8], [0], [1.0])          # acts on qubit 3 of a 3-qubit system
     assert e.value.status == 1
@@ -107,6 +156,22 @@ def test_unsupported_width_rejected(lib):
     from paper_2208_05637_amd import param_count, NQSError
     with pytest.raises(NQSError):
         param_count(12, 1, 100, "bf16")
+    # above 64 qubits the 256-row tiles of BF16 at width 256 and FP32 at width
+    # 128 leave no LDS for the head of 132 outputs
+    for prec, h in (("bf16", 256), ("fp32", 128)):
+        assert param_count(64, 1, h, prec) > 0
+        with pytest.raises(NQSError):
+            param_count(65, 1, h, prec)
+    with pytest.raises(NQSError):
+        param_count(129, 1, 64, "fp64")
+
+
+@pytest.mark.parametrize("n,L,h,prec,mode", [(76, 3, 512, "bf16w", 0), (65, 1, 64, "fp64", 0),
+                                             (128, 2, 256, "fp32", 1), (100, 2, 512, "bf16", 0)])
+def test_param_layout_above_64_qubits(lib, n, L, h, prec, mode):
+    from paper_2208_05637_amd import param_count
+    want = made.n_params(made.Net(n=n, n_layers=L, width=h, phase_mode=mode))
+    assert param_count(n, L, h, prec, phase_mode=mode) == want == gen_param_count(n, L, h, mode)
 
 
 def test_adam_rejects_arguments_on_the_host(lib):
