@@ -21,7 +21,9 @@ network: the timed path again, the split-BF16, plain BF16 and FP32 GPU paths
 (throughput + energy) and the FP64 GPU path (the energy reference of the
 prefix); the timed path with the paper's separate phase sub-model and with
 the forward and a random sampling order; one Adam step (Sec. 6) on the
-network's parameters; and the FP64 CPU
+network's parameters; the timed network kind and shape at 76 qubits (bit
+strings of two words; a sparser synthetic molecule with the paper's term
+count for that size, uniform sector samples); and the FP64 CPU
 oracle on --cpu-samples samples (CPU baseline, and the per-sample check of
 every GPU path).
 """
@@ -76,6 +78,48 @@ def measured_traffic(workload, prec, waves):
         return None
 
 
+# Bit strings of two words: 76 qubits, the size of the paper's largest system
+# (38 spatial orbitals, 19 + 19 electrons).  The integrals' two-electron part
+# is cut below 2.5e-5, which leaves about as many Pauli strings as the
+# paper's 76-qubit molecule (1,625,991).
+WIDE_N_ORB, WIDE_CUTOFF = 38, 2.5e-5
+
+
+def wide_76(nqs, ctx, cfg, prec, waves, count):
+    """Local-energy throughput of the timed network kind and shape at 76 qubits
+    (uniform sector samples: the sampler takes at most 64 qubits)."""
+    import numpy as np
+    import torch
+    from gen.inputs import hamiltonian, init_params, sector_samples
+    t = time.time()
+    terms = hamiltonian(WIDE_N_ORB, 0, cutoff=WIDE_CUTOFF)
+    log(f"76-qubit Hamiltonian: {len(terms)} strings in {time.time() - t:.1f}s")
+    n, nu = 2 * WIDE_N_ORB, WIDE_N_ORB // 2
+    H = nqs.Hamiltonian.from_terms(terms).upload(ctx)
+    params = torch.from_numpy(init_params(n, cfg["L"], cfg["h"], seed=1, dtype=cfg["params"])).to(ctx.device)
+    xs = sector_samples(n, nu, nu, count, seed=2)
+    pl = nqs.Plan(ctx, H, cfg["L"], cfg["h"], nu, nu, prec, max_batch=count)
+    pl.configure(waves_per_block=waves)
+    nqs.local_energy(pl, params, xs)      # warm
+    torch.cuda.synchronize()
+    pl.profile(True)
+    el = nqs.local_energy(pl, params, xs)
+    pr = pl.profile_read()
+    pl.profile(False)
+    status = nqs.device_status(pl)
+    el = el.cpu().numpy()
+    res = {"n_qubits": n, "terms": H.K, "groups": H.G, "samples": count, "samples_kind": "uniform in the sector",
+           "entries_per_sample": pl.entries_per_sample, "chunk_samples": pl.chunk_samples,
+           "samples_terms_per_s": count * H.K / (pr["eloc_ms"] / 1e3),
+           "connected_configs_per_s": pr["forward_rows"] / (pr["eloc_ms"] / 1e3),
+           "forward_tflops": pr["forward_flops"] / (pr["forward_ms"] / 1e3) / 1e12,
+           "forward_ms_per_launch": pr["forward_ms"] / max(pr["forward_launches"], 1),
+           "energy_mean": float(np.mean(el[:, 0])), "device_status": status}
+    log(f"76 qubits ({H.K} strings, {count} samples): {res['samples_terms_per_s']:.3e} samples*terms/s, "
+        f"{res['forward_tflops']:.1f} TFLOP/s")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +132,8 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-side", action="store_true", help="skip the prefix paths")
+    ap.add_argument("--wide-samples", type=int, default=512,
+                    help="samples of the 76-qubit side workload (0 skips it)")
     ap.add_argument("--chunk", type=int, default=0, help="samples per chunk (0 = plan default)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (plan defaults)")
     ap.add_argument("--dedup", default=None, choices=["on", "off", "auto"],
@@ -407,6 +453,9 @@ def main():
                 f"{var[name]['forward_tflops']:.1f} TFLOP/s, E = {ev:.8f}")
             del pl
         out["variants_on_prefix"] = {"prefix_samples": P, "precision": prec, **var}
+
+        if args.wide_samples > 0:
+            out["wide_76_qubits"] = wide_76(nqs, ctx, cfg, prec, kinfo["waves_per_block"], args.wide_samples)
 
     if not args.no_cpu:
         from threadpoolctl import threadpool_info
