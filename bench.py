@@ -21,7 +21,9 @@ network: the timed path again, the split-BF16, plain BF16 and FP32 GPU paths
 (throughput + energy) and the FP64 GPU path (the energy reference of the
 prefix); the timed path with the paper's separate phase sub-model and with
 the forward and a random sampling order; one Adam step (Sec. 6) on the
-network's parameters; the timed network kind and shape at 76 qubits (bit
+network's parameters; the matrix elements from structured per-group tables
+against the term list (enumeration of the first chunk, local energy of the
+prefix); the timed network kind and shape at 76 qubits (bit
 strings of two words; a sparser synthetic molecule with the paper's term
 count for that size, uniform sector samples); and the FP64 CPU
 oracle on --cpu-samples samples (CPU baseline, and the per-sample check of
@@ -117,6 +119,55 @@ def wide_76(nqs, ctx, cfg, prec, waves, count):
            "energy_mean": float(np.mean(el[:, 0])), "device_status": status}
     log(f"76 qubits ({H.K} strings, {count} samples): {res['samples_terms_per_s']:.3e} samples*terms/s, "
         f"{res['forward_tflops']:.1f} TFLOP/s")
+    return res
+
+
+def tables_side(nqs, ctx, terms, cfg, prec, waves, dedup, x, chunk, xp, params, ref):
+    """Matrix elements from the structured tables (NQS_H_TABLES) against the term
+    list: the enumeration of the batch's first chunk (diagonal, count, scan,
+    write; no dedup), and the local energy of the prefix with the tables in
+    the prefix path's configuration (ref: that path's result)."""
+    import numpy as np
+    import torch
+    res = {}
+    for tables in (False, True):
+        Hh = nqs.Hamiltonian.from_terms(terms, tables=tables).upload(ctx)
+        ep = nqs.Plan(ctx, Hh, cfg["L"], cfg["h"], cfg["n_up"], cfg["n_dn"], prec, max_batch=chunk,
+                      chunk_samples=chunk)
+        con = nqs.connected(ep, x[:chunk])      # warm
+        del con
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        con = nqs.connected(ep, x[:chunk])
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        key = "tables" if tables else "term_list"
+        res[f"enumeration_ms_first_chunk_{key}"] = e0.elapsed_time(e1)
+        res[f"device_bytes_{key}"] = Hh.bytes
+        res["entries_first_chunk"] = int(con["n_entries"].item())
+        del con, ep
+        if tables:
+            P = xp.shape[0]
+            pl = nqs.Plan(ctx, Hh, cfg["L"], cfg["h"], cfg["n_up"], cfg["n_dn"], prec, max_batch=P, dedup=dedup)
+            pl.configure(waves_per_block=waves)
+            nqs.local_energy(pl, params, xp)    # warm
+            torch.cuda.synchronize()
+            pl.profile(True)
+            el = nqs.local_energy(pl, params, xp)
+            pr = pl.profile_read()
+            pl.profile(False)
+            el = el.cpu().numpy()
+            res["samples_terms_per_s_prefix"] = P * Hh.K / (pr["eloc_ms"] / 1e3)
+            res["samples_terms_per_s_prefix_term_list"] = ref["value"]
+            res["dedup"] = bool(dedup)
+            res["max_abs_dE_loc_vs_term_list"] = float(np.max(np.abs(el - ref["eloc"])))
+            del pl
+        del Hh
+    log(f"structured tables: first-chunk enumeration {res['enumeration_ms_first_chunk_tables']:.2f} ms "
+        f"(term list {res['enumeration_ms_first_chunk_term_list']:.2f} ms); prefix "
+        f"{res['samples_terms_per_s_prefix']:.3e} samples*terms/s (term list "
+        f"{res['samples_terms_per_s_prefix_term_list']:.3e}); max |dE_loc| vs term list "
+        f"{res['max_abs_dE_loc_vs_term_list']:.2e}")
     return res
 
 
@@ -456,6 +507,9 @@ def main():
 
         if args.wide_samples > 0:
             out["wide_76_qubits"] = wide_76(nqs, ctx, cfg, prec, kinfo["waves_per_block"], args.wide_samples)
+
+        out["structured_tables"] = tables_side(nqs, ctx, terms, cfg, prec, kinfo["waves_per_block"], plan.dedup,
+                                               x, plan.chunk_samples, xp, params, side[prec])
 
     if not args.no_cpu:
         from threadpoolctl import threadpool_info

@@ -116,6 +116,21 @@ typedef struct {
    (an integer test).  Without the flag a group is skipped only when its
    matrix element is exactly 0.0. */
 #define NQS_H_CONSERVES_SPIN_SECTORS 1u
+/* Structured matrix elements (the Jordan-Wigner structure of a molecular
+   Hamiltonian, Sec. 5.1).  Inside group g with flip f every term's z mask is
+   split as z = u xor (z & f), u = z & ~f.  The terms with equal u form a
+   sub-group s (in order of first appearance in the canonical order); its
+   table T_s has 2^m entries, m = popcount(f) <= 4, T_s[b] = sum over its
+   terms of ct_k (-1)^{popcount(z_k & f & spread(b))} in canonical order,
+   spread(b) placing bit j of b on the j-th lowest qubit of f.  The
+   enumeration then evaluates
+       h_g(x) = sum_s (-1)^{popcount(x & u_s)} T_s[bits of x at f]
+   which is Eq. mtx_element summed over the group, in another order: a
+   double excitation is one sub-group with a 16-entry table, a single
+   excitation a few 4-entry tables (a linear form in the occupations), the
+   diagonal one entry per term.  A group whose flip has more than 4 qubits
+   gives NQS_ERR_UNSUPPORTED at nqs_ham_create. */
+#define NQS_H_TABLES 2u
 
 typedef struct nqs_ham nqs_ham;
 nqs_status nqs_ham_create(const nqs_pauli_terms* terms, nqs_ham** out);
@@ -130,6 +145,15 @@ nqs_status nqs_ham_upload(nqs_ham* ham, nqs_ctx* ctx, void* d_storage, size_t by
    gx [G][W], goff [G+1], tz [K][W], tc_re [K], tc_im [K]. */
 nqs_status nqs_ham_export(const nqs_ham* ham, uint64_t* gx, int64_t* goff, uint64_t* tz,
                           double* tc_re, double* tc_im);
+/* Sizes and host copy of the tables of an NQS_H_TABLES Hamiltonian (zero
+   sizes otherwise; any pointer may be NULL to skip): S sub-groups, E table
+   entries; soff [G+1] first sub-group of each group, su [S][W] off-flip z
+   masks, stab [S] first table entry of each sub-group, tab_re [E],
+   tab_im [E] (zero unless has_imag), fpos [G][4] the flip's qubits in
+   ascending order, -1 past its popcount. */
+nqs_status nqs_ham_table_info(const nqs_ham* ham, int64_t* S, int64_t* E);
+nqs_status nqs_ham_export_tables(const nqs_ham* ham, int64_t* soff, uint64_t* su, int64_t* stab,
+                                 double* tab_re, double* tab_im, int8_t* fpos);
 void       nqs_ham_destroy(nqs_ham* ham);
 
 /* ------------------------------------------------------------------ network

@@ -10,6 +10,7 @@ STATUS_NAMES = {0: "NQS_OK", 1: "NQS_ERR_INVALID_ARGUMENT", 2: "NQS_ERR_UNSUPPOR
                 3: "NQS_ERR_NOT_HERMITIAN", 4: "NQS_ERR_WORKSPACE_TOO_SMALL", 5: "NQS_ERR_HIP",
                 6: "NQS_ERR_DEVICE"}
 NQS_H_CONSERVES_SPIN_SECTORS = 1
+NQS_H_TABLES = 2
 NQS_PLAN_DEDUP_ON = 1
 NQS_PLAN_DEDUP_OFF = 2
 NQS_PLAN_DEDUP_AUTO = 4
@@ -71,6 +72,8 @@ SIGNATURES = {
                                C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "nqs_ham_upload": (C.c_int, [_P, _P, _P, _SZ]),
     "nqs_ham_export": (C.c_int, [_P, _P, _P, _P, _P, _P]),
+    "nqs_ham_table_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64)]),
+    "nqs_ham_export_tables": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "nqs_ham_destroy": (None, [_P]),
     "nqs_net_param_count": (C.c_int, [C.POINTER(NetDesc), C.POINTER(_I64)]),
     "nqs_plan_create": (C.c_int, [_P, _P, C.POINTER(NetDesc), _I64, C.c_uint32, _I64, C.POINTER(_P)]),

@@ -74,7 +74,8 @@ class Hamiltonian:
     """Pauli-string Hamiltonian canonicalised on the host (merge, drop, fold, sort, group)."""
 
     def __init__(self, n_qubits, x_mask, z_mask, coeff, coeff_imag=None, drop_tol=1e-10,
-                 conserves_spin=True):
+                 conserves_spin=True, tables=False):
+        """tables: evaluate matrix elements from per-group structured tables (NQS_H_TABLES)."""
         self.lib = L.load()
         self.n = int(n_qubits)
         self.words = words(self.n)
@@ -88,7 +89,8 @@ class Hamiltonian:
         self._ci = None if coeff_imag is None else np.ascontiguousarray(np.asarray(coeff_imag, dtype=np.float64))
         t = L.PauliTerms(self.n, self._x.shape[0], self._x.ctypes.data, self._z.ctypes.data,
                          self._c.ctypes.data, None if self._ci is None else self._ci.ctypes.data,
-                         float(drop_tol), L.NQS_H_CONSERVES_SPIN_SECTORS if conserves_spin else 0)
+                         float(drop_tol), (L.NQS_H_CONSERVES_SPIN_SECTORS if conserves_spin else 0)
+                         | (L.NQS_H_TABLES if tables else 0))
         h = C.c_void_p()
         L.check(self.lib.nqs_ham_create(C.byref(t), C.byref(h)), "nqs_ham_create")
         self.handle = h
@@ -121,6 +123,22 @@ class Hamiltonian:
         L.check(self.lib.nqs_ham_export(self.handle, gx.ctypes.data, goff.ctypes.data, tz.ctypes.data,
                                         tre.ctypes.data, tim.ctypes.data), "nqs_ham_export")
         return dict(gx=gx, goff=goff, tz=tz, tre=tre, tim=tim)
+
+    def export_tables(self):
+        """Host copy of the structured tables (empty arrays without NQS_H_TABLES)."""
+        S, E = C.c_int64(), C.c_int64()
+        L.check(self.lib.nqs_ham_table_info(self.handle, C.byref(S), C.byref(E)), "nqs_ham_table_info")
+        S, E = S.value, E.value
+        soff = np.zeros(self.G + 1 if S else 0, dtype=np.int64)
+        su = np.zeros((S, self.words), dtype=np.uint64)
+        stab = np.zeros(S, dtype=np.int64)
+        tre = np.zeros(E, dtype=np.float64)
+        tim = np.zeros(E, dtype=np.float64)
+        fpos = np.zeros((self.G if S else 0, 4), dtype=np.int8)
+        L.check(self.lib.nqs_ham_export_tables(self.handle, soff.ctypes.data, su.ctypes.data, stab.ctypes.data,
+                                               tre.ctypes.data, tim.ctypes.data, fpos.ctypes.data),
+                "nqs_ham_export_tables")
+        return dict(soff=soff, su=su, stab=stab, tre=tre, tim=tim, fpos=fpos)
 
     def __del__(self):
         if getattr(self, "handle", None):

@@ -68,6 +68,38 @@ __device__ __forceinline__ void group_h(const HamDev& H, const Bits<W>& x, long 
   im = b;
 }
 
+// h_g(x) from the structured tables: sum over the group's sub-groups s of
+// (-1)^{popcount(x & u_s)} T_s[bits of x at the flip's qubits], sub-groups in
+// order; the same sum as group_h in another order.
+template <bool IMAG, int W>
+__device__ __forceinline__ void group_h_tables(const HamDev& H, const Bits<W>& x, int g, double& re, double& im) {
+  int idx = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int p = H.fpos[4 * g + j];
+    if (p >= 0) {
+      const uint64_t word = W == 1 ? x.w[0] : x.w[(p >> 6) & (W - 1)];
+      idx |= (int)((word >> (p & 63)) & 1ull) << j;
+    }
+  }
+  double a = 0.0, b = 0.0;
+  for (long long s = H.soff[g]; s < H.soff[g + 1]; ++s) {
+    const unsigned long long par = (unsigned long long)(popc_and<W>(x, H.su, s) & 1) << 63;
+    const long long e = H.stab[s] + idx;
+    a += __longlong_as_double(__double_as_longlong(H.tabre[e]) ^ par);
+    if constexpr (IMAG) b += __longlong_as_double(__double_as_longlong(H.tabim[e]) ^ par);
+  }
+  re = a;
+  im = b;
+}
+
+// h_g(x) of group g, from the term list or from the tables
+template <bool IMAG, int W>
+__device__ __forceinline__ void group_value(const HamDev& H, const Bits<W>& x, int g, double& re, double& im) {
+  if (H.tables) group_h_tables<IMAG, W>(H, x, g, re, im);
+  else group_h<IMAG, W>(H, x, H.goff[g], H.goff[g + 1], re, im);
+}
+
 // the flip f keeps the number of up (even qubits) and down (odd qubits) electrons
 template <int W>
 __device__ __forceinline__ bool sector_ok(const Bits<W>& x, const Bits<W>& f) {
@@ -88,7 +120,7 @@ __global__ void diag_kernel(HamDev H, const uint64_t* __restrict__ xs, long long
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S) return;
   double re = 0.0, im = 0.0;
-  if (H.gfirst) group_h<IMAG, W>(H, load_bits<W>(xs, i), H.goff[0], H.goff[1], re, im);
+  if (H.gfirst) group_value<IMAG, W>(H, load_bits<W>(xs, i), 0, re, im);
   diag[2 * i] = re;
   diag[2 * i + 1] = im;
 }
@@ -123,7 +155,7 @@ __global__ void count_kernel(HamDev H, const uint64_t* __restrict__ xs, long lon
       ok = sector_ok<W>(x, f);
     } else {
       double re, im;
-      group_h<IMAG, W>(H, x, H.goff[g], H.goff[g + 1], re, im);
+      group_value<IMAG, W>(H, x, g, re, im);
       ok = (re != 0.0) || (im != 0.0);
     }
     c += ok ? 1 : 0;
@@ -279,7 +311,7 @@ __global__ void write_kernel(HamDev H, const uint64_t* __restrict__ xs, long lon
   for (int g = g0; g < g1; ++g) {
     const Bits<W> f = load_bits<W>(H.gx, g);
     double re, im;
-    group_h<IMAG, W>(H, x, H.goff[g], H.goff[g + 1], re, im);
+    group_value<IMAG, W>(H, x, g, re, im);
     const bool ok = H.filter ? sector_ok<W>(x, f) : ((re != 0.0) || (im != 0.0));
     if (live && ok) {
       if (pos < cap) {

@@ -77,11 +77,73 @@ struct nqs_ham {
   std::vector<double> tre, tim;
   // census of non-empty flips by (up bits, down bits) for the entry bound
   std::map<std::pair<int, int>, long long> census;
+  // structured matrix elements (NQS_H_TABLES)
+  bool tables = false;
+  std::vector<long long> soff;   // [G+1]
+  std::vector<uint64_t> su;      // [S][words]
+  std::vector<long long> stab;   // [S]
+  std::vector<double> tabre, tabim;
+  std::vector<int8_t> fpos;      // [G][4]
   // device copy
   char* d_base = nullptr;
   size_t bytes = 0;
   size_t o_gx = 0, o_goff = 0, o_tz = 0, o_tre = 0, o_tim = 0;
+  size_t o_soff = 0, o_su = 0, o_stab = 0, o_tabre = 0, o_tabim = 0, o_fpos = 0;
 };
+
+// Tables of the structured matrix elements of group g (the flip's qubits,
+// sub-groups by off-flip z mask in order of first appearance, one 2^m-entry
+// table each, summed in canonical order).  False if the flip has more than
+// four qubits.
+static bool build_group_tables(nqs_ham* h, size_t g) {
+  const int W = h->words;
+  const uint64_t* f = &h->gx[g * W];
+  int8_t pos[4] = {-1, -1, -1, -1};
+  int m = 0;
+  for (int w = 0; w < W; ++w)
+    for (int b = 0; b < 64; ++b)
+      if ((f[w] >> b) & 1ull) {
+        if (m == 4) return false;
+        pos[m++] = (int8_t)(64 * w + b);
+      }
+  for (int j = 0; j < 4; ++j) h->fpos.push_back(pos[j]);
+  const long long k0 = h->goff[g], k1 = h->goff[g + 1];
+  const long long s0 = (long long)h->stab.size();
+  std::vector<std::array<uint64_t, 2>> seen;
+  std::vector<long long> sub_of(k1 - k0);
+  for (long long k = k0; k < k1; ++k) {
+    std::array<uint64_t, 2> u{0, 0};
+    for (int w = 0; w < W; ++w) u[w] = h->tz[k * W + w] & ~f[w];
+    size_t s = 0;
+    while (s < seen.size() && seen[s] != u) ++s;
+    if (s == seen.size()) seen.push_back(u);
+    sub_of[k - k0] = (long long)s;
+  }
+  const int E = 1 << m;
+  for (size_t s = 0; s < seen.size(); ++s) {
+    h->stab.push_back((long long)h->tabre.size());
+    for (int w = 0; w < W; ++w) h->su.push_back(seen[s][w]);
+    for (int b = 0; b < E; ++b) {
+      // x's bits at the flip's qubits, spread back to their positions
+      uint64_t xb[2] = {0, 0};
+      for (int j = 0; j < m; ++j)
+        if ((b >> j) & 1) xb[pos[j] >> 6] |= 1ull << (pos[j] & 63);
+      double re = 0.0, im = 0.0;
+      for (long long k = k0; k < k1; ++k) {
+        if (sub_of[k - k0] != (long long)s) continue;
+        int par = 0;
+        for (int w = 0; w < W; ++w) par += __builtin_popcountll(xb[w] & h->tz[k * W + w] & f[w]);
+        const double sg = (par & 1) ? -1.0 : 1.0;
+        re += sg * h->tre[k];
+        im += sg * h->tim[k];
+      }
+      h->tabre.push_back(re);
+      h->tabim.push_back(im);
+    }
+  }
+  h->soff.push_back(s0 + (long long)seen.size());
+  return true;
+}
 
 struct nqs_plan {
   nqs_ctx* ctx = nullptr;
@@ -186,6 +248,15 @@ static HamDev ham_dev(const nqs_plan* p) {
   H.gfirst = ham_has_diag(h) ? 1 : 0;
   H.filter = (h->flags & NQS_H_CONSERVES_SPIN_SECTORS) ? 1 : 0;
   H.words = h->words;
+  H.tables = h->tables ? 1 : 0;
+  if (h->tables) {
+    H.soff = (const long long*)(h->d_base + h->o_soff);
+    H.su = (const uint64_t*)(h->d_base + h->o_su);
+    H.stab = (const long long*)(h->d_base + h->o_stab);
+    H.tabre = (const double*)(h->d_base + h->o_tabre);
+    H.tabim = h->has_imag ? (const double*)(h->d_base + h->o_tabim) : nullptr;
+    H.fpos = (const int8_t*)(h->d_base + h->o_fpos);
+  }
   return H;
 }
 
@@ -252,6 +323,8 @@ nqs_status nqs_ham_create(const nqs_pauli_terms* t, nqs_ham** out) {
   if (t->n_terms > 0 && (!t->x_mask || !t->z_mask || !t->coeff))
     return fail(NQS_ERR_INVALID_ARGUMENT, "NULL term arrays");
   if (!(t->drop_tol >= 0.0)) return fail(NQS_ERR_INVALID_ARGUMENT, "drop_tol must be >= 0");
+  if (t->flags & ~(NQS_H_CONSERVES_SPIN_SECTORS | NQS_H_TABLES))
+    return fail(NQS_ERR_INVALID_ARGUMENT, "unknown Hamiltonian flags 0x%x", t->flags);
   const int W = (t->n_qubits + 63) / 64;
   // valid bits of each word
   uint64_t valid[2] = {0, 0};
@@ -343,6 +416,16 @@ nqs_status nqs_ham_create(const nqs_pauli_terms* t, nqs_ham** out) {
     if (up + dn == 0) continue;
     h->census[{up, dn}] += 1;
   }
+  if (t->flags & NQS_H_TABLES) {
+    h->tables = true;
+    h->soff.push_back(0);
+    for (size_t gi = 0; gi < G; ++gi) {
+      if (!build_group_tables(h, gi)) {
+        delete h;
+        return fail(NQS_ERR_UNSUPPORTED, "group %zu flips more than 4 qubits: no tables", gi);
+      }
+    }
+  }
   // device layout
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
@@ -351,6 +434,14 @@ nqs_status nqs_ham_create(const nqs_pauli_terms* t, nqs_ham** out) {
   h->o_tz = take(K * W * 8);
   h->o_tre = take(K * 8);
   h->o_tim = h->has_imag ? take(K * 8) : 0;
+  if (h->tables) {
+    h->o_soff = take(h->soff.size() * 8);
+    h->o_su = take(h->su.size() * 8);
+    h->o_stab = take(h->stab.size() * 8);
+    h->o_tabre = take(h->tabre.size() * 8);
+    h->o_tabim = h->has_imag ? take(h->tabim.size() * 8) : 0;
+    h->o_fpos = take(h->fpos.size());
+  }
   h->bytes = std::max<size_t>(o, 256);
   *out = h;
   return NQS_OK;
@@ -380,6 +471,17 @@ nqs_status nqs_ham_upload(nqs_ham* h, nqs_ctx* ctx, void* d_storage, size_t byte
     if (h->has_imag)
       HIP_TRY(hipMemcpyAsync(d + h->o_tim, h->tim.data(), h->tim.size() * 8, hipMemcpyHostToDevice, s));
   }
+  if (h->tables) {
+    auto put = [&](size_t off, const void* src, size_t n) {
+      return n ? hipMemcpyAsync(d + off, src, n, hipMemcpyHostToDevice, s) : hipSuccess;
+    };
+    HIP_TRY(put(h->o_soff, h->soff.data(), h->soff.size() * 8));
+    HIP_TRY(put(h->o_su, h->su.data(), h->su.size() * 8));
+    HIP_TRY(put(h->o_stab, h->stab.data(), h->stab.size() * 8));
+    HIP_TRY(put(h->o_tabre, h->tabre.data(), h->tabre.size() * 8));
+    if (h->has_imag) HIP_TRY(put(h->o_tabim, h->tabim.data(), h->tabim.size() * 8));
+    HIP_TRY(put(h->o_fpos, h->fpos.data(), h->fpos.size()));
+  }
   HIP_TRY(hipStreamSynchronize(s));
   h->d_base = d;
   return NQS_OK;
@@ -392,6 +494,25 @@ nqs_status nqs_ham_export(const nqs_ham* h, uint64_t* gx, int64_t* goff, uint64_
   if (tz) std::copy(h->tz.begin(), h->tz.end(), tz);
   if (tre) std::copy(h->tre.begin(), h->tre.end(), tre);
   if (tim) std::copy(h->tim.begin(), h->tim.end(), tim);
+  return NQS_OK;
+}
+
+nqs_status nqs_ham_table_info(const nqs_ham* h, int64_t* S, int64_t* E) {
+  if (!h) return fail(NQS_ERR_INVALID_ARGUMENT, "ham is NULL");
+  if (S) *S = (int64_t)h->stab.size();
+  if (E) *E = (int64_t)h->tabre.size();
+  return NQS_OK;
+}
+
+nqs_status nqs_ham_export_tables(const nqs_ham* h, int64_t* soff, uint64_t* su, int64_t* stab, double* tab_re,
+                                 double* tab_im, int8_t* fpos) {
+  if (!h) return fail(NQS_ERR_INVALID_ARGUMENT, "ham is NULL");
+  if (soff) for (size_t i = 0; i < h->soff.size(); ++i) soff[i] = (int64_t)h->soff[i];
+  if (su) std::copy(h->su.begin(), h->su.end(), su);
+  if (stab) for (size_t i = 0; i < h->stab.size(); ++i) stab[i] = (int64_t)h->stab[i];
+  if (tab_re) std::copy(h->tabre.begin(), h->tabre.end(), tab_re);
+  if (tab_im) std::copy(h->tabim.begin(), h->tabim.end(), tab_im);
+  if (fpos) std::copy(h->fpos.begin(), h->fpos.end(), fpos);
   return NQS_OK;
 }
 

@@ -89,6 +89,16 @@ struct HamDev {
   int gfirst;          // 1 if group 0 is the empty flip
   int filter;          // spin-sector filter on
   int words;           // 1 or 2
+  // structured matrix elements (tables != 0): sub-groups soff[g] .. soff[g+1],
+  // off-flip masks su[s][words], table of sub-group s at stab[s], 2^m entries
+  // indexed by the bits of x at fpos[4g .. 4g+3] (-1 unused)
+  int tables;
+  const long long* soff;
+  const uint64_t* su;
+  const long long* stab;
+  const double* tabre;
+  const double* tabim;   // nullptr when every folded coefficient is real
+  const int8_t* fpos;
 };
 
 // ---- launchers (kernels_*.hip) -------------------------------------------

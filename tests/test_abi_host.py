@@ -190,3 +190,74 @@ def test_binding_rejects_tensors_the_kernels_would_overrun():
                      (torch.zeros(12, dtype=torch.float64)[::2], "strided")):
         with pytest.raises(ValueError):
             _dev_tensor(bad, why, torch.float64, 6, "cpu")
+
+
+def _table_h(tb, g, x_int, W):
+    """h_g(x) from exported structured tables, as the header defines it (test-side model)."""
+    idx = 0
+    for j, p in enumerate(tb["fpos"][g].tolist()):
+        if p >= 0:
+            idx |= ((x_int >> p) & 1) << j
+    re = im = 0.0
+    for s in range(tb["soff"][g], tb["soff"][g + 1]):
+        u = sum(int(w) << (64 * k) for k, w in enumerate(tb["su"][s].tolist()))
+        sg = -1.0 if bin(x_int & u).count("1") & 1 else 1.0
+        re += sg * tb["tre"][tb["stab"][s] + idx]
+        im += sg * tb["tim"][tb["stab"][s] + idx]
+    return complex(re, im)
+
+
+@pytest.mark.parametrize("N,cutoff", [(6, 0.0), (12, 0.0), (38, 0.05)])
+def test_structured_tables_reproduce_the_group_sums(lib, N, cutoff):
+    """Tables built by nqs_ham_create(NQS_H_TABLES): one 16-entry table per double
+    excitation, 4-entry tables for singles, one entry per diagonal term; evaluated
+    with the header's formula they give the oracle's h_g(x) for every group to the
+    rounding of two summation orders, 2 m eps sum |c| (m terms in the group)."""
+    from gen.inputs import hamiltonian, sector_samples
+    t = hamiltonian(N, 0, cutoff=cutoff)
+    n = 2 * N
+    W = 1 if n <= 64 else 2
+    H = _ham(n, t.x_mask, t.z_mask, t.coeff, flags=1)
+    from paper_2208_05637_amd import Hamiltonian
+    Ht = Hamiltonian(n, t.x_mask, t.z_mask, t.coeff, tables=True)
+    tb = Ht.export_tables()
+    assert Ht.bytes > H.bytes and tb["soff"][-1] == len(tb["stab"])
+    ref = pauli.canonical_terms(t.x_mask, t.z_mask, t.coeff)
+    gx, goff = pauli.groups(ref)
+    sizes = [int(v).bit_count() for v in gx.tolist()]
+    nsub = np.diff(tb["soff"])
+    for g, m in enumerate(sizes):
+        ents = {int(tb["stab"][s + 1] - tb["stab"][s]) if s + 1 < len(tb["stab"]) else len(tb["tre"]) - int(tb["stab"][s])
+                for s in range(tb["soff"][g], tb["soff"][g + 1])}
+        assert ents == {1 << m}
+        if m == 4:
+            assert nsub[g] == 1                       # a double: one Jordan-Wigner string, 16 entries
+        if m == 0:
+            assert nsub[g] == goff[g + 1] - goff[g]   # the diagonal: one entry per term
+    xs = pauli.configs(sector_samples(n, N // 2, N // 2, 3, seed=11))
+    eps = 2.0 ** -53
+    rng = np.random.default_rng(N)
+    groups = range(len(gx)) if len(gx) < 400 else rng.choice(len(gx), 400, replace=False)
+    for x in xs.tolist():
+        for g in groups:
+            a, b = goff[g], goff[g + 1]
+            want = complex(0.0)
+            for k in range(a, b):
+                want += ref["ct"][k] * (-1.0 if bin(int(x) & int(ref["z"][k])).count("1") & 1 else 1.0)
+            got = _table_h(tb, g, int(x), W)
+            bound = 2 * (b - a) * eps * np.sum(np.abs(ref["c"][a:b]))
+            assert abs(got - want) <= bound, (g, got, want)
+
+
+def test_structured_tables_rejections(lib):
+    from paper_2208_05637_amd import Hamiltonian, NQSError
+    x = np.array([0b11111], dtype=np.uint64)           # a five-qubit flip has no 4-bit table index
+    with pytest.raises(NQSError) as e:
+        Hamiltonian(6, x, np.zeros(1, dtype=np.uint64), [1.0], tables=True)
+    assert e.value.status == 2
+    Hamiltonian(6, x, np.zeros(1, dtype=np.uint64), [1.0])                  # fine without tables
+    from paper_2208_05637_amd import _lib
+    t = _lib.PauliTerms(6, 1, x.ctypes.data, np.zeros(1, dtype=np.uint64).ctypes.data,
+                        np.ones(1).ctypes.data, None, 1e-10, 8)
+    h = C.c_void_p()
+    assert lib.nqs_ham_create(C.byref(t), C.byref(h)) == 1                 # unknown flag
