@@ -23,8 +23,8 @@ configuration, t), so a draw does not depend on where the entry sits in the
 buffer.
 
 Random numbers: Philox4x64-10 (Salmon, Moraes, Dror and Shaw, "Parallel random
-numbers: as easy as 1, 2, 3", SC 2011), counter (x_parent, t, 0, 0), key
-(seed, 0).  Binomial draw Bin(c, p) from the counter's first two outputs:
+numbers: as easy as 1, 2, 3", SC 2011), counter (x_parent mod 2^64, t,
+x_parent >> 64, 0) (the last two words are zero up to 64 qubits), key (seed, 0).  Binomial draw Bin(c, p) from the counter's first two outputs:
 with q = min(p, 1 - p), inversion of the distribution function summed from
 k = 0 when c q < 32 (stopping where the terms underflow to zero, which bounds
 the search when u lies above the rounded total), otherwise the normal approximation
@@ -36,6 +36,16 @@ import math
 import numpy as np
 
 from . import made
+from .pauli import configs
+
+
+def _as_configs(vals, n):
+    if n <= 64:
+        return np.array(vals, dtype=np.uint64)
+    out = np.empty(len(vals), dtype=object)
+    for i, v in enumerate(vals):
+        out[i] = int(v)
+    return out
 
 _M0, _M1 = 0xD2E7470EE14C6C93, 0xCA5A826395121157
 _W0, _W1 = 0x9E3779B97F4A7C15, 0xBB67AE8584CAA73B
@@ -88,13 +98,14 @@ def binomial(c, p, u1, u2):
 
 def split_draws(count, p1, x_parent, t, seed):
     """Draws of the child with x = 1 out of `count`."""
-    w = philox4x64_10((x_parent, t, 0, 0), (seed, 0))
+    x_parent = int(x_parent)
+    w = philox4x64_10((x_parent & _MASK, t, x_parent >> 64, 0), (seed, 0))
     return binomial(count, p1, uniform53(w[0]), uniform53(w[1]))
 
 
 def conditionals(net: made.Net, params, xs, t):
     """P(x_{order[t]} = 1 | earlier positions) for each configuration of xs."""
-    xs = np.asarray(xs, dtype=np.uint64)
+    xs = configs(xs)
     _, _, cache = made.forward(net, params, xs)
     q = net.order[t]
     o = cache["o"][:, q]
@@ -104,12 +115,13 @@ def conditionals(net: made.Net, params, xs, t):
 
 
 def sample(net: made.Net, params, n_draws, seed, max_unique):
-    """(configurations uint64 [U], counts int64 [U]) in buffer order."""
+    """(configurations [U], counts int64 [U]) in buffer order; configurations are
+    uint64 up to 64 qubits and Python integers (dtype object) above."""
     xs = [0]
     cs = [int(n_draws)]
     for t in range(net.n):
-        q = net.order[t]
-        p = conditionals(net, params, np.array(xs, dtype=np.uint64), t)
+        q = int(net.order[t])   # a Python integer: the child bit 1 << q for any qubit
+        p = conditionals(net, params, _as_configs(xs, net.n), t)
         c1 = [split_draws(c, float(p[i]), x, t, seed) for i, (x, c) in enumerate(zip(xs, cs))]
         kids = [(x, c - k) for x, c, k in zip(xs, cs, c1)] + \
                [(x | (1 << q), k) for x, k in zip(xs, c1)]
@@ -120,4 +132,4 @@ def sample(net: made.Net, params, n_draws, seed, max_unique):
             kids = [kids[i] for i in sorted(keep)]
         xs = [x for x, _ in kids]
         cs = [c for _, c in kids]
-    return np.array(xs, dtype=np.uint64), np.array(cs, dtype=np.int64)
+    return _as_configs(xs, net.n), np.array(cs, dtype=np.int64)

@@ -187,3 +187,32 @@ def test_wide_local_energy_is_invariant_under_relabelling_across_the_word_bounda
     eb = vmc.local_energy(tb, nb, pb, _obj([_relabel_int(v, pi) for v in xs]))
     scale = np.sum(np.abs(t.coeff))
     assert np.max(np.abs(ea - eb)) < 1e-12 * scale
+
+
+def test_wide_sampler_counter_and_properties():
+    """The sampler's counter carries the configuration's high word in its third
+    word (zero up to 64 qubits, so one-word draws are unchanged); at 66 qubits
+    with an unbounded buffer every draw is kept (counts sum to n_draws), the
+    configurations are distinct and in the sector, and the draws of the first
+    position split binomially with the network's conditional there."""
+    from oracle import sampler
+    x = (1 << 63) | 12345
+    assert sampler.split_draws(1000, 0.3, x, 5, 9) == sampler.binomial(
+        1000, 0.3, *[sampler.uniform53(w) for w in sampler.philox4x64_10((x, 5, 0, 0), (9, 0))[:2]])
+    xw = x | (7 << 64)
+    w = sampler.philox4x64_10((x, 5, 7, 0), (9, 0))
+    assert sampler.split_draws(1000, 0.3, xw, 5, 9) == sampler.binomial(1000, 0.3, sampler.uniform53(w[0]),
+                                                                        sampler.uniform53(w[1]))
+    n, L, h, draws = 66, 1, 16, 20000
+    net = made.Net(n=n, n_layers=L, width=h, n_up=2, n_dn=2)
+    params = init_params(n, L, h, seed=3, std=0.5)
+    xs, cs = sampler.sample(net, params, draws, seed=4, max_unique=10**9)
+    assert xs.dtype == object and int(cs.sum()) == draws and np.all(cs > 0)
+    assert len(set(int(v) for v in xs)) == len(xs)
+    xb = made.bits(net, xs)
+    assert np.all(xb[:, 0::2].sum(axis=1) == 2) and np.all(xb[:, 1::2].sum(axis=1) == 2)
+    assert any(int(v) >> 64 for v in xs)
+    q0 = int(net.order[0])
+    p0 = float(sampler.conditionals(net, params, pauli.configs(np.zeros((1, 2), dtype=np.uint64)), 0)[0])
+    k1 = int(cs[xb[:, q0] == 1].sum())
+    assert abs(k1 - draws * p0) <= 5 * np.sqrt(draws * p0 * (1 - p0))
