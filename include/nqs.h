@@ -334,8 +334,7 @@ nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* d_w
 
 /* ---------------------------------------------------------------- sampler
  * Unique-sample autoregressive sampling of the plan's network (Sec. 4,
- * Sampling; Eq. modifier for the Hamming-weight constraint), for plans of
- * at most 64 qubits (NQS_ERR_UNSUPPORTED above).  A buffer of
+ * Sampling; Eq. modifier for the Hamming-weight constraint).  A buffer of
  * distinct configurations with draw counts starts as the all-zero
  * configuration holding n_draws draws; at each sampling position t (qubit
  * order[t]) every entry is doubled into x = 0 / x = 1 children, its draws
@@ -343,11 +342,11 @@ nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* d_w
  * (0 or 1 where the modifier forces the value), empty children are dropped,
  * and beyond max_unique entries those with the fewest draws are eliminated
  * (ties: earlier buffer entries kept; the buffer is ordered by the bits in
- * sampling order).  Random numbers: Philox4x64-10, counter (parent
- * configuration, t, 0, 0), key (seed, 0); Bin(c, p) by inversion from 0 when
+ * sampling order).  Random numbers: Philox4x64-10, counter (the parent's
+ * word 0, t, its word 1 (0 up to 64 qubits), 0), key (seed, 0); Bin(c, p) by inversion from 0 when
  * c min(p, 1-p) < 32, else the normal approximation with continuity
  * correction (Box-Muller), reflected for p > 1/2.
- * Outputs (device): d_x[u] configurations (uint64, bit j = qubit j), d_w[u]
+ * Outputs (device): d_x[u] configurations (W uint64 words each), d_w[u]
  * their draw counts as f64 weights, d_n_unique[0] = U <= max_unique, for
  * u < U in buffer order.  d_x and d_w hold max_unique entries.  The network
  * arithmetic is the plan's precision.  d_ws: nqs_sample_workspace_size

@@ -357,7 +357,7 @@ def energy_grad_multi(items, workspace=None):
 
 
 def sample(plan, params, n_draws, seed, max_unique):
-    """Unique-sample autoregressive sampling (Sec. 4): (x int64 [U], weights f64 [U])."""
+    """Unique-sample autoregressive sampling (Sec. 4): (x int64 [U] or [U, W], weights f64 [U])."""
     params = _params(plan, params)
     dev = plan.ctx.device
     need = C.c_size_t()
@@ -365,7 +365,8 @@ def sample(plan, params, n_draws, seed, max_unique):
             "nqs_sample_workspace_size")
     raw = torch.empty(need.value + 256, dtype=torch.uint8, device=dev)
     ws = C.c_void_p((raw.data_ptr() + 255) & ~255)
-    x = torch.empty(int(max_unique), dtype=torch.int64, device=dev)
+    x = torch.empty(int(max_unique) if plan.words == 1 else (int(max_unique), plan.words), dtype=torch.int64,
+                    device=dev)
     w = torch.empty(int(max_unique), dtype=torch.float64, device=dev)
     nu = torch.zeros(1, dtype=torch.int64, device=dev)
     L.check(plan.lib.nqs_sample(plan.handle, _ptr(params), int(n_draws), int(seed) & (2**64 - 1),

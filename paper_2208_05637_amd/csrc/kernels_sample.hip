@@ -75,13 +75,15 @@ __device__ long long binomial_draw(long long c, double p, double u1, double u2) 
   return flip ? c - k : k;
 }
 
-__global__ void sample_init_kernel(uint64_t* x, long long* cnt, long long n_draws, long long* d_u) {
-  x[0] = 0;
+__global__ void sample_init_kernel(uint64_t* x, int words, long long* cnt, long long n_draws, long long* d_u) {
+  for (int w = 0; w < words; ++w) x[w] = 0;
   cnt[0] = n_draws;
   *d_u = 1;
 }
 
-// Children of entry i: (x, c - k) at i and (x | 1 << q, k) at U + i.
+// Children of entry i: (x, c - k) at i and (x | 1 << q, k) at U + i.  The
+// counter of the draw is (x's low word, t, x's high word, 0).
+template <int W>
 __global__ void sample_split_kernel(const uint64_t* __restrict__ x, const long long* __restrict__ cnt,
                                     const double2* __restrict__ cond, const long long* __restrict__ d_u,
                                     long long umax, int t, int q, uint64_t seed, uint64_t* __restrict__ kx,
@@ -93,13 +95,19 @@ __global__ void sample_split_kernel(const uint64_t* __restrict__ x, const long l
   const double2 cd = cond[i];
   const int code = (int)cd.y;
   const double p1 = code == 1 ? 0.0 : (code == 2 ? 1.0 : 1.0 / (1.0 + exp(-cd.x)));
-  uint64_t w[4] = {x[i], (uint64_t)t, 0ull, 0ull};
+  uint64_t xi[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) xi[k] = x[i * W + k];
+  uint64_t w[4] = {xi[0], (uint64_t)t, W == 2 ? xi[W - 1] : 0ull, 0ull};
   philox4x64_10(w, seed, 0ull);
   const long long c = cnt[i];
   const long long k1 = binomial_draw(c, p1, uniform53(w[0]), uniform53(w[1]));
-  kx[i] = x[i];
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    kx[i * W + k] = xi[k];
+    kx[(U + i) * W + k] = xi[k] | ((q >> 6) == k ? (1ull << (q & 63)) : 0ull);
+  }
   kc[i] = c - k1;
-  kx[U + i] = x[i] | (1ull << q);
   kc[U + i] = k1;
 }
 
@@ -176,6 +184,7 @@ __global__ void sample_keep_flags(const long long* __restrict__ kc, const long l
   keep[i] = k ? 1 : 0;
 }
 
+template <int W>
 __global__ void sample_compact_kernel(const uint64_t* __restrict__ kx, const long long* __restrict__ kc,
                                       const int* __restrict__ keep, const long long* __restrict__ koff,
                                       long long n2, uint64_t* __restrict__ x, long long* __restrict__ cnt,
@@ -184,10 +193,12 @@ __global__ void sample_compact_kernel(const uint64_t* __restrict__ kx, const lon
   if (i == 0) *d_u = koff[n2];
   if (i >= n2 || !keep[i]) return;
   const long long d = koff[i];
-  x[d] = kx[i];
+#pragma unroll
+  for (int k = 0; k < W; ++k) x[d * W + k] = kx[i * W + k];
   cnt[d] = kc[i];
 }
 
+template <int W>
 __global__ void sample_finish_kernel(const uint64_t* __restrict__ x, const long long* __restrict__ cnt,
                                      const long long* __restrict__ d_u, long long umax, uint64_t* __restrict__ ox,
                                      double* __restrict__ ow, long long* __restrict__ on) {
@@ -195,19 +206,21 @@ __global__ void sample_finish_kernel(const uint64_t* __restrict__ x, const long 
   const long long U = *d_u;
   if (i == 0) *on = U;
   if (i >= U || i >= umax) return;
-  ox[i] = x[i];
+#pragma unroll
+  for (int k = 0; k < W; ++k) ox[i * W + k] = x[i * W + k];
   ow[i] = (double)cnt[i];
 }
 
 static unsigned blocks_for(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
-void launch_sample_init(uint64_t* x, long long* cnt, long long n_draws, long long* d_u, hipStream_t s) {
-  hipLaunchKernelGGL(sample_init_kernel, dim3(1), dim3(1), 0, s, x, cnt, n_draws, d_u);
+void launch_sample_init(uint64_t* x, int words, long long* cnt, long long n_draws, long long* d_u, hipStream_t s) {
+  hipLaunchKernelGGL(sample_init_kernel, dim3(1), dim3(1), 0, s, x, words, cnt, n_draws, d_u);
 }
 
 void launch_sample_step(const SampleBufs& b, long long umax, int t, int q, uint64_t seed, hipStream_t s) {
   const long long n2 = 2 * umax;
-  hipLaunchKernelGGL(sample_split_kernel, dim3(blocks_for(umax, 256)), dim3(256), 0, s, b.x, b.cnt,
+  auto split = b.words == 2 ? sample_split_kernel<2> : sample_split_kernel<1>;
+  hipLaunchKernelGGL(split, dim3(blocks_for(umax, 256)), dim3(256), 0, s, b.x, b.cnt,
                      (const double2*)b.cond, b.d_u, umax, t, q, seed, b.kx, b.kc, b.d_nk);
   hipLaunchKernelGGL(sample_select_kernel, dim3(1), dim3(kSelThreads), 0, s, b.kc, b.d_nk, umax, b.sel);
   hipLaunchKernelGGL(sample_tie_flags, dim3(blocks_for(n2, 256)), dim3(256), 0, s, b.kc, b.d_nk, b.sel, n2, b.eq);
@@ -215,13 +228,15 @@ void launch_sample_step(const SampleBufs& b, long long umax, int t, int q, uint6
   hipLaunchKernelGGL(sample_keep_flags, dim3(blocks_for(n2, 256)), dim3(256), 0, s, b.kc, b.d_nk, b.sel,
                      b.eqoff, n2, b.keep);
   launch_scan(b.keep, n2, b.koff, b.stmp, s);
-  hipLaunchKernelGGL(sample_compact_kernel, dim3(blocks_for(n2, 256)), dim3(256), 0, s, b.kx, b.kc, b.keep,
+  auto compact = b.words == 2 ? sample_compact_kernel<2> : sample_compact_kernel<1>;
+  hipLaunchKernelGGL(compact, dim3(blocks_for(n2, 256)), dim3(256), 0, s, b.kx, b.kc, b.keep,
                      b.koff, n2, b.x, b.cnt, b.d_u);
 }
 
 void launch_sample_finish(const SampleBufs& b, long long umax, uint64_t* ox, double* ow, long long* on,
                           hipStream_t s) {
-  hipLaunchKernelGGL(sample_finish_kernel, dim3(blocks_for(umax, 256)), dim3(256), 0, s, b.x, b.cnt, b.d_u,
+  auto finish = b.words == 2 ? sample_finish_kernel<2> : sample_finish_kernel<1>;
+  hipLaunchKernelGGL(finish, dim3(blocks_for(umax, 256)), dim3(256), 0, s, b.x, b.cnt, b.d_u,
                      umax, ox, ow, on);
 }
 

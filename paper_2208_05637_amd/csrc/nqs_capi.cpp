@@ -1311,9 +1311,9 @@ SampleLayout sample_layout(const nqs_plan* p, int64_t U) {
   L.err = take(256);
   L.packed = take(p->packed_bytes);
   L.cond = take((size_t)U * 16);
-  L.x = take((size_t)U * 8);
+  L.x = take((size_t)U * 8 * p->g.words);
   L.cnt = take((size_t)U * 8);
-  L.kx = take(U2 * 8);
+  L.kx = take(U2 * 8 * p->g.words);
   L.kc = take(U2 * 8);
   L.eq = take(U2 * 4);
   L.keep = take(U2 * 4);
@@ -1330,7 +1330,6 @@ SampleLayout sample_layout(const nqs_plan* p, int64_t U) {
 
 nqs_status nqs_sample_workspace_size(const nqs_plan* p, int64_t max_unique, size_t* bytes) {
   if (!p || !bytes) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
-  if (p->g.words != 1) return fail(NQS_ERR_UNSUPPORTED, "the sampler takes at most 64 qubits");
   if (max_unique < 1 || max_unique > (1LL << 30))
     return fail(NQS_ERR_INVALID_ARGUMENT, "max_unique %lld outside 1..2^30", (long long)max_unique);
   *bytes = sample_layout(p, max_unique).total;
@@ -1340,7 +1339,6 @@ nqs_status nqs_sample_workspace_size(const nqs_plan* p, int64_t max_unique, size
 nqs_status nqs_sample(nqs_plan* p, const float* params, int64_t n_draws, uint64_t seed, int64_t max_unique,
                       uint64_t* d_x, double* d_w, int64_t* d_n_unique, void* ws, size_t ws_bytes) {
   if (!p || !params || !d_x || !d_w || !d_n_unique) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
-  if (p->g.words != 1) return fail(NQS_ERR_UNSUPPORTED, "the sampler takes at most 64 qubits");
   if (n_draws < 1 || n_draws > (1LL << 62)) return fail(NQS_ERR_INVALID_ARGUMENT, "n_draws outside 1..2^62");
   if (max_unique < 1 || max_unique > (1LL << 30))
     return fail(NQS_ERR_INVALID_ARGUMENT, "max_unique %lld outside 1..2^30", (long long)max_unique);
@@ -1363,9 +1361,10 @@ nqs_status nqs_sample(nqs_plan* p, const float* params, int64_t n_draws, uint64_
   b.sel = at<long long>(ws, L.sel);
   b.d_u = at<long long>(ws, L.du);
   b.d_nk = at<long long>(ws, L.dnk);
+  b.words = p->g.words;
   void* packed = at<void>(ws, L.packed);
   launch_pack_fused(p->g, params, packed, s);
-  launch_sample_init(b.x, b.cnt, n_draws, b.d_u, s);
+  launch_sample_init(b.x, b.words, b.cnt, n_draws, b.d_u, s);
   for (int t = 0; t < p->g.n; ++t) {
     launch_forward_cond(p->g, p->variant, packed, b.x, max_unique, b.d_u, b.cond, t, s);
     launch_sample_step(b, max_unique, t, (int)p->g.order[t], seed, s);

@@ -198,8 +198,9 @@ struct SampleBufs {
   long long* sel;    // [2] threshold, quota
   long long* d_u;    // entries in the buffer
   long long* d_nk;   // children
+  int words;         // 64-bit words per configuration (x and kx hold `words` words each)
 };
-void launch_sample_init(uint64_t* x, long long* cnt, long long n_draws, long long* d_u, hipStream_t s);
+void launch_sample_init(uint64_t* x, int words, long long* cnt, long long n_draws, long long* d_u, hipStream_t s);
 void launch_sample_step(const SampleBufs& b, long long umax, int t, int q, uint64_t seed, hipStream_t s);
 void launch_sample_finish(const SampleBufs& b, long long umax, uint64_t* ox, double* ow, long long* on,
                           hipStream_t s);
