@@ -87,10 +87,10 @@ def measured_traffic(workload, prec, waves):
 WIDE_N_ORB, WIDE_CUTOFF = 38, 2.5e-5
 
 
-def wide_76(nqs, ctx, cfg, prec, waves, count):
+def wide_76(nqs, ctx, cfg, prec, count):
     """Local-energy throughput of the timed network kind and shape at 76 qubits,
     on `count` unique configurations drawn from the network by the GPU sampler
-    (10^12 draws)."""
+    (10^12 draws), workgroup shape and dedup autotuned."""
     import numpy as np
     import torch
     from gen.inputs import hamiltonian, init_params
@@ -100,14 +100,21 @@ def wide_76(nqs, ctx, cfg, prec, waves, count):
     n, nu = 2 * WIDE_N_ORB, WIDE_N_ORB // 2
     H = nqs.Hamiltonian.from_terms(terms).upload(ctx)
     params = torch.from_numpy(init_params(n, cfg["L"], cfg["h"], seed=1, dtype=cfg["params"])).to(ctx.device)
-    pl = nqs.Plan(ctx, H, cfg["L"], cfg["h"], nu, nu, prec, max_batch=count)
+    pl = nqs.Plan(ctx, H, cfg["L"], cfg["h"], nu, nu, prec, max_batch=count, dedup="auto")
     s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     s0.record(ctx.stream)
     xs, _ = nqs.sample(pl, params, 10**12, seed=2, max_unique=count)
     s1.record(ctx.stream)
     torch.cuda.synchronize()
     count = xs.shape[0]
-    pl.configure(waves_per_block=waves)
+    pl.autotune(params, xs)               # workgroup shape and dedup, as for the main batch
+    # connected configurations per distinct one over the batch (one chunk)
+    con = nqs.connected(pl if pl.dedup else nqs.Plan(ctx, H, cfg["L"], cfg["h"], nu, nu, prec, max_batch=count,
+                                                     dedup=True), xs)
+    torch.cuda.synchronize()
+    ratio = int(con["n_entries"].item()) / max(int(con["n_unique"].item()), 1)
+    entries = int(con["n_entries"].item())
+    del con
     nqs.local_energy(pl, params, xs)      # warm
     torch.cuda.synchronize()
     pl.profile(True)
@@ -119,13 +126,16 @@ def wide_76(nqs, ctx, cfg, prec, waves, count):
     res = {"n_qubits": n, "terms": H.K, "groups": H.G, "samples": count,
            "samples_kind": "unique configurations drawn from the network (10^12 draws)",
            "sampler_ms": s0.elapsed_time(s1),
-           "entries_per_sample": pl.entries_per_sample, "chunk_samples": pl.chunk_samples,
+           "entries_per_sample_bound": pl.entries_per_sample, "entries": entries, "dedup_ratio": ratio,
+           "chunk_samples": pl.chunk_samples, "dedup": pl.dedup, "forward_rows": pr["forward_rows"],
+           "forward_waves_per_block": pl.kernel_info()["waves_per_block"],
            "samples_terms_per_s": count * H.K / (pr["eloc_ms"] / 1e3),
            "connected_configs_per_s": pr["forward_rows"] / (pr["eloc_ms"] / 1e3),
            "forward_tflops": pr["forward_flops"] / (pr["forward_ms"] / 1e3) / 1e12,
            "forward_ms_per_launch": pr["forward_ms"] / max(pr["forward_launches"], 1),
            "energy_mean": float(np.mean(el[:, 0])), "device_status": status}
-    log(f"76 qubits ({H.K} strings, {count} samples): {res['samples_terms_per_s']:.3e} samples*terms/s, "
+    log(f"76 qubits ({H.K} strings, {count} samples, {entries} entries, dedup ratio {ratio:.3f}, dedup "
+        f"{'on' if pl.dedup else 'off'}): {res['samples_terms_per_s']:.3e} samples*terms/s, "
         f"{res['forward_tflops']:.1f} TFLOP/s")
     return res
 
@@ -514,7 +524,7 @@ def main():
         out["variants_on_prefix"] = {"prefix_samples": P, "precision": prec, **var}
 
         if args.wide_samples > 0:
-            out["wide_76_qubits"] = wide_76(nqs, ctx, cfg, prec, kinfo["waves_per_block"], args.wide_samples)
+            out["wide_76_qubits"] = wide_76(nqs, ctx, cfg, prec, args.wide_samples)
 
         out["structured_tables"] = tables_side(nqs, ctx, terms, cfg, prec, kinfo["waves_per_block"], plan.dedup,
                                                x, plan.chunk_samples, xp, params, side[prec])

@@ -219,8 +219,9 @@ typedef struct {
 nqs_status nqs_net_param_count(const nqs_net_desc* net, int64_t* n_params);
 
 /* --------------------------------------------------------------------- plan */
-/* Dedup applies to one-word strings below 64 qubits; at 64 qubits or more
-   the flags are accepted and dedup stays off. */
+/* Dedup applies at every width except exactly 64 qubits, where the one-word
+   table's all-ones empty marker is a valid string (the flags are accepted
+   and dedup stays off). */
 #define NQS_PLAN_DEDUP_ON   1u   /* deduplicate connected configurations per chunk */
 #define NQS_PLAN_DEDUP_OFF  2u   /* never deduplicate (default when no flag is set) */
 #define NQS_PLAN_DEDUP_AUTO 4u   /* size the workspace for dedup, start with it on and
@@ -381,7 +382,7 @@ nqs_status nqs_adam_step(nqs_ctx* ctx, int64_t n, float* d_params, const double*
  * order (FP64).  Entry buffers must hold `capacity` entries; the count is
  * written to d_n_entries[0] (if it exceeds capacity only the first
  * `capacity` are written and NQS_DEV_ENTRY_OVERFLOW is raised).  With dedup
- * (plan flag; one-word strings only) d_unique[u] receives the distinct x' (any order), d_n_unique[0]
+ * (plan flag) d_unique[u] receives the distinct x' (W words each, in the order of their first entries), d_n_unique[0]
  * their number and d_entry_unique[e] the index of entry e's x' in d_unique;
  * without dedup these outputs may be NULL.
  */

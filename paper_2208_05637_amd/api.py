@@ -387,7 +387,7 @@ def connected(plan, samples, capacity=None):
         n_entries=torch.zeros(1, dtype=torch.int64, device=dev),
     )
     if plan.dedup:
-        out.update(unique=torch.empty(cap, dtype=torch.int64, device=dev),
+        out.update(unique=torch.empty(cap if plan.words == 1 else (cap, plan.words), dtype=torch.int64, device=dev),
                    entry_unique=torch.empty(cap, dtype=torch.int32, device=dev),
                    n_unique=torch.zeros(1, dtype=torch.int64, device=dev))
     ws, nb = plan.workspace()

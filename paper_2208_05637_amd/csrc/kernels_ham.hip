@@ -456,6 +456,42 @@ __global__ __launch_bounds__(512) void dedup_insert_kernel(const uint64_t* __res
   }
 }
 
+// Two-word keys: one lane per entry, straight into the global table.  A slot
+// word holds (tag << 32) | the entry that inserted the key (entries < 2^28,
+// so a slot word is never the all-ones empty marker); a probe whose tag
+// matches compares the full key with that entry's words in xe, which earlier
+// kernels wrote, so no lane waits on another.
+// eu[e] <- global slot of entry e's key; owner[slot] <- smallest entry holding it.
+__global__ __launch_bounds__(256) void dedup_insert_wide_kernel(const uint64_t* __restrict__ xe,
+                                                                const long long* __restrict__ d_count,
+                                                                long long cap,
+                                                                unsigned long long* __restrict__ hkeys,
+                                                                int* __restrict__ owner, long long HT,
+                                                                int* __restrict__ eu, unsigned* err) {
+  long long count = *d_count;
+  if (count > cap) count = cap;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const uint64_t lo = xe[2 * e], hi = xe[2 * e + 1];
+  const unsigned long long hsh = mix64(lo ^ mix64(hi));
+  const unsigned long long mine = (hsh & 0xFFFFFFFF00000000ull) | (unsigned long long)e;
+  const unsigned long long hmask = (unsigned long long)HT - 1;
+  unsigned long long gs = hsh & hmask;
+  int found = -1;
+  for (long long probe = 0; probe < HT; ++probe) {
+    const unsigned long long prev = atomicCAS(&hkeys[gs], kEmpty, mine);
+    if (prev == kEmpty) { found = (int)gs; break; }
+    if ((prev >> 32) == (mine >> 32)) {
+      const long long pe = (long long)(prev & 0xFFFFFFFFull);
+      if (xe[2 * pe] == lo && xe[2 * pe + 1] == hi) { found = (int)gs; break; }
+    }
+    gs = (gs + 1) & hmask;
+  }
+  if (found < 0) atomicOr(err, kErrHashOverflow);
+  else atomicMin(&owner[found], (int)e);
+  eu[e] = found;
+}
+
 // first[e] = 1 where entry e is the first holder of its key (0 beyond the count).
 __global__ void dedup_first_kernel(const long long* __restrict__ d_count, long long cap,
                                    const int* __restrict__ eu, const int* __restrict__ owner,
@@ -474,6 +510,7 @@ __global__ void dedup_first_kernel(const long long* __restrict__ d_count, long l
 }
 
 // The first holders, in entry order: xu[rank] = key, slot_id[slot] = rank.
+template <int W>
 __global__ void dedup_place_kernel(const long long* __restrict__ d_count, long long cap,
                                    const int* __restrict__ first, const long long* __restrict__ rank,
                                    const uint64_t* __restrict__ xe, const int* __restrict__ eu,
@@ -487,7 +524,8 @@ __global__ void dedup_place_kernel(const long long* __restrict__ d_count, long l
   for (long long e = i0; e < count; e += stride) {
     if (!first[e]) continue;
     const long long id = rank[e];
-    xu[id] = xe[e];
+#pragma unroll
+    for (int k = 0; k < W; ++k) xu[id * W + k] = xe[e * W + k];
     slot_id[eu[e]] = (int)id;
   }
 }
@@ -506,7 +544,7 @@ __global__ void dedup_remap_kernel(const long long* __restrict__ d_count, long l
 
 long long dedup_rank_tmp_elems(long long cap) { return scan_tiles(cap) + 1; }
 
-void launch_dedup(const uint64_t* xe, const long long* d_count, long long cap, uint64_t* hkeys,
+void launch_dedup(const uint64_t* xe, int words, const long long* d_count, long long cap, uint64_t* hkeys,
                   int* hslot, long long HT, int* eu, uint64_t* xu, long long* d_nu,
                   int* first, long long* rank, long long* rank_tmp, unsigned* err, hipStream_t s) {
   launch_fill_u64(hkeys, kEmpty, HT, s);
@@ -514,14 +552,19 @@ void launch_dedup(const uint64_t* xe, const long long* d_count, long long cap, u
   launch_fill_u64(d_nu, 0ull, 1, s);
   long long tiles = (cap + kDedupTile - 1) / kDedupTile;
   if (tiles <= 0) return;
-  hipLaunchKernelGGL(dedup_insert_kernel, dim3((unsigned)tiles), dim3(512), 0, s, xe, d_count, cap,
-                     (unsigned long long*)hkeys, hslot, HT, eu, err);
+  if (words == 2)
+    hipLaunchKernelGGL(dedup_insert_wide_kernel, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, xe, d_count,
+                       cap, (unsigned long long*)hkeys, hslot, HT, eu, err);
+  else
+    hipLaunchKernelGGL(dedup_insert_kernel, dim3((unsigned)tiles), dim3(512), 0, s, xe, d_count, cap,
+                       (unsigned long long*)hkeys, hslot, HT, eu, err);
   long long blocks = (cap + 255) / 256;
   if (blocks > 16384) blocks = 16384;
   hipLaunchKernelGGL(dedup_first_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d_count, cap, eu,
                      (const int*)hslot, first);
   launch_scan(first, cap, rank, rank_tmp, s);
-  hipLaunchKernelGGL(dedup_place_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d_count, cap, first, rank,
+  auto place = words == 2 ? dedup_place_kernel<2> : dedup_place_kernel<1>;
+  hipLaunchKernelGGL(place, dim3((unsigned)blocks), dim3(256), 0, s, d_count, cap, first, rank,
                      xe, eu, hslot, xu, d_nu);
   hipLaunchKernelGGL(dedup_remap_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d_count, cap,
                      (const int*)hslot, eu);

@@ -217,7 +217,7 @@ static WsLayout layout(const nqs_plan* p, int64_t B) {
     L.hkeys = take((size_t)p->HT * 8);
     L.hslot = take((size_t)p->HT * 4);
     L.eu = take((size_t)p->EC * 4);
-    L.xu = take((size_t)p->EC * 8);
+    L.xu = take((size_t)p->EC * 8 * p->g.words);
     L.nu = take(8);
     L.dfirst = take((size_t)p->EC * 4);
     L.drank = take(((size_t)p->EC + 1) * 8);
@@ -722,9 +722,10 @@ nqs_status nqs_plan_create(nqs_ctx* ctx, const nqs_ham* ham, const nqs_net_desc*
     grid_for(half, ngroups, r2, gp2);
     p->SRcap = std::max<int64_t>(p->S0 * p->R, half * r2);
   }
-  // the hash table keys one-word strings and all-ones marks an empty slot, so
-  // there is no dedup at 64 qubits or more
-  p->dedup_cap = (flags & (NQS_PLAN_DEDUP_ON | NQS_PLAN_DEDUP_AUTO)) != 0 && g.n < 64;
+  // a one-word table holds the keys themselves and all-ones marks an empty
+  // slot, so there is no dedup at exactly 64 qubits (two-word tables hold
+  // entry indices and take every width above)
+  p->dedup_cap = (flags & (NQS_PLAN_DEDUP_ON | NQS_PLAN_DEDUP_AUTO)) != 0 && (g.n < 64 || g.words == 2);
   p->dedup = p->dedup_cap;
   p->dedup_auto = (flags & NQS_PLAN_DEDUP_AUTO) != 0 && p->dedup_cap;
   if (p->dedup_cap) {
@@ -928,7 +929,7 @@ static ChunkFwd enum_chunk(nqs_plan* p, const uint64_t* x, int64_t c0, int64_t S
   if (p->dedup) {
     uint64_t* xu = at<uint64_t>(ws, L.xu);
     long long* nu = at<long long>(ws, L.nu);
-    launch_dedup(xe, d_total, p->EC, at<uint64_t>(ws, L.hkeys), at<int>(ws, L.hslot), p->HT, at<int>(ws, L.eu), xu,
+    launch_dedup(xe, p->g.words, d_total, p->EC, at<uint64_t>(ws, L.hkeys), at<int>(ws, L.hslot), p->HT, at<int>(ws, L.eu), xu,
                  nu, at<int>(ws, L.dfirst), at<long long>(ws, L.drank), at<long long>(ws, L.drtmp), err, s);
     return {xu, nu, bound, at<double>(ws, L.lpe)};
   }
@@ -1413,7 +1414,7 @@ nqs_status nqs_connected(nqs_plan* p, const uint64_t* x, int64_t B, int64_t capa
   if (p->dedup) {
     if (capacity > p->EC || (int64_t)2 * capacity > p->HT)
       return fail(NQS_ERR_INVALID_ARGUMENT, "capacity exceeds the plan's dedup buffers");
-    launch_dedup(d_ex, (const long long*)d_n_entries, capacity, at<uint64_t>(ws, L.hkeys), at<int>(ws, L.hslot),
+    launch_dedup(d_ex, p->g.words, (const long long*)d_n_entries, capacity, at<uint64_t>(ws, L.hkeys), at<int>(ws, L.hslot),
                  p->HT, d_eunique, d_unique, (long long*)d_n_unique, at<int>(ws, L.dfirst), at<long long>(ws, L.drank),
                  at<long long>(ws, L.drtmp), err, s);
   }

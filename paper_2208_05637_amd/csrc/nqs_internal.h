@@ -158,11 +158,12 @@ void launch_write(const HamDev& H, const uint64_t* x, long long S, int R, int gp
                   const long long* off, long long cap, uint64_t* xe, double* he, int* esample,
                   int hstride, unsigned* err, hipStream_t s);
 
-// Distinct keys of xe[0 .. min(*d_count, cap)) into xu in the order of their
-// first entries, eu[e] = index of entry e's key in xu, *d_nu = their number.
+// Distinct keys of xe[0 .. min(*d_count, cap)) (`words` 64-bit words each)
+// into xu in the order of their first entries, eu[e] = index of entry e's key
+// in xu, *d_nu = their number.
 // first: int[cap], rank: i64[cap + 1], rank_tmp: dedup_rank_tmp_elems(cap).
 long long dedup_rank_tmp_elems(long long cap);
-void launch_dedup(const uint64_t* xe, const long long* d_count, long long cap, uint64_t* hkeys,
+void launch_dedup(const uint64_t* xe, int words, const long long* d_count, long long cap, uint64_t* hkeys,
                   int* hslot, long long HT, int* eu, uint64_t* xu, long long* d_nu,
                   int* first, long long* rank, long long* rank_tmp, unsigned* err, hipStream_t s);
 

@@ -79,8 +79,11 @@ def test_wide_connected_bit_exact(nqs, ctx, h76, filt):
     H = nqs.Hamiltonian.from_terms(terms, conserves_spin=filt).upload(ctx)
     B = 70
     plan = nqs.Plan(ctx, H, 1, 64, 19, 19, "fp64", max_batch=B, chunk_samples=B, dedup=True)
-    assert not plan.dedup                       # one-word strings only
+    assert plan.dedup
     xs = sector_samples(n, 19, 19, B, seed=5)
+    # samples 1..8: connected configurations of sample 0, so the chunk shares configurations
+    _, ent0 = vmc.connected(ref, xs[:1])
+    xs[1:9] = _words([int(v) for v in ent0[0][1][:8].tolist()])
     out = nqs.connected(plan, xs)
     diag_ref, ent = vmc.connected(ref, xs, sector_filter=filt)
     torch.cuda.synchronize()
@@ -100,6 +103,13 @@ def test_wide_connected_bit_exact(nqs, ctx, h76, filt):
         assert np.array_equal(eh[pos:pos + k, 1], hv.imag)
         pos += k
     assert any(v >> 64 for v in ex) and any(v & 1 for v in ex)
+    # dedup: the distinct configurations in the order of their first entries, and each entry's index
+    nu = int(out["n_unique"].item())
+    uq = _ints(out["unique"][:nu].cpu().numpy())
+    first = list(dict.fromkeys(ex))
+    assert uq == first and nu < ne
+    eu = out["entry_unique"][:ne].cpu().numpy()
+    assert [uq[j] for j in eu.tolist()] == ex
 
 
 @pytest.mark.parametrize("n,prec,h,L,order_kind,tol", [
@@ -221,12 +231,11 @@ def test_wide_energy_bf16_weights(nqs, ctx, h76):
 
 
 def test_wide_rejections(nqs, ctx, h76):
-    """Two-word plans: no dedup, no multi-instance launch; bad shapes rejected."""
+    """Two-word plans: no multi-instance launch; bad shapes rejected."""
     from paper_2208_05637_amd import NQSError
     terms, H, ref = h76
     n = 2 * N76
     plan = nqs.Plan(ctx, H, 1, 64, 19, 19, "fp64", max_batch=8, dedup="auto")
-    assert not plan.dedup
     params = torch.from_numpy(init_params(n, 1, 64, seed=1)).cuda()
     xs = torch.from_numpy(sector_samples(n, 19, 19, 4, seed=1).view(np.int64)).cuda()
     item = dict(plan=plan, params=params, samples=xs, energy=torch.empty(3, dtype=torch.float64, device="cuda"),
@@ -286,3 +295,28 @@ def test_wide_sampler_matches_oracle_fp64(nqs, ctx, n, L, h, nu, nd, draws, umax
     assert xg == [int(v) for v in xr.tolist()]
     assert np.array_equal(w.cpu().numpy(), cr.astype(np.float64))
     assert any(v >> 64 for v in xg)
+
+
+@pytest.mark.parametrize("prec,h,L", [("fp64", 64, 2), ("bf16w", 512, 3)])
+def test_wide_dedup_on_off_bit_identical(nqs, ctx, h76, prec, h, L):
+    """Dedup only regroups rows: with two-word keys the local energies are bit
+    for bit those without it, over several chunks of samples drawn from the
+    network, with eight connected configurations of the first sample placed
+    after it so that the first chunk shares configurations."""
+    terms, H, ref = h76
+    n = 2 * N76
+    params = torch.from_numpy(init_params(n, L, h, seed=1, std=0.3 if h < 512 else 0.1,
+                                          dtype="bf16" if prec == "bf16w" else "fp32")).cuda()
+    mk = lambda d: nqs.Plan(ctx, H, L, h, 19, 19, prec, max_batch=200, dedup=d, chunk_samples=64)
+    x, w = nqs.sample(mk(False), params, 10**9, seed=3, max_unique=200)
+    nb = nqs.connected(mk(False), x[:1])["x"][:8]
+    x = torch.cat([x[:1], nb, x[1:]])[:200].contiguous()
+    pd = mk(True)
+    e_on = nqs.local_energy(pd, params, x)
+    e_off = nqs.local_energy(mk(False), params, x)
+    con = nqs.connected(mk(True), x[:64])
+    ne, nu = int(con["n_entries"].item()), int(con["n_unique"].item())
+    print(f"{prec}: 200 sampled configurations, first chunk {ne} entries, {nu} distinct ({ne / nu:.2f})")
+    assert pd.dedup and nu < ne
+    assert torch.equal(e_on, e_off)
+    assert nqs.device_status(pd) == 0
