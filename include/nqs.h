@@ -329,7 +329,8 @@ typedef struct {
   double*         d_energy;  /* [3] */
   double*         d_grad;    /* [n_params] */
 } nqs_instance;
-/* Instances of more than 64 qubits give NQS_ERR_UNSUPPORTED. */
+/* Instances of more than 64 qubits run their forwards as launches of their
+   own inside the same call (the shared work lists take one-word strings). */
 nqs_status nqs_multi_workspace_size(int n_inst, const nqs_instance* inst, size_t* bytes);
 nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* d_ws, size_t ws_bytes);
 

@@ -1044,8 +1044,6 @@ static nqs_status multi_layout(int n_inst, const nqs_instance* inst, std::vector
     const nqs_instance& I = inst[i];
     if (!I.plan) return fail(NQS_ERR_INVALID_ARGUMENT, "instance %d has no plan", i);
     if (I.plan->ctx != inst[0].plan->ctx) return fail(NQS_ERR_INVALID_ARGUMENT, "instances on different contexts");
-    if (I.plan->g.words != 1)
-      return fail(NQS_ERR_UNSUPPORTED, "instance %d: multi-instance launches take at most 64 qubits", i);
     if (I.B < 1 || I.B > I.plan->max_batch)
       return fail(NQS_ERR_INVALID_ARGUMENT, "instance %d: batch %lld outside 1..%lld", i, (long long)I.B,
                   (long long)I.plan->max_batch);
@@ -1092,31 +1090,43 @@ nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* ws,
     pack_net(p, inst[i].d_params, at<void>(W[i], L[i].packed), s);
   }
   // the forward segments of instance i's rows: its network, and with a
-  // separate phase network a second segment that writes the phases
+  // separate phase network a second segment that writes the phases (hg: the
+  // host copy of each segment's geometry)
+  std::vector<const Geom*> hg;
   auto add_segs = [&](int i, const uint64_t* x, const long long* d_count, double* out, long long bound,
                       std::vector<int>& ids, std::vector<FwdSeg>& segs) {
     const nqs_plan* p = inst[i].plan;
     ids.push_back(i);
+    hg.push_back(&p->g);
     segs.push_back(FwdSeg{at<Geom>(W[i], L[i].geom), at<void>(W[i], L[i].packed), x, d_count, out, bound, 0,
                           nullptr});
     if (p->two) {
       ids.push_back(i);
+      hg.push_back(&p->gp);
       segs.push_back(FwdSeg{at<Geom>(W[i], L[i].geom) + 1, at<char>(W[i], L[i].packed) + p->packed_phase, x,
                             d_count, out, bound, 0, nullptr});
     }
   };
   // One forward launch per group of segments whose networks share
   // (precision, width, variant): the segments' tiles form one work list.
+  // Segments of two-word strings take the single-segment forward, one launch each.
   auto launch_groups = [&](const std::vector<int>& ids, const std::vector<FwdSeg>& segs) {
     std::vector<bool> done(ids.size(), false);
     for (size_t a = 0; a < ids.size(); ++a) {
       if (done[a]) continue;
       const Geom& ga = inst[ids[a]].plan->g;
       const int va = inst[ids[a]].plan->variant;
+      if (ga.words != 1) {
+        const FwdSeg& sg = segs[a];
+        launch_forward(*hg[a], va, sg.packed, sg.x, sg.rows_bound, sg.d_count, sg.out, nullptr, s);
+        done[a] = true;
+        continue;
+      }
       FwdLaunch la{};
       for (size_t b = a; b < ids.size(); ++b) {
         const Geom& gb = inst[ids[b]].plan->g;
-        if (done[b] || gb.prec != ga.prec || gb.h != ga.h || inst[ids[b]].plan->variant != va) continue;
+        if (done[b] || gb.words != 1 || gb.prec != ga.prec || gb.h != ga.h || inst[ids[b]].plan->variant != va)
+          continue;
         la.seg[la.nseg++] = segs[b];
         done[b] = true;
         if (la.nseg == kMaxSeg) {
@@ -1136,6 +1146,7 @@ nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* ws,
   for (int64_t r = 0;; ++r) {
     ids.clear();
     segs.clear();
+    hg.clear();
     std::vector<int> rid;
     std::vector<int64_t> c0s, scs;
     for (int i = 0; i < n_inst; ++i) {
