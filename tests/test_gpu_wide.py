@@ -315,3 +315,65 @@ def test_wide_dedup_on_off_bit_identical(nqs, ctx, h76, prec, h, L):
     assert pd.dedup and nu < ne
     assert torch.equal(e_on, e_off)
     assert nqs.device_status(pd) == 0
+
+
+def test_wide_graph_capture_replay_matches_eager(nqs, ctx, h76):
+    """A 76-qubit energy-and-gradient step (dedup on, three chunks) captured in
+    a HIP graph: every replay equals the eager call, with eager work between
+    replays."""
+    terms, H, ref = h76
+    n, L, h = 2 * N76, 2, 256
+    dev = ctx.device
+    params = torch.from_numpy(init_params(n, L, h, seed=1, std=0.2)).to(dev)
+    plan = nqs.Plan(ctx, H, L, h, 19, 19, "fp32", max_batch=96, dedup=True, chunk_samples=32)
+    xt, wt = nqs.sample(plan, params, 10**8, seed=6, max_unique=96)
+    B = xt.shape[0]
+    eager = [t.clone() for t in nqs.energy_grad(plan, params, xt, wt)]
+    energy = torch.empty(3, dtype=torch.float64, device=dev)
+    grad = torch.empty(plan.n_params, dtype=torch.float64, device=dev)
+    eloc = torch.empty((B, 2), dtype=torch.float64, device=dev)
+    plan.workspace()
+    s = torch.cuda.Stream()
+    ctx.use_stream(s)
+    try:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            nqs.energy_grad(plan, params, xt, wt, eloc=eloc, energy=energy, grad=grad)
+    finally:
+        ctx.use_stream(torch.cuda.current_stream())
+    for rep in range(3):
+        energy.zero_(); grad.zero_(); eloc.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(energy, eager[0]) and torch.equal(grad, eager[1]) and torch.equal(eloc, eager[2])
+        _ = nqs.local_energy(plan, params, xt)     # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_wide_autotune_choices(nqs, ctx, h76):
+    """The autotuner on a two-word plan (dedup auto) times every candidate;
+    for one workgroup shape the dedup and chunk choices give the same local
+    energies bit for bit (they only regroup rows), and the two shapes (whose
+    head sums its k slices in another order) agree to the 1e-3 bar of the
+    sampled full-size checks."""
+    terms, H, ref = h76
+    n, L, h = 2 * N76, 2, 512
+    dev = ctx.device
+    params = torch.from_numpy(init_params(n, L, h, seed=1, dtype="bf16")).to(dev)
+    plan = nqs.Plan(ctx, H, L, h, 19, 19, "bf16w", max_batch=64, dedup="auto", chunk_samples=32)
+    xs = torch.from_numpy(sector_samples(n, 19, 19, 64, seed=8).view(np.int64)).to(dev)
+    rep = plan.autotune(params, xs)
+    assert len(rep["candidates"]) >= 4
+    by_shape = {}
+    for c in rep["candidates"]:
+        plan.configure(waves_per_block=c["waves_per_block"], dedup=c["dedup"], chunk_samples=c["chunk_samples"])
+        el = nqs.local_energy(plan, params, xs).clone()
+        first = by_shape.setdefault(c["waves_per_block"], el)
+        assert torch.equal(el, first), c
+    shapes = list(by_shape.values())
+    assert len(shapes) == 2
+    d = float((shapes[0] - shapes[1]).abs().max())
+    print(f"76 qubits: max |dE_loc| between the two workgroup shapes = {d:.3e}")
+    assert d <= 1e-3
+    assert nqs.device_status(plan) == 0
