@@ -129,12 +129,13 @@ class Hamiltonian:
         S, E = C.c_int64(), C.c_int64()
         L.check(self.lib.nqs_ham_table_info(self.handle, C.byref(S), C.byref(E)), "nqs_ham_table_info")
         S, E = S.value, E.value
-        soff = np.zeros(self.G + 1 if S else 0, dtype=np.int64)
+        # soff and fpos are sized by the groups: a table Hamiltonian without terms still has soff[0]
+        soff = np.zeros(self.G + 1, dtype=np.int64)
         su = np.zeros((S, self.words), dtype=np.uint64)
         stab = np.zeros(S, dtype=np.int64)
         tre = np.zeros(E, dtype=np.float64)
         tim = np.zeros(E, dtype=np.float64)
-        fpos = np.zeros((self.G if S else 0, 4), dtype=np.int8)
+        fpos = np.zeros((self.G, 4), dtype=np.int8)
         L.check(self.lib.nqs_ham_export_tables(self.handle, soff.ctypes.data, su.ctypes.data, stab.ctypes.data,
                                                tre.ctypes.data, tim.ctypes.data, fpos.ctypes.data),
                 "nqs_ham_export_tables")

@@ -249,6 +249,14 @@ def test_structured_tables_reproduce_the_group_sums(lib, N, cutoff):
             assert abs(got - want) <= bound, (g, got, want)
 
 
+def test_structured_tables_of_an_empty_hamiltonian(lib):
+    from paper_2208_05637_amd import Hamiltonian
+    z = np.zeros(0, dtype=np.uint64)
+    H = Hamiltonian(4, z, z, np.zeros(0), tables=True)
+    tb = H.export_tables()
+    assert H.K == 0 and H.G == 0 and tb["soff"].tolist() == [0] and len(tb["tre"]) == 0
+
+
 def test_structured_tables_rejections(lib):
     from paper_2208_05637_amd import Hamiltonian, NQSError
     x = np.array([0b11111], dtype=np.uint64)           # a five-qubit flip has no 4-bit table index
