@@ -20,5 +20,10 @@ Modules
   vmc   : local energy (Eq. local_energy_auto, Alg. 1), the energy estimate
           (Eq. total_energy_sum), the VMC gradient (Eq. grad), and the
           per-(sample, flip-group) validity bits and matrix elements.
+  sampler : unique-sample autoregressive sampling (Sec. 4, Sampling).
+  adam  : the optimiser step (Sec. 6).
+
+Bit strings are uint64 arrays up to 64 qubits and Python integers (dtype
+object) of any width above; every function takes either.
 """
 from . import pauli, made, vmc  # noqa: F401
