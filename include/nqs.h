@@ -72,6 +72,11 @@ const char* nqs_status_str(int status);
 size_t nqs_last_error(char* buf, size_t len);
 /* Library version, major*10000 + minor*100 + patch. */
 int nqs_version(void);
+/* SHA-256 (hex, static storage) of the sources the library was built from,
+   as computed by the package's build script; "unknown" for a build that did
+   not define it.  The Python binding refuses a library whose hash differs
+   from that of the sources beside it (a stale build). */
+const char* nqs_source_hash(void);
 
 /* ------------------------------------------------------------------ context */
 typedef struct nqs_ctx nqs_ctx;
@@ -261,12 +266,15 @@ nqs_status nqs_plan_kernel_info(const nqs_plan* plan, int* waves_per_block, int*
    and keeps the fastest in the plan.  The choice is cached per process,
    keyed by the network shape, the Hamiltonian's term and group counts and
    the plan's chunk; a later call with the same key applies it without timing
-   (NQS_TUNE_FORCE re-times).  Every candidate computes the same local
+   (NQS_TUNE_FORCE re-times; NQS_TUNE_CACHE_ONLY applies a cached choice if
+   there is one and otherwise returns NQS_OK with n_candidates = 0 and the
+   plan unchanged, without timing or touching the device).  Every candidate computes the same local
    energies up to the forward's rounding (dedup and chunking change nothing;
    the two variants split the head's k sum differently).  Synchronises the
    context's stream; not for use under graph capture.  d_ws must hold
    nqs_plan_workspace_size(plan, B) bytes.  report may be NULL. */
 #define NQS_TUNE_FORCE 1u
+#define NQS_TUNE_CACHE_ONLY 2u
 #define NQS_TUNE_MAX_CANDIDATES 16
 typedef struct {
   int     waves_per_block;
@@ -283,6 +291,22 @@ typedef struct {
 } nqs_tune_report;
 nqs_status nqs_plan_autotune(nqs_plan* plan, const float* d_params, const uint64_t* d_samples, int64_t B,
                              void* d_ws, size_t ws_bytes, uint32_t flags, nqs_tune_report* report);
+
+/* The tuner's cached choices as a text file, so that a later process applies
+   them without timing (a tuning database, as kept for the chunk size of the
+   paper's mini-batches, Sec. 5.2).  nqs_tune_db_save writes every entry of
+   this process's cache to path (through a temporary file renamed over it);
+   nqs_tune_db_load adds the entries of path to the cache, replacing equal
+   keys, and sets *n_loaded (may be NULL).  A key holds the network shape and
+   precision, the Hamiltonian's term and group counts, the per-sample entry
+   bound, the created chunk, the dedup mode and the device index; an entry is
+   applied by nqs_plan_autotune (without NQS_TUNE_FORCE) only to a plan with
+   the same key whose workspace has room for it.  Errors: NULL path or an
+   unreadable/unwritable file (NQS_ERR_INVALID_ARGUMENT); a malformed line
+   stops the load with NQS_ERR_INVALID_ARGUMENT, keeping the lines before
+   it.  Host only. */
+nqs_status nqs_tune_db_save(const char* path);
+nqs_status nqs_tune_db_load(const char* path, int* n_loaded);
 
 /* ---------------------------------------------------------------- hot path
  * All pointers are device pointers; d_ws is a workspace of at least

@@ -15,6 +15,7 @@ NQS_PLAN_DEDUP_ON = 1
 NQS_PLAN_DEDUP_OFF = 2
 NQS_PLAN_DEDUP_AUTO = 4
 NQS_TUNE_FORCE = 1
+NQS_TUNE_CACHE_ONLY = 2
 NQS_TUNE_MAX_CANDIDATES = 16
 NQS_DEV_ZERO_AMPLITUDE = 1
 NQS_DEV_ENTRY_OVERFLOW = 2
@@ -64,6 +65,7 @@ SIGNATURES = {
     "nqs_status_str": (C.c_char_p, [C.c_int]),
     "nqs_last_error": (_SZ, [C.c_char_p, _SZ]),
     "nqs_version": (C.c_int, []),
+    "nqs_source_hash": (C.c_char_p, []),
     "nqs_ctx_create": (C.c_int, [C.c_int, _P, C.POINTER(_P)]),
     "nqs_ctx_set_stream": (C.c_int, [_P, _P]),
     "nqs_ctx_destroy": (None, [_P]),
@@ -84,6 +86,8 @@ SIGNATURES = {
     "nqs_plan_configure": (C.c_int, [_P, C.c_int, C.c_int, _I64]),
     "nqs_plan_kernel_info": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "nqs_plan_autotune": (C.c_int, [_P, _P, _P, _I64, _P, _SZ, C.c_uint32, C.POINTER(TuneReport)]),
+    "nqs_tune_db_save": (C.c_int, [C.c_char_p]),
+    "nqs_tune_db_load": (C.c_int, [C.c_char_p, C.POINTER(C.c_int)]),
     "nqs_log_psi": (C.c_int, [_P, _P, _P, _I64, _P, _P, _SZ]),
     "nqs_local_energy": (C.c_int, [_P, _P, _P, _I64, _P, _P, _SZ]),
     "nqs_energy_grad": (C.c_int, [_P, _P, _P, _P, _I64, _P, _P, _P, _P, _SZ]),
@@ -118,6 +122,13 @@ def load():
         raise ImportError(f"HIP library {LIB_PATH} is missing; build it with "
                           "python -m paper_2208_05637_amd.build")
     lib = C.CDLL(LIB_PATH)
+    lib.nqs_source_hash.restype = C.c_char_p
+    lib.nqs_source_hash.argtypes = []
+    from .build import source_hash
+    built, now = lib.nqs_source_hash().decode(), source_hash()
+    if built != now:
+        raise ImportError(f"HIP library {LIB_PATH} was built from other sources ({built[:12]}) than the "
+                          f"tree holds ({now[:12]}); rebuild it with python -m paper_2208_05637_amd.build")
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
         fn.restype = res

@@ -47,6 +47,19 @@ def _strings(x, device, W):
     return t, t.shape[0]
 
 
+def tune_db_load(path):
+    """Add the tuner choices stored in path to this process's cache; returns the
+    number of entries read."""
+    n = C.c_int()
+    L.check(L.load().nqs_tune_db_load(str(path).encode(), C.byref(n)), "nqs_tune_db_load")
+    return n.value
+
+
+def tune_db_save(path):
+    """Write this process's tuner choices to path."""
+    L.check(L.load().nqs_tune_db_save(str(path).encode()), "nqs_tune_db_save")
+
+
 class Context:
     """A device + stream binding (no device memory is allocated)."""
 
@@ -212,15 +225,16 @@ class Plan:
                 "nqs_plan_kernel_info")
         return dict(waves_per_block=w.value, rows_per_block=r.value, tuned=bool(t.value))
 
-    def autotune(self, params, samples, force=False):
+    def autotune(self, params, samples, force=False, cache_only=False):
         """Time the candidate kernel variants / dedup / chunk sizes on a prefix of
-        the samples and keep the fastest; returns the timings."""
+        the samples and keep the fastest; returns the timings.  cache_only:
+        apply a cached (or database) choice if there is one, never time."""
         params = _params(self, params)
         x, B = _strings(samples, self.ctx.device, self.words)
         rep = L.TuneReport()
         ws, nb = self.workspace()
-        L.check(self.lib.nqs_plan_autotune(self.handle, _ptr(params), _ptr(x), B, ws, nb,
-                                           L.NQS_TUNE_FORCE if force else 0, C.byref(rep)),
+        flags = (L.NQS_TUNE_FORCE if force else 0) | (L.NQS_TUNE_CACHE_ONLY if cache_only else 0)
+        L.check(self.lib.nqs_plan_autotune(self.handle, _ptr(params), _ptr(x), B, ws, nb, flags, C.byref(rep)),
                 "nqs_plan_autotune")
         self._refresh()
         cands = [dict(waves_per_block=c.waves_per_block, dedup=bool(c.dedup), chunk_samples=c.chunk_samples,

@@ -2,6 +2,7 @@
 
 Usage: python -m paper_2208_05637_amd.build   (or build() from Python)
 """
+import hashlib
 import os
 import shutil
 import subprocess
@@ -30,9 +31,25 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src):
+def source_hash():
+    """SHA-256 over the library's sources and public header, in a fixed order;
+    compiled into the library so that a load can tell a stale build."""
+    h = hashlib.sha256()
+    names = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp", ".h")))
+    for f in names:
+        h.update(f.encode() + b"\0")
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    with open(os.path.join(ROOT, "include", "nqs.h"), "rb") as fh:
+        h.update(b"nqs.h\0" + fh.read())
+    return h.hexdigest()
+
+
+def _compile(src, digest):
     obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
     cmd = [hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    if src == "nqs_capi.cpp":
+        cmd.append(f'-DNQS_SOURCE_HASH="{digest}"')
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -43,8 +60,9 @@ def _compile(src):
 
 def build(verbose=False):
     os.makedirs(OBJDIR, exist_ok=True)
+    digest = source_hash()
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda f: _compile(f, digest), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -286,6 +286,11 @@ size_t nqs_last_error(char* buf, size_t len) {
 
 int nqs_version(void) { return 100; }
 
+#ifndef NQS_SOURCE_HASH
+#define NQS_SOURCE_HASH "unknown"
+#endif
+const char* nqs_source_hash(void) { return NQS_SOURCE_HASH; }
+
 nqs_status nqs_ctx_create(int device, void* stream, nqs_ctx** out) {
   if (!out) return fail(NQS_ERR_INVALID_ARGUMENT, "out is NULL");
   *out = nullptr;
@@ -1199,7 +1204,10 @@ nqs_status nqs_plan_autotune(nqs_plan* p, const float* params, const uint64_t* x
                              size_t ws_bytes, uint32_t flags, nqs_tune_report* rep) {
   if (!p || !params || !x) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
   if (B < 1) return fail(NQS_ERR_INVALID_ARGUMENT, "autotuning needs at least one sample");
-  if (flags & ~NQS_TUNE_FORCE) return fail(NQS_ERR_INVALID_ARGUMENT, "unknown tune flags 0x%x", flags);
+  if (flags & ~(NQS_TUNE_FORCE | NQS_TUNE_CACHE_ONLY))
+    return fail(NQS_ERR_INVALID_ARGUMENT, "unknown tune flags 0x%x", flags);
+  if ((flags & NQS_TUNE_FORCE) && (flags & NQS_TUNE_CACHE_ONLY))
+    return fail(NQS_ERR_INVALID_ARGUMENT, "NQS_TUNE_FORCE and NQS_TUNE_CACHE_ONLY exclude each other");
   WsLayout L;
   nqs_status st = check_ws(p, B, ws, ws_bytes, L);
   if (st != NQS_OK) return st;
@@ -1210,7 +1218,9 @@ nqs_status nqs_plan_autotune(nqs_plan* p, const float* params, const uint64_t* x
   if (!(flags & NQS_TUNE_FORCE)) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
-    if (it != g_tune_cache.end()) {
+    // an entry read from a database file is applied only where the plan's
+    // workspace has room for it (dedup tables, chunk within the created one)
+    if (it != g_tune_cache.end() && (!it->second.dedup || p->dedup_cap) && it->second.S <= p->S0) {
       p->variant = it->second.variant;
       p->dedup = it->second.dedup;
       set_chunk(p, it->second.S);
@@ -1223,6 +1233,7 @@ nqs_status nqs_plan_autotune(nqs_plan* p, const float* params, const uint64_t* x
       return NQS_OK;
     }
   }
+  if (flags & NQS_TUNE_CACHE_ONLY) return NQS_OK;
   struct Cand { int v; bool d; int64_t S; };
   std::vector<Cand> cands;
   const int nv = forward_variants(p->g.prec, p->g.h);
@@ -1278,6 +1289,70 @@ nqs_status nqs_plan_autotune(nqs_plan* p, const float* params, const uint64_t* x
     g_tune_cache[key] = TuneVal{p->variant, p->dedup, p->S, best_ms};
   }
   return NQS_OK;
+}
+
+// Tuner database: the cached choices as text, one entry per line, so a later
+// process applies them without timing.  Fields: the 11 key values, then the
+// forward's waves per workgroup, dedup, chunk and the measured ms.
+nqs_status nqs_tune_db_save(const char* path) {
+  if (!path) return fail(NQS_ERR_INVALID_ARGUMENT, "path is NULL");
+  std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return fail(NQS_ERR_INVALID_ARGUMENT, "cannot write %s", tmp.c_str());
+  fprintf(f, "# nqs tuner database v1: n L h precision K G entries_per_sample chunk dedup_auto device phase_mode"
+             " | waves dedup chunk ms\n");
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : g_tune_cache) {
+      const TuneKey& k = kv.first;
+      const TuneVal& v = kv.second;
+      fprintf(f, "%d %d %d %d %lld %lld %lld %lld %d %d %d | %d %d %lld %.6f\n", std::get<0>(k), std::get<1>(k),
+              std::get<2>(k), std::get<3>(k), (long long)std::get<4>(k), (long long)std::get<5>(k),
+              (long long)std::get<6>(k), (long long)std::get<7>(k), std::get<8>(k), std::get<9>(k), std::get<10>(k),
+              forward_variant_waves(std::get<3>(k), std::get<2>(k), v.variant), v.dedup ? 1 : 0, (long long)v.S,
+              v.ms);
+    }
+  }
+  const bool ok = fclose(f) == 0;
+  if (!ok || rename(tmp.c_str(), path) != 0) return fail(NQS_ERR_INVALID_ARGUMENT, "cannot write %s", path);
+  return NQS_OK;
+}
+
+nqs_status nqs_tune_db_load(const char* path, int* n_loaded) {
+  if (!path) return fail(NQS_ERR_INVALID_ARGUMENT, "path is NULL");
+  if (n_loaded) *n_loaded = 0;
+  FILE* f = fopen(path, "r");
+  if (!f) return fail(NQS_ERR_INVALID_ARGUMENT, "cannot read %s", path);
+  char line[512];
+  int n = 0, lineno = 0;
+  nqs_status st = NQS_OK;
+  while (fgets(line, sizeof(line), f)) {
+    ++lineno;
+    if (line[0] == '#' || line[0] == '\n') continue;
+    int a[11] = {};
+    long long b[4] = {};
+    int waves = 0, dedup = 0;
+    long long S = 0;
+    double ms = 0.0;
+    const int got = sscanf(line, "%d %d %d %d %lld %lld %lld %lld %d %d %d | %d %d %lld %lf", &a[0], &a[1], &a[2],
+                           &a[3], &b[0], &b[1], &b[2], &b[3], &a[8], &a[9], &a[10], &waves, &dedup, &S, &ms);
+    int v = -1;
+    if (got == 15 && a[3] >= 0 && a[3] <= NQS_BF16W && a[2] > 0)
+      for (int k = 0; k < forward_variants(a[3], a[2]); ++k)
+        if (forward_variant_waves(a[3], a[2], k) == waves) v = k;
+    if (v < 0 || S < 1 || S > b[3]) {
+      st = fail(NQS_ERR_INVALID_ARGUMENT, "%s:%d: not a tuner database entry", path, lineno);
+      break;
+    }
+    const TuneKey key{a[0], a[1], a[2], a[3], (int64_t)b[0], (int64_t)b[1], (int64_t)b[2], (int64_t)b[3], a[8], a[9],
+                      a[10]};
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = TuneVal{v, dedup != 0, (int64_t)S, ms};
+    ++n;
+  }
+  fclose(f);
+  if (n_loaded) *n_loaded = n;
+  return st;
 }
 
 nqs_status nqs_plan_configure(nqs_plan* p, int waves_per_block, int dedup, int64_t chunk_samples) {

@@ -269,3 +269,34 @@ def test_structured_tables_rejections(lib):
                         np.ones(1).ctypes.data, None, 1e-10, 8)
     h = C.c_void_p()
     assert lib.nqs_ham_create(C.byref(t), C.byref(h)) == 1                 # unknown flag
+
+
+def test_library_built_from_the_sources_beside_it(lib):
+    from paper_2208_05637_amd.build import source_hash
+    assert lib.nqs_source_hash().decode() == source_hash()
+
+
+def test_tune_db_round_trip(lib, tmp_path):
+    import paper_2208_05637_amd as nqs
+    # one entry per precision kind with a workgroup shape every width offers
+    src = tmp_path / "in.txt"
+    lines = ["# comment line",
+             "60 4 1024 4 1189663 244771 73125 3670 1 0 0 | 8 1 3670 987.500000",
+             "24 2 256 1 29737 5479 1818 147669 0 0 0 | 8 0 73834 12.250000"]
+    src.write_text("\n".join(lines) + "\n")
+    assert nqs.tune_db_load(src) == 2
+    out = tmp_path / "out.txt"
+    nqs.tune_db_save(out)
+    saved = [ln for ln in out.read_text().splitlines() if not ln.startswith("#")]
+    for ln in lines[1:]:
+        assert ln in saved
+    bad = tmp_path / "bad.txt"
+    bad.write_text("60 4 1024 4 | 8\n")
+    with pytest.raises(nqs.NQSError):
+        nqs.tune_db_load(bad)
+    # a workgroup shape the kernel does not have is rejected
+    bad.write_text("60 4 1024 4 1189663 244771 73125 3670 1 0 0 | 5 1 3670 1.0\n")
+    with pytest.raises(nqs.NQSError):
+        nqs.tune_db_load(bad)
+    with pytest.raises(nqs.NQSError):
+        nqs.tune_db_load(tmp_path / "missing.txt")
