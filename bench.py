@@ -418,6 +418,7 @@ def main():
         nqs.energy_grad(plan, params, x, w, eloc=eloc, energy=energy, grad=grad)
         torch.cuda.synchronize()
         warm_run += 1
+        log(f"warmup step {warm_run - 1} done at {elapsed():.1f}s")
 
     plan.profile(True)
     torch.cuda.synchronize()
@@ -426,6 +427,10 @@ def main():
     ev0.record(ctx.stream)
     for i in range(steps):
         nqs.energy_grad(plan, params, x, w, eloc=eloc, energy=energy, grad=grad)
+        if T_step > 2.0:
+            # a progress line per long step (the wait between steps costs microseconds of a step)
+            torch.cuda.synchronize()
+            log(f"timed step {i} done at {elapsed():.1f}s")
     ev1.record(ctx.stream)
     torch.cuda.synchronize()
     prof = plan.profile_read()
