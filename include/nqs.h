@@ -333,6 +333,23 @@ nqs_status nqs_energy_grad(nqs_plan* plan, const float* d_params, const uint64_t
                            const double* d_weights, int64_t B, double* d_eloc,
                            double* d_energy, double* d_grad, void* d_ws, size_t ws_bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc):
+   nqs_energy_grad with the library's own workspace, a static device array of
+   NQS_NOALLOC_SCRATCH_BYTES per GPU, held from the first context created on
+   that GPU until the process ends.  Calls no allocating routine.  Arguments
+   and results as nqs_energy_grad; d_flags (device uint32, may be NULL)
+   receives the call's device error word (NQS_DEV_* bits), which the call
+   clears at its start.  Fails with NQS_ERR_WORKSPACE_TOO_SMALL, before
+   anything is enqueued, when nqs_plan_workspace_size(plan, B) exceeds the
+   array (create the plan with a smaller max_batch or chunk).  Every call on
+   one GPU uses the same array: calls that overlap on that GPU (several
+   streams or threads) race, so the caller orders them.  Not profiled. */
+#define NQS_NOALLOC_SCRATCH_BYTES (256u << 20)
+nqs_status nqs_energy_grad_noalloc(nqs_plan* plan, const float* d_params, const uint64_t* d_samples,
+                                   const double* d_weights, int64_t B, double* d_eloc,
+                                   double* d_energy, double* d_grad, uint32_t* d_flags);
+
 /* Several independent (Hamiltonian, network, samples) instances in one call
    (the paper's independent units of work, Sec. 5.2).  Each instance uses
    its own plan (all plans on the same context) and its own part of d_ws,

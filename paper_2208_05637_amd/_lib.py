@@ -14,6 +14,7 @@ NQS_H_TABLES = 2
 NQS_PLAN_DEDUP_ON = 1
 NQS_PLAN_DEDUP_OFF = 2
 NQS_PLAN_DEDUP_AUTO = 4
+NQS_NOALLOC_SCRATCH_BYTES = 256 << 20
 NQS_TUNE_FORCE = 1
 NQS_TUNE_CACHE_ONLY = 2
 NQS_TUNE_MAX_CANDIDATES = 16
@@ -91,6 +92,7 @@ SIGNATURES = {
     "nqs_log_psi": (C.c_int, [_P, _P, _P, _I64, _P, _P, _SZ]),
     "nqs_local_energy": (C.c_int, [_P, _P, _P, _I64, _P, _P, _SZ]),
     "nqs_energy_grad": (C.c_int, [_P, _P, _P, _P, _I64, _P, _P, _P, _P, _SZ]),
+    "nqs_energy_grad_noalloc": (C.c_int, [_P, _P, _P, _P, _I64, _P, _P, _P, _P]),
     "nqs_multi_workspace_size": (C.c_int, [C.c_int, C.POINTER(Instance), C.POINTER(_SZ)]),
     "nqs_energy_grad_multi": (C.c_int, [C.c_int, C.POINTER(Instance), _P, _SZ]),
     "nqs_sample_workspace_size": (C.c_int, [_P, _I64, C.POINTER(_SZ)]),

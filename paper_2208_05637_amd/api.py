@@ -331,6 +331,31 @@ def energy_grad(plan, params, samples, weights=None, eloc=None, energy=None, gra
     return energy, grad, eloc
 
 
+def energy_grad_noalloc(plan, params, samples, weights=None, eloc=None, energy=None, grad=None, flags=None):
+    """energy_grad on the library's own static device workspace (no workspace
+    tensor): for callers that cannot allocate, e.g. under graph capture with
+    every output passed in.  Returns (energy, grad, eloc, flags), flags a
+    uint32 device tensor (viewed as int32) holding the call's error word."""
+    params = _params(plan, params)
+    dev = plan.ctx.device
+    x, B = _strings(samples, dev, plan.words)
+    w = None
+    if weights is not None:
+        w = _dev_tensor(torch.as_tensor(weights, dtype=torch.float64).to(dev).contiguous(), "weights",
+                        torch.float64, B, dev)
+    eloc = torch.empty((B, 2), dtype=torch.float64, device=dev) if eloc is None else eloc
+    energy = torch.empty(3, dtype=torch.float64, device=dev) if energy is None else energy
+    grad = torch.empty(plan.n_params, dtype=torch.float64, device=dev) if grad is None else grad
+    flags = torch.empty(1, dtype=torch.int32, device=dev) if flags is None else flags
+    _dev_tensor(eloc, "eloc", torch.float64, 2 * B, dev)
+    _dev_tensor(energy, "energy", torch.float64, 3, dev)
+    _dev_tensor(grad, "grad", torch.float64, plan.n_params, dev)
+    _dev_tensor(flags, "flags", torch.int32, 1, dev)
+    L.check(plan.lib.nqs_energy_grad_noalloc(plan.handle, _ptr(params), _ptr(x), _ptr(w), B, _ptr(eloc),
+                                             _ptr(energy), _ptr(grad), _ptr(flags)), "nqs_energy_grad_noalloc")
+    return energy, grad, eloc, flags
+
+
 def _instances(items):
     arr = (L.Instance * len(items))()
     for i, it in enumerate(items):

@@ -291,6 +291,28 @@ int nqs_version(void) { return 100; }
 #endif
 const char* nqs_source_hash(void) { return NQS_SOURCE_HASH; }
 
+// Workspace of the allocation-free entry point: one array per device, whose
+// address hipGetSymbolAddress gives once per device at context creation (in
+// host code the array's name is not a device address).
+static __device__ __align__(256) unsigned char scratch[NQS_NOALLOC_SCRATCH_BYTES];
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;   // device -> that device's copy of scratch
+
+// with `device` current
+nqs_status scratch_attach(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr.count(device)) return NQS_OK;
+  void* ptr = nullptr;
+  HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr || ((uintptr_t)ptr & 255)) return fail(NQS_ERR_HIP, "scratch array of device %d at %p", device, ptr);
+  g_scratch_ptr[device] = ptr;
+  return NQS_OK;
+}
+
+__global__ void copy_flags_kernel(const unsigned* src, unsigned* dst) { *dst = *src; }
+}  // namespace
+
 nqs_status nqs_ctx_create(int device, void* stream, nqs_ctx** out) {
   if (!out) return fail(NQS_ERR_INVALID_ARGUMENT, "out is NULL");
   *out = nullptr;
@@ -302,6 +324,8 @@ nqs_status nqs_ctx_create(int device, void* stream, nqs_ctx** out) {
   if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(NQS_ERR_UNSUPPORTED, "device arch %s is not gfx950", prop.gcnArchName);
   HIP_TRY(hipSetDevice(device));
+  const nqs_status sa = scratch_attach(device);
+  if (sa != NQS_OK) return sa;
   nqs_ctx* c = new nqs_ctx;
   c->device = device;
   c->stream = (hipStream_t)stream;
@@ -1038,6 +1062,38 @@ nqs_status nqs_energy_grad(nqs_plan* p, const float* params, const uint64_t* x, 
     if (t2) p->recs.push_back({t0, t2, 0, -1});
   }
   return launch_check("energy gradient");
+}
+
+nqs_status nqs_energy_grad_noalloc(nqs_plan* p, const float* params, const uint64_t* x, const double* w, int64_t B,
+                                   double* eloc, double* energy, double* grad, uint32_t* d_flags) {
+  if (!p) return fail(NQS_ERR_INVALID_ARGUMENT, "plan is NULL");
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(p->ctx->device);
+    if (it == g_scratch_ptr.end())
+      return fail(NQS_ERR_INVALID_ARGUMENT, "no scratch array attached for device %d", p->ctx->device);
+    ws = it->second;
+  }
+  if (B >= 1 && B <= p->max_batch) {
+    const size_t need = layout(p, B).total;
+    if (need > (size_t)NQS_NOALLOC_SCRATCH_BYTES)
+      return fail(NQS_ERR_WORKSPACE_TOO_SMALL,
+                  "%lld samples need %zu bytes of workspace with this plan; the allocation-free entry point has "
+                  "%zu (create the plan with a smaller batch or chunk)",
+                  (long long)B, need, (size_t)NQS_NOALLOC_SCRATCH_BYTES);
+  }
+  // no profiling: its events would be created here, and its slots live in the workspace
+  const bool prof = p->prof;
+  p->prof = false;
+  nqs_status st = nqs_energy_grad(p, params, x, w, B, eloc, energy, grad, ws, (size_t)NQS_NOALLOC_SCRATCH_BYTES);
+  p->prof = prof;
+  if (st == NQS_OK && d_flags) {
+    hipLaunchKernelGGL(copy_flags_kernel, dim3(1), dim3(1), 0, p->ctx->stream,
+                       (const unsigned*)((const char*)ws + layout(p, B).err), (unsigned*)d_flags);
+    st = launch_check("energy gradient (allocation-free): flags");
+  }
+  return st;
 }
 
 // Workspace of a multi-instance call: each instance's layout, 256-byte aligned, in order.

@@ -300,3 +300,11 @@ def test_tune_db_round_trip(lib, tmp_path):
         nqs.tune_db_load(bad)
     with pytest.raises(nqs.NQSError):
         nqs.tune_db_load(tmp_path / "missing.txt")
+
+
+def test_noalloc_scratch_size_matches_header():
+    import re
+    from paper_2208_05637_amd import _lib
+    h = open(os.path.join(ROOT, "include", "nqs.h")).read()
+    a, b = re.search(r"#define NQS_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", h).groups()
+    assert _lib.NQS_NOALLOC_SCRATCH_BYTES == int(a) << int(b)
