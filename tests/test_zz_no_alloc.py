@@ -35,13 +35,13 @@ def test_noalloc_equals_workspace_call(nqs, ctx, prec, L, h, dedup):
     H = nqs.Hamiltonian.from_terms(terms).upload(ctx)
     params = init_params(n, L, h, seed=1, dtype="bf16" if prec == "bf16w" else "fp32")
     xs, w = unique_with_counts(sector_samples(n, 3, 3, 2000, seed=2))
-    assert len(xs) == 400
+    assert len(xs) > 300
     plan = nqs.Plan(ctx, H, L, h, 3, 3, prec, max_batch=len(xs), dedup=dedup)
     assert plan.workspace_size(len(xs)) <= nqs._lib.NQS_NOALLOC_SCRATCH_BYTES
     p = torch.from_numpy(params).cuda()
     ref = pauli.canonical_terms(terms.x_mask, terms.z_mask, terms.coeff)
     net = made.Net(n=n, n_layers=L, width=h, n_up=3, n_dn=3)
-    for B in (400, 123):       # the second call is smaller and runs on the first call's leftovers
+    for B in (len(xs), 123):       # the second call is smaller and runs on the first call's leftovers
         print(f"noalloc {prec}: B = {B}", flush=True)
         e1, g1, l1 = nqs.energy_grad(plan, p, xs[:B], w[:B])
         e2, g2, l2, fl = nqs.energy_grad_noalloc(plan, p, xs[:B], w[:B])
