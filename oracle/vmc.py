@@ -48,15 +48,17 @@ def log_psi(net, params, configs_in, rows=32768):
     return la, phi
 
 
-def local_energy(terms, net, params, samples, batch_terms=4_000_000):
+def local_energy(terms, net, params, samples, batch_terms=4_000_000, scale=False):
     """E_loc(x_i) = sum_k ct_k (-1)^{popcount(x_i & z_k)} psi(x_i ^ x_k) / psi(x_i)  (Eq. local_energy_auto).
 
-    Returns complex128 [B].  Raises on a zero-amplitude sample.
+    Returns complex128 [B].  Raises on a zero-amplitude sample.  With
+    ``scale``, returns (E_loc, S) with S_i = sum_k |summand_k|, the magnitude
+    the rounding of the K-term sum is relative to.
     """
-    return local_energy_fn(terms, lambda c: log_psi(net, params, c), samples, batch_terms)
+    return local_energy_fn(terms, lambda c: log_psi(net, params, c), samples, batch_terms, scale)
 
 
-def local_energy_fn(terms, logpsi, samples, batch_terms=4_000_000):
+def local_energy_fn(terms, logpsi, samples, batch_terms=4_000_000, scale=False):
     """Eq. local_energy_auto for any amplitude given as ``logpsi(configs) -> (log|psi|, phase)``."""
     samples = configs(samples)
     xk, zk, ct = terms["x"], terms["z"], terms["ct"]
@@ -64,6 +66,7 @@ def local_energy_fn(terms, logpsi, samples, batch_terms=4_000_000):
     if np.any(~np.isfinite(la_s)):
         raise ValueError("sample with zero amplitude")
     out = np.empty(len(samples), dtype=np.complex128)
+    S = np.empty(len(samples))
     K = len(xk)
     per = max(1, batch_terms // max(K, 1))
     for start in range(0, len(samples), per):
@@ -82,7 +85,9 @@ def local_energy_fn(terms, logpsi, samples, batch_terms=4_000_000):
         summand = ct[None, :] * sign * ratio
         for i in range(xs.shape[0]):
             out[start + i] = complex(math.fsum(summand[i].real), math.fsum(summand[i].imag))
-    return out
+            if scale:
+                S[start + i] = math.fsum(np.abs(summand[i]))
+    return (out, S) if scale else out
 
 
 def energy(eloc, weights=None):

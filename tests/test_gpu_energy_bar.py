@@ -1,0 +1,214 @@
+"""The BF16-network workloads against the FP64 oracle at their full batches
+(Eq. total_energy_sum), and the 24-qubit FP32 workload's gradient against the
+oracle and central finite differences (Eq. grad), through the C ABI.
+
+Every batch is drawn from the workload's own network by the GPU unique-sample
+sampler (10^12 draws, counts as weights), as bench.py draws it, and the BF16
+path runs over the whole batch in the plan the benchmark uses.  Then, for each
+workload (for the four-instance workload, after one nqs_energy_grad_multi
+call over all four at full batches):
+  (1) the FP64 GPU path's local energies equal the oracle's on 16
+      configurations spread over the batch, to 1e-10 * S_i with
+      S_i = sum_k |summand_k| (the rounding scale of the K-term sum);
+  (2) the BF16 path's weighted mean of the local energies over 1,024
+      configurations spread over the batch is within 1e-5 Ha of the FP64 GPU
+      path's mean over the same configurations and weights.
+(1) ties the FP64 GPU path to the oracle; (2) carries the 1e-5 Ha bar from it
+to the BF16 path.  Per-sample BF16 errors (~1e-5 to 1e-4 Ha at these widths)
+are printed: the bar is on the mean.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import made, pauli, vmc
+from gen import config_inputs, hamiltonian, init_params
+
+pytestmark = pytest.mark.gpu
+
+BAR_HA = 1e-5
+
+
+@pytest.fixture(scope="module")
+def nqs():
+    import paper_2208_05637_amd as m
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(nqs):
+    return nqs.Context(0)
+
+
+def _closed_conn(N, nu, nd):
+    t = 1
+    for s in (nu, nd):
+        t += s * (N - s) + math.comb(s, 2) * math.comb(N - s, 2)
+    return t + nu * (N - nu) * nd * (N - nd)
+
+
+def _workload(nqs, ctx, name):
+    """(terms, H, params numpy, params device, cfg, x, w, plan): the batch drawn from the network."""
+    terms, params_np, _, _, cfg = config_inputs(name, batch=16)
+    H = nqs.Hamiltonian.from_terms(terms).upload(ctx)
+    p = torch.from_numpy(params_np).cuda()
+    mk = lambda mb: nqs.Plan(ctx, H, cfg["L"], cfg["h"], cfg["n_up"], cfg["n_dn"], cfg["precision"], max_batch=mb,
+                             dedup=cfg["dedup"])
+    x, w = nqs.sample(mk(16), p, 10**12, seed=2, max_unique=cfg["B"])
+    assert x.shape[0] == cfg["B"] and float(w.sum()) <= 1e12 and bool((w > 0).all())
+    return terms, H, params_np, p, cfg, x, w, mk(cfg["B"])
+
+
+def _bar(nqs, ctx, terms, H, cfg, params_np, p, x, w, el_b, label):
+    B = x.shape[0]
+    xs = x.cpu().numpy().view(np.uint64)
+    wn = w.cpu().numpy()
+    sub = np.unique(np.linspace(0, B - 1, min(B, 1024)).astype(np.int64))
+    assert len(sub) >= min(B, 1024)
+    p64 = nqs.Plan(ctx, H, cfg["L"], cfg["h"], cfg["n_up"], cfg["n_dn"], "fp64", max_batch=len(sub),
+                   dedup=cfg["n"] != 64)
+    el64 = nqs.local_energy(p64, p, xs[sub]).cpu().numpy()
+    assert nqs.device_status(p64) == 0
+    j16 = np.unique(np.linspace(0, len(sub) - 1, 16).astype(np.int64))
+    ref = pauli.canonical_terms(terms.x_mask, terms.z_mask, terms.coeff)
+    net = made.Net(n=cfg["n"], n_layers=cfg["L"], width=cfg["h"], n_up=cfg["n_up"], n_dn=cfg["n_dn"])
+    el_ref, S = vmc.local_energy(ref, net, params_np, xs[sub[j16]], scale=True)
+    d64 = np.abs(el64[j16, 0] + 1j * el64[j16, 1] - el_ref)
+    ws = wn[sub]
+    Eb = math.fsum(ws * el_b[sub, 0]) / math.fsum(ws)
+    E64 = math.fsum(ws * el64[:, 0]) / math.fsum(ws)
+    dps = np.abs(el_b[sub, 0] - el64[:, 0])
+    print(f"{label}: FP64 GPU vs oracle max |dE_loc|/S_i = {np.max(d64 / S):.2e}; BF16 mean over {len(sub)} "
+          f"samples {Eb:.10f} vs FP64 {E64:.10f}, |dE| = {abs(Eb - E64):.2e} Ha; per-sample max "
+          f"{dps.max():.2e}, median {np.median(dps):.2e} Ha")
+    assert np.all(d64 <= 1e-10 * S)
+    assert abs(Eb - E64) <= BAR_HA
+
+
+def test_energy_bar_40_qubits(nqs, ctx):
+    terms, H, params_np, p, cfg, x, w, plan = _workload(nqs, ctx, "c3")
+    N = cfg["N"]
+    assert plan.entries_per_sample == _closed_conn(N, N // 2, N // 2) - 1
+    energy, grad, eloc = nqs.energy_grad(plan, p, x, w)
+    torch.cuda.synchronize()
+    assert nqs.device_status(plan) == 0
+    el = eloc.cpu().numpy()
+    wn = w.cpu().numpy()
+    E = math.fsum(wn * el[:, 0]) / math.fsum(wn)
+    assert abs(E - energy[0].item()) <= 1e-12 * abs(E)
+    assert bool(torch.isfinite(grad).all())
+    _bar(nqs, ctx, terms, H, cfg, params_np, p, x, w, el, "40 qubits, 32,768 sampled")
+
+
+def test_energy_bar_60_qubits(nqs, ctx):
+    """The benchmark's workload at full size in its launch configuration (65,536 sampled configurations,
+    3,670-sample chunks, the tuned workgroup shape and dedup of the committed tuner database)."""
+    import os
+    terms, H, params_np, p, cfg, x, w, plan = _workload(nqs, ctx, "c4")
+    N = cfg["N"]
+    assert plan.entries_per_sample == _closed_conn(N, N // 2, N // 2) - 1
+    assert plan.chunk_samples == (256 << 20) // 73125
+    db = os.path.join(os.path.dirname(nqs.LIB_PATH), "tune_db.txt")
+    nqs.tune_db_load(db)
+    assert plan.autotune(p, x[:1], cache_only=True)["from_cache"]
+    energy, grad, eloc = nqs.energy_grad(plan, p, x, w)
+    torch.cuda.synchronize()
+    assert nqs.device_status(plan) == 0
+    el, wn = eloc.cpu().numpy(), w.cpu().numpy()
+    e = energy.cpu().numpy()
+    E = math.fsum(wn * el[:, 0]) / math.fsum(wn)
+    assert abs(E - e[0]) <= 1e-12 * abs(E) and e[2] == math.fsum(wn)
+    assert bool(torch.isfinite(grad).all())
+    _bar(nqs, ctx, terms, H, cfg, params_np, p, x, w, el, "60 qubits, 65,536 sampled")
+
+
+def test_energy_bar_four_instances_one_call(nqs, ctx):
+    """16/28/44/64 qubits at 4,096/16,384/32,768/16,384 sampled configurations, one nqs_energy_grad_multi
+    call; each instance equals its single call bit for bit and meets the bar."""
+    items, refs = [], []
+    dev = ctx.device
+    for name in ("c5a", "c5b", "c5c", "c5d"):
+        terms, H, params_np, p, cfg, x, w, plan = _workload(nqs, ctx, name)
+        B = x.shape[0]
+        items.append(dict(plan=plan, params=p, samples=x, weights=w,
+                          eloc=torch.empty((B, 2), dtype=torch.float64, device=dev),
+                          energy=torch.empty(3, dtype=torch.float64, device=dev),
+                          grad=torch.empty(plan.n_params, dtype=torch.float64, device=dev)))
+        refs.append((terms, H, params_np, cfg))
+    ws = nqs.multi_workspace(items)
+    nqs.energy_grad_multi(items, ws)
+    torch.cuda.synchronize()
+    for it, (terms, H, params_np, cfg) in zip(items, refs):
+        assert nqs.device_status(it["plan"]) == 0
+        e1, g1, l1 = nqs.energy_grad(it["plan"], it["params"], it["samples"], it["weights"])
+        assert torch.equal(l1, it["eloc"]) and torch.equal(g1, it["grad"]) and torch.equal(e1, it["energy"])
+        _bar(nqs, ctx, terms, H, cfg, params_np, it["params"], it["samples"], it["weights"],
+             it["eloc"].cpu().numpy(), f"{cfg['n']} qubits in the four-instance call, {it['samples'].shape[0]}")
+
+
+def test_24_qubits_gradient_oracle_and_central_fd(nqs, ctx):
+    """24 qubits, L = 2, h = 256, FP32 path with the hand backward: 8,192 draws from the network (all kept:
+    unique configurations with counts).  Local energies against the oracle on 64 of them; the gradient
+    against the oracle's gradient over the whole batch (given the FP64 GPU local energies, which the first
+    check pins); and 20 random parameters (seed 3) against central differences, h = 1e-4, of the
+    frozen-local-energy surrogate F(theta) = sum_i (w_i/W) 2 [(Re l_i - E) log|psi_theta(x_i)| +
+    Im l_i phi_theta(x_i)], whose gradient is Eq. grad's estimator, with log psi from the GPU FP64 path."""
+    N, n, L, h = 12, 24, 2, 256
+    terms = hamiltonian(N, 0)
+    H = nqs.Hamiltonian.from_terms(terms).upload(ctx)
+    params_np = init_params(n, L, h, seed=1)
+    p = torch.from_numpy(params_np).cuda()
+    x, w = nqs.sample(nqs.Plan(ctx, H, L, h, 6, 6, "fp32", max_batch=16), p, 8192, seed=2, max_unique=8192)
+    assert float(w.sum()) == 8192.0
+    B = x.shape[0]
+    xs, wn = x.cpu().numpy().view(np.uint64), w.cpu().numpy()
+    p32 = nqs.Plan(ctx, H, L, h, 6, 6, "fp32", max_batch=B)
+    p64 = nqs.Plan(ctx, H, L, h, 6, 6, "fp64", max_batch=B, dedup=True)
+    E32, g32, l32 = (t.cpu().numpy() for t in nqs.energy_grad(p32, p, x, w))
+    E64, g64, l64 = (t.cpu().numpy() for t in nqs.energy_grad(p64, p, x, w))
+    assert nqs.device_status(p32) == 0 and nqs.device_status(p64) == 0
+    ref = pauli.canonical_terms(terms.x_mask, terms.z_mask, terms.coeff)
+    net = made.Net(n=n, n_layers=L, width=h, n_up=6, n_dn=6)
+    j = np.unique(np.linspace(0, B - 1, 64).astype(np.int64))
+    el_ref, S = vmc.local_energy(ref, net, params_np, xs[j], scale=True)
+    d64 = np.abs(l64[j, 0] + 1j * l64[j, 1] - el_ref)
+    d32 = np.abs(l32[j, 0] + 1j * l32[j, 1] - el_ref)
+    assert np.all(d64 <= 1e-10 * S) and np.all(d32 <= 1e-4 * S)
+    l64c = l64[:, 0] + 1j * l64[:, 1]
+    E_ref, _, _ = vmc.energy(l64c, wn)
+    assert abs(E64[0] - E_ref) <= 1e-12 * abs(E_ref)
+    g_ref = vmc.gradient(net, params_np, xs, wn, l64c, E_ref)
+    r64 = np.linalg.norm(g64 - g_ref) / np.linalg.norm(g_ref)
+    r32 = np.linalg.norm(g32 - g_ref) / np.linalg.norm(g_ref)
+    assert r64 <= 1e-9 and r32 <= 1e-4
+    assert abs(E32[0] - E64[0]) <= 1e-4
+
+    W = math.fsum(wn)
+
+    def surrogate(theta, l, Ebar):
+        lp = nqs.log_psi(p64, theta, x).cpu().numpy()
+        return math.fsum(wn * 2.0 * ((l[:, 0] - Ebar) * lp[:, 0] + l[:, 1] * lp[:, 1])) / W
+
+    rng = np.random.default_rng(3)
+    idx = [int(k) for k in rng.permutation(len(params_np)) if g64[k] != 0.0][:20]
+    assert len(idx) == 20
+    worst64 = worst32 = 0.0
+    for k in idx:
+        tp, tm = p.clone(), p.clone()
+        tp[k] += 1e-4
+        tm[k] -= 1e-4
+        dh = float(tp[k].item()) - float(tm[k].item())
+        fd64 = (surrogate(tp, l64, E64[0]) - surrogate(tm, l64, E64[0])) / dh
+        fd32 = (surrogate(tp, l32, E32[0]) - surrogate(tm, l32, E32[0])) / dh
+        worst64 = max(worst64, abs(fd64 - g64[k]))
+        worst32 = max(worst32, abs(fd32 - g32[k]))
+    gmax = np.max(np.abs(g64))
+    print(f"24 qubits, {B} configurations: |dg|/|g| FP64 {r64:.2e}, FP32 {r32:.2e}; central FD on 20 parameters: "
+          f"max |FD - g| / max|g| = {worst64 / gmax:.2e} (FP64 path), {worst32 / gmax:.2e} (FP32 path)")
+    # the FD truncation error is h^2/6 F''' plus, where a +-h step crosses a ReLU kink for some sample, up to
+    # (w_i/W) x slope x h/2 for that sample: ~1e-8 here, well under this bar
+    assert worst64 <= 1e-5 * gmax
+    assert worst32 <= 2e-4 * gmax

@@ -74,66 +74,3 @@ def test_40_qubits_full_batch_sampled(nqs, ctx, name, prec, tol):
     print(f"{name} {prec}: sampled |dE_loc| = {d}, E = {energy[0]:.10f}")
     assert np.all(d <= tol)
     assert np.all(np.isfinite(grad))
-
-
-def test_four_instances_one_call(nqs, ctx):
-    """16/28/44/64 qubits, each with its own H, network and samples, in one nqs_energy_grad_multi."""
-    items, refs = [], []
-    plans = []
-    for name, B in (("c5a", 512), ("c5b", 256), ("c5c", 128), ("c5d", 64)):
-        terms, params, xs, w, cfg = config_inputs(name, batch=B)
-        H = nqs.Hamiltonian.from_terms(terms).upload(ctx)
-        plan = nqs.Plan(ctx, H, cfg["L"], cfg["h"], cfg["n_up"], cfg["n_dn"], cfg["precision"],
-                        max_batch=len(xs), dedup=cfg["dedup"])
-        plans.append((plan, H))
-        dev = ctx.device
-        it = dict(plan=plan, params=torch.from_numpy(params).to(dev),
-                  samples=torch.from_numpy(xs.view(np.int64)).to(dev),
-                  weights=torch.from_numpy(w).to(dev),
-                  eloc=torch.empty((len(xs), 2), dtype=torch.float64, device=dev),
-                  energy=torch.empty(3, dtype=torch.float64, device=dev),
-                  grad=torch.empty(plan.n_params, dtype=torch.float64, device=dev))
-        items.append(it)
-        refs.append((terms, params, xs, w, cfg))
-    ws = nqs.multi_workspace(items)
-    nqs.energy_grad_multi(items, ws)
-    torch.cuda.synchronize()
-    for it, (terms, params, xs, w, cfg) in zip(items, refs):
-        el = it["eloc"].cpu().numpy()
-        # each instance equals its own single-instance call
-        e1, g1, l1 = nqs.energy_grad(it["plan"], it["params"], it["samples"], it["weights"])
-        assert torch.equal(l1, it["eloc"]) and torch.equal(g1, it["grad"]) and torch.equal(e1, it["energy"])
-        el_ref = _oracle_eloc(terms, cfg, params, xs[:2])
-        d = np.abs(el[:2, 0] + 1j * el[:2, 1] - el_ref)
-        print(f"{cfg['n']} qubits: |dE_loc| = {d}")
-        assert np.all(d <= 2e-3)
-
-
-def test_60_qubits_full_batch_sampled(nqs, ctx):
-    """The benchmark's workload at full size, in its launch configuration: 65,536 unique
-    configurations drawn from the 60-qubit BF16 network by the GPU sampler (10^12 draws),
-    energy and gradient over all of them; sampled local energies against the oracle."""
-    terms, params, _, _, cfg = config_inputs("c4")
-    H = nqs.Hamiltonian.from_terms(terms).upload(ctx)
-    mk = lambda mb: nqs.Plan(ctx, H, cfg["L"], cfg["h"], cfg["n_up"], cfg["n_dn"], cfg["precision"],
-                             max_batch=mb, dedup=cfg["dedup"])
-    p = torch.from_numpy(params).cuda()
-    x, w = nqs.sample(mk(16), p, 10**12, seed=2, max_unique=cfg["B"])
-    assert x.numel() == cfg["B"] and float(w.sum()) <= 1e12 and bool((w > 0).all())
-    plan = mk(cfg["B"])
-    N = cfg["N"]
-    assert plan.entries_per_sample == _closed_conn(N, N // 2, N // 2) - 1
-    assert plan.kernel_info()["waves_per_block"] == 16 and plan.chunk_samples == (256 << 20) // 73125
-    energy, grad, eloc = nqs.energy_grad(plan, p, x, w)
-    torch.cuda.synchronize()
-    assert nqs.device_status(plan) == 0
-    energy, grad, eloc, wn = energy.cpu().numpy(), grad.cpu().numpy(), eloc.cpu().numpy(), w.cpu().numpy()
-    E = math.fsum(wn * eloc[:, 0]) / math.fsum(wn)
-    assert abs(E - energy[0]) <= 1e-12 * abs(E) and energy[2] == math.fsum(wn)
-    xs = x.cpu().numpy().view(np.uint64)
-    idx = np.array([0, len(xs) - 1])
-    el_ref = _oracle_eloc(terms, cfg, params, xs[idx])
-    d = np.abs(eloc[idx, 0] + 1j * eloc[idx, 1] - el_ref)
-    print(f"c4 bf16w, 65,536 sampled configurations: sampled |dE_loc| = {d}, E = {energy[0]:.10f}")
-    assert np.all(d <= 1e-3)
-    assert np.all(np.isfinite(grad))

@@ -192,3 +192,23 @@ def test_energy_weights_and_exact_sum():
     el = np.array([1e16 + 1j, 1.0, -1e16 - 1j, 3.0])
     E, I, W = vmc.energy(el, [1, 1, 1, 1])
     assert E == 1.0 and I == 0.0 and W == 4.0
+
+
+@pytest.mark.parametrize("N,nu,nd", [(3, 1, 2), (4, 2, 2)])
+def test_local_energy_scale_is_sum_of_absolute_summands(N, nu, nd):
+    """S_i from local_energy(scale=True) equals sum_k |c_k| |psi(x ^ x_k)| / |psi(x)| built from the dense
+    sector amplitudes and the unmerged per-term products (the sign and phase drop out of |.|), and
+    bounds |E_loc| (the triangle inequality)."""
+    n = 2 * N
+    terms = _terms(N)
+    net = made.Net(n=n, n_layers=2, width=16, n_up=nu, n_dn=nd)
+    params = init_params(n, 2, 16, seed=7, std=0.5)
+    basis = pauli.sector_basis(n, nu, nd)
+    la, ph, _ = made.forward(net, params, basis)
+    amp = dict(zip(basis.tolist(), np.exp(la).tolist()))
+    el, S = vmc.local_energy(terms, net, params, basis, scale=True)
+    assert np.allclose(el, vmc.local_energy(terms, net, params, basis), rtol=0, atol=0)
+    for i, x in enumerate(basis.tolist()):
+        ref = sum(abs(c) * amp.get(x ^ int(xk), 0.0) / amp[x] for xk, c in zip(terms["x"].tolist(), terms["ct"]))
+        assert abs(S[i] - ref) <= 1e-13 * ref
+        assert abs(el[i]) <= S[i] * (1 + 1e-13)
