@@ -194,21 +194,29 @@ def test_24_qubits_gradient_oracle_and_central_fd(nqs, ctx):
 
     rng = np.random.default_rng(3)
     idx = [int(k) for k in rng.permutation(len(params_np)) if g64[k] != 0.0][:20]
-    assert len(idx) == 20
-    worst64 = worst32 = 0.0
-    for k in idx:
+    # the heads' parameters (W_o, b_o, W_phi, b_phi at the end of the flat layout) enter log|psi| and phi
+    # through no ReLU, so their central differences carry only the O(h^2) truncation
+    head0 = h * n + h + (L - 1) * (h * h + h)
+    head = [int(k) for k in head0 + rng.permutation(len(params_np) - head0) if g64[k] != 0.0][:10]
+    assert len(idx) == 20 and len(head) == 10
+
+    def fd(k, l, Ebar):
         tp, tm = p.clone(), p.clone()
         tp[k] += 1e-4
         tm[k] -= 1e-4
         dh = float(tp[k].item()) - float(tm[k].item())
-        fd64 = (surrogate(tp, l64, E64[0]) - surrogate(tm, l64, E64[0])) / dh
-        fd32 = (surrogate(tp, l32, E32[0]) - surrogate(tm, l32, E32[0])) / dh
-        worst64 = max(worst64, abs(fd64 - g64[k]))
-        worst32 = max(worst32, abs(fd32 - g32[k]))
+        return (surrogate(tp, l, Ebar) - surrogate(tm, l, Ebar)) / dh
+
     gmax = np.max(np.abs(g64))
-    print(f"24 qubits, {B} configurations: |dg|/|g| FP64 {r64:.2e}, FP32 {r32:.2e}; central FD on 20 parameters: "
-          f"max |FD - g| / max|g| = {worst64 / gmax:.2e} (FP64 path), {worst32 / gmax:.2e} (FP32 path)")
-    # the FD truncation error is h^2/6 F''' plus, where a +-h step crosses a ReLU kink for some sample, up to
-    # (w_i/W) x slope x h/2 for that sample: ~1e-8 here, well under this bar
-    assert worst64 <= 1e-5 * gmax
-    assert worst32 <= 2e-4 * gmax
+    d64 = np.array([abs(fd(k, l64, E64[0]) - g64[k]) for k in idx]) / gmax
+    d32 = np.array([abs(fd(k, l32, E32[0]) - g32[k]) for k in idx]) / gmax
+    dh64 = np.array([abs(fd(k, l64, E64[0]) - g64[k]) for k in head]) / gmax
+    print(f"24 qubits, {B} configurations: |dg|/|g| FP64 {r64:.2e}, FP32 {r32:.2e}; central FD (h = 1e-4), "
+          f"max |FD - g| / max|g|: 20 random parameters {d64.max():.2e} (FP64 path), {d32.max():.2e} (FP32 path); "
+          f"10 head parameters {dh64.max():.2e} (FP64 path)")
+    # A +-h step that moves a hidden pre-activation across 0 for some sample makes that sample's term
+    # non-smooth inside the step: its FD error is up to (w_i/W) 2|l_i - E| |d log psi / d a| h / 2 (measured:
+    # 2.9e-5 of max|g| on one of the 20, identical for both paths, while the smooth head parameters agree to
+    # ~1e-12).
+    assert d64.max() <= 1e-4 and d32.max() <= 2e-4
+    assert dh64.max() <= 1e-7
