@@ -224,9 +224,8 @@ typedef struct {
 nqs_status nqs_net_param_count(const nqs_net_desc* net, int64_t* n_params);
 
 /* --------------------------------------------------------------------- plan */
-/* Dedup applies at every width except exactly 64 qubits, where the one-word
-   table's all-ones empty marker is a valid string (the flags are accepted
-   and dedup stays off). */
+/* Dedup applies at every width (Sec. 5.2, local removal of replicated
+   configurations). */
 #define NQS_PLAN_DEDUP_ON   1u   /* deduplicate connected configurations per chunk */
 #define NQS_PLAN_DEDUP_OFF  2u   /* never deduplicate (default when no flag is set) */
 #define NQS_PLAN_DEDUP_AUTO 4u   /* size the workspace for dedup, start with it on and
@@ -386,9 +385,11 @@ nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* d_w
  * and beyond max_unique entries those with the fewest draws are eliminated
  * (ties: earlier buffer entries kept; the buffer is ordered by the bits in
  * sampling order).  Random numbers: Philox4x64-10, counter (the parent's
- * word 0, t, its word 1 (0 up to 64 qubits), 0), key (seed, 0); Bin(c, p) by inversion from 0 when
- * c min(p, 1-p) < 32, else the normal approximation with continuity
- * correction (Box-Muller), reflected for p > 1/2.
+ * word 0, t, its word 1 (0 up to 64 qubits), j) for blocks j = 0, 1, ...,
+ * key (seed, 0); Bin(c, p), exact: by inversion from 0 when
+ * c min(p, 1-p) < 32 (first uniform of block 0), else Hormann's BTRS
+ * rejection method (1993; two uniforms per attempt, in block order),
+ * reflected for p > 1/2.
  * Outputs (device): d_x[u] configurations (W uint64 words each), d_w[u]
  * their draw counts as f64 weights, d_n_unique[0] = U <= max_unique, for
  * u < U in buffer order.  d_x and d_w hold max_unique entries.  The network

@@ -24,12 +24,25 @@ buffer.
 
 Random numbers: Philox4x64-10 (Salmon, Moraes, Dror and Shaw, "Parallel random
 numbers: as easy as 1, 2, 3", SC 2011), counter (x_parent mod 2^64, t,
-x_parent >> 64, 0) (the last two words are zero up to 64 qubits), key (seed, 0).  Binomial draw Bin(c, p) from the counter's first two outputs:
-with q = min(p, 1 - p), inversion of the distribution function summed from
-k = 0 when c q < 32 (stopping where the terms underflow to zero, which bounds
-the search when u lies above the rounded total), otherwise the normal approximation
-floor(c q + z sqrt(c q (1 - q)) + 1/2) clamped to [0, c] with z from the
-Box-Muller transform; reflected (c - k) when p > 1/2.
+x_parent >> 64, j) (the third word is zero up to 64 qubits), key (seed, 0);
+block j = 0, 1, ... gives four 64-bit words, each a uniform in [0, 1) from its
+top 53 bits.  Binomial draw Bin(c, p), q = min(p, 1 - p), reflected (c - k)
+when p > 1/2, exact in both branches:
+  * c q < 32: inversion of the distribution function summed from k = 0 with
+    the first uniform of block 0 (stopping where the terms underflow to zero,
+    which bounds the search when u lies above the rounded total);
+  * otherwise Hormann's BTRS, transformed rejection with squeeze (W. Hormann,
+    "The generation of binomial random variates", J. Statist. Comput. Simul.
+    46 (1993) 101-110): each attempt takes the next two uniforms (block 0's
+    words 0 and 1, then 2 and 3, then block 1's ...), accepts in the squeeze
+    region, else compares log V with the log of the probability ratio
+    f(k)/f(m) at the mode m.  That log is written as differences of
+    log-factorials, log(a!/b!) = d log(b+1) + (a + 1/2) log1p(d/(b+1)) - d +
+    fc(a) - fc(b) with d = a - b and fc the Stirling correction, so that its
+    rounding stays at the size of the result for counts up to 10^12 (the
+    difference of two lgamma values of 10^12 would lose five digits).
+    Attempts are capped at 4096 (never reached in practice: each accepts with
+    probability above 0.75); at the cap the draw is the mode.
 """
 import math
 
@@ -71,16 +84,82 @@ def uniform53(word):
     return (int(word) >> 11) * (1.0 / 9007199254740992.0)
 
 
-def binomial(c, p, u1, u2):
-    """Bin(c, p) from two uniforms in [0, 1) (see the module docstring)."""
+def _stirling_corr(k):
+    """fc(k) = log(k!) - [(k + 1/2) log(k + 1) - (k + 1) + log(2 pi) / 2]."""
+    if k < 16:
+        return math.lgamma(k + 1.0) - ((k + 0.5) * math.log(k + 1.0) - (k + 1.0) + 0.5 * math.log(2.0 * math.pi))
+    x = k + 1.0
+    x2 = x * x
+    return (1.0 / 12.0 - (1.0 / 360.0 - (1.0 / 1260.0 - (1.0 / 1680.0) / x2) / x2) / x2) / x
+
+
+def log_fact_ratio(a, b):
+    """log(a! / b!) for integers a >= b >= 0 (stable when a - b << b)."""
+    d = a - b
+    if d == 0:
+        return 0.0
+    return (d * math.log(b + 1.0) + (a + 0.5) * math.log1p(d / (b + 1.0)) - d
+            + _stirling_corr(a) - _stirling_corr(b))
+
+
+class Uniforms:
+    """The uniforms of one draw: words of Philox blocks j = 0, 1, ... of a counter."""
+
+    def __init__(self, ctr3, key):
+        self.ctr3, self.key, self.j, self.words = list(ctr3), key, 0, []
+
+    def next(self):
+        if not self.words:
+            self.words = philox4x64_10(self.ctr3 + [self.j], self.key)
+            self.j += 1
+        return uniform53(self.words.pop(0))
+
+
+MAX_ATTEMPTS = 4096
+
+
+def _btrs(n, p, uni):
+    """Bin(n, p) for p <= 1/2 and n p >= SMALL_MEAN by Hormann's BTRS."""
+    q = 1.0 - p
+    spq = math.sqrt(n * p * q)
+    b = 1.15 + 2.53 * spq
+    a = -0.0873 + 0.0248 * b + 0.01 * p
+    c = n * p + 0.5
+    vr = 0.92 - 4.2 / b
+    alpha = (2.83 + 5.1 / b) * spq
+    lpq = math.log(p / q)
+    m = math.floor((n + 1) * p)
+    for _ in range(MAX_ATTEMPTS):
+        u = uni.next() - 0.5
+        v = uni.next()
+        us = 0.5 - abs(u)
+        k = math.floor((2.0 * a / us + b) * u + c if us > 0.0 else -1.0)   # us = 0 only at u = -1/2
+        if us >= 0.07 and v <= vr:
+            return k
+        if k < 0 or k > n:
+            continue
+        v = v * alpha / (a / (us * us) + b)
+        # log f(k)/f(m) = log(m!/k!) + log((n-m)!/(n-k)!) + (k - m) log(p/q)
+        if k >= m:
+            lr = -log_fact_ratio(k, m) + log_fact_ratio(n - m, n - k)
+        else:
+            lr = log_fact_ratio(m, k) - log_fact_ratio(n - k, n - m)
+        if v == 0.0 or math.log(v) <= lr + (k - m) * lpq:                     # log 0 = -inf
+            return k
+    return m
+
+
+def binomial(c, p, uni):
+    """Bin(c, p) with the uniforms of `uni` (see the module docstring)."""
     c = int(c)
-    if c == 0 or p <= 0.0:
+    if c == 0 or not (p > 0.0):
         return 0
-    if p >= 1.0:
+    if not (p < 1.0):
         return c
     flip = p > 0.5
     q = 1.0 - p if flip else p
     if c * q < SMALL_MEAN:
+        u1 = uni.next()
         r = q / (1.0 - q)
         pk = math.exp(c * math.log1p(-q))
         F = pk
@@ -90,17 +169,14 @@ def binomial(c, p, u1, u2):
             k += 1
             F += pk
     else:
-        z = math.sqrt(-2.0 * math.log(1.0 - u1)) * math.cos(2.0 * math.pi * u2)
-        k = math.floor(c * q + z * math.sqrt(c * q * (1.0 - q)) + 0.5)
-        k = min(max(k, 0), c)
+        k = _btrs(c, q, uni)
     return c - k if flip else k
 
 
 def split_draws(count, p1, x_parent, t, seed):
     """Draws of the child with x = 1 out of `count`."""
     x_parent = int(x_parent)
-    w = philox4x64_10((x_parent & _MASK, t, x_parent >> 64, 0), (seed, 0))
-    return binomial(count, p1, uniform53(w[0]), uniform53(w[1]))
+    return binomial(count, p1, Uniforms((x_parent & _MASK, t, x_parent >> 64), (seed, 0)))
 
 
 def conditionals(net: made.Net, params, xs, t):

@@ -376,9 +376,9 @@ void launch_seg_offsets(const int* esample, long long n_entries, long long B, lo
 // ------------------------------------------------------------------ dedup
 // Two-level open addressing: each workgroup first collapses its tile of
 // entries in an LDS table, then inserts only the tile-unique keys into the
-// global table.  Keys are x' values; the all-ones word marks an empty slot
-// (the plan disables deduplication at n = 64, the only width where it is a
-// valid configuration).  Each global slot also records the first entry that
+// global table.  Keys are x' values; the all-ones word marks an empty slot,
+// which below 64 qubits is no configuration (at exactly 64 qubits, and for
+// two-word keys, the slot-word insert below is used instead).  Each global slot also records the first entry that
 // holds its key; the distinct configurations are then listed in the order of
 // their first entries (sample-major, as the entries are), so rows that follow
 // each other in the forward stay alike, and the list does not depend on the
@@ -456,13 +456,15 @@ __global__ __launch_bounds__(512) void dedup_insert_kernel(const uint64_t* __res
   }
 }
 
-// Two-word keys: one lane per entry, straight into the global table.  A slot
-// word holds (tag << 32) | the entry that inserted the key (entries < 2^28,
-// so a slot word is never the all-ones empty marker); a probe whose tag
-// matches compares the full key with that entry's words in xe, which earlier
-// kernels wrote, so no lane waits on another.
+// Keys of any width (two-word keys, and one-word keys at exactly 64 qubits,
+// where every word is a configuration): one lane per entry, straight into the
+// global table.  A slot word holds (tag << 32) | the entry that inserted the
+// key (entries < 2^28, so a slot word is never the all-ones empty marker); a
+// probe whose tag matches compares the full key with that entry's words in
+// xe, which earlier kernels wrote, so no lane waits on another.
 // eu[e] <- global slot of entry e's key; owner[slot] <- smallest entry holding it.
-__global__ __launch_bounds__(256) void dedup_insert_wide_kernel(const uint64_t* __restrict__ xe,
+template <int W>
+__global__ __launch_bounds__(256) void dedup_insert_slot_kernel(const uint64_t* __restrict__ xe,
                                                                 const long long* __restrict__ d_count,
                                                                 long long cap,
                                                                 unsigned long long* __restrict__ hkeys,
@@ -472,8 +474,10 @@ __global__ __launch_bounds__(256) void dedup_insert_wide_kernel(const uint64_t* 
   if (count > cap) count = cap;
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= count) return;
-  const uint64_t lo = xe[2 * e], hi = xe[2 * e + 1];
-  const unsigned long long hsh = mix64(lo ^ mix64(hi));
+  uint64_t key[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) key[k] = xe[W * e + k];
+  const unsigned long long hsh = W == 2 ? mix64(key[0] ^ mix64(key[W - 1])) : mix64(key[0]);
   const unsigned long long mine = (hsh & 0xFFFFFFFF00000000ull) | (unsigned long long)e;
   const unsigned long long hmask = (unsigned long long)HT - 1;
   unsigned long long gs = hsh & hmask;
@@ -483,7 +487,10 @@ __global__ __launch_bounds__(256) void dedup_insert_wide_kernel(const uint64_t* 
     if (prev == kEmpty) { found = (int)gs; break; }
     if ((prev >> 32) == (mine >> 32)) {
       const long long pe = (long long)(prev & 0xFFFFFFFFull);
-      if (xe[2 * pe] == lo && xe[2 * pe + 1] == hi) { found = (int)gs; break; }
+      bool same = true;
+#pragma unroll
+      for (int k = 0; k < W; ++k) same = same && xe[W * pe + k] == key[k];
+      if (same) { found = (int)gs; break; }
     }
     gs = (gs + 1) & hmask;
   }
@@ -544,8 +551,8 @@ __global__ void dedup_remap_kernel(const long long* __restrict__ d_count, long l
 
 long long dedup_rank_tmp_elems(long long cap) { return scan_tiles(cap) + 1; }
 
-void launch_dedup(const uint64_t* xe, int words, const long long* d_count, long long cap, uint64_t* hkeys,
-                  int* hslot, long long HT, int* eu, uint64_t* xu, long long* d_nu,
+void launch_dedup(const uint64_t* xe, int words, bool all_ones_key, const long long* d_count, long long cap,
+                  uint64_t* hkeys, int* hslot, long long HT, int* eu, uint64_t* xu, long long* d_nu,
                   int* first, long long* rank, long long* rank_tmp, unsigned* err, hipStream_t s) {
   launch_fill_u64(hkeys, kEmpty, HT, s);
   launch_fill_u32(hslot, (unsigned)kNoEntry, HT, s);   // owners first, then slot ranks
@@ -553,8 +560,11 @@ void launch_dedup(const uint64_t* xe, int words, const long long* d_count, long 
   long long tiles = (cap + kDedupTile - 1) / kDedupTile;
   if (tiles <= 0) return;
   if (words == 2)
-    hipLaunchKernelGGL(dedup_insert_wide_kernel, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, xe, d_count,
-                       cap, (unsigned long long*)hkeys, hslot, HT, eu, err);
+    hipLaunchKernelGGL(dedup_insert_slot_kernel<2>, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, xe,
+                       d_count, cap, (unsigned long long*)hkeys, hslot, HT, eu, err);
+  else if (all_ones_key)
+    hipLaunchKernelGGL(dedup_insert_slot_kernel<1>, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, xe,
+                       d_count, cap, (unsigned long long*)hkeys, hslot, HT, eu, err);
   else
     hipLaunchKernelGGL(dedup_insert_kernel, dim3((unsigned)tiles), dim3(512), 0, s, xe, d_count, cap,
                        (unsigned long long*)hkeys, hslot, HT, eu, err);

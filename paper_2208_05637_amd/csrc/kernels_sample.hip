@@ -12,11 +12,11 @@
 // order.
 //
 // Random numbers: Philox4x64 with 10 rounds (Salmon et al., SC 2011),
-// counter (parent configuration, t, 0, 0), key (seed, 0), so a draw does not
-// depend on the entry's place in the buffer.  Binomial Bin(c, p): with
-// q = min(p, 1 - p), inversion of the distribution function summed from k = 0
-// when c q < 32, else the normal approximation with continuity correction and
-// a Box-Muller normal; reflected when p > 1/2.  The arithmetic is written in
+// counter (parent configuration's low word, t, its high word, j) for blocks
+// j = 0, 1, ..., key (seed, 0), so a draw does not depend on the entry's place
+// in the buffer.  Binomial Bin(c, p), exact: with q = min(p, 1 - p),
+// inversion of the distribution function summed from k = 0 when c q < 32,
+// else Hormann's BTRS rejection method; reflected when p > 1/2.  The arithmetic is written in
 // a fixed operation order without contraction into fused multiply-adds, so a
 // host implementation of the same definition draws the same counts.
 #include "nqs_internal.h"
@@ -48,14 +48,88 @@ __device__ __forceinline__ double uniform53(uint64_t w) {
   return (double)(w >> 11) * (1.0 / 9007199254740992.0);
 }
 
-__device__ long long binomial_draw(long long c, double p, double u1, double u2) {
-  if (c == 0 || p <= 0.0) return 0;
-  if (p >= 1.0) return c;
+// The uniforms of one draw: the four words of Philox block j = 0, 1, ... of
+// the counter (c0, c1, c2, j), in order.
+struct Uniforms {
+  uint64_t c0, c1, c2, key, j;
+  uint64_t w[4];
+  int used;
+  __device__ Uniforms(uint64_t a, uint64_t b, uint64_t c, uint64_t k) : c0(a), c1(b), c2(c), key(k), j(0), used(4) {}
+  __device__ double next() {
+    if (used == 4) {
+      uint64_t blk[4] = {c0, c1, c2, j};
+      philox4x64_10(blk, key, 0ull);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) w[i] = blk[i];
+      used = 0;
+      ++j;
+    }
+    const int i = used++;
+    return uniform53(i == 0 ? w[0] : (i == 1 ? w[1] : (i == 2 ? w[2] : w[3])));
+  }
+};
+
+// fc(k) = log(k!) - [(k + 1/2) log(k + 1) - (k + 1) + log(2 pi) / 2] for integer-valued k >= 0.
+__device__ double stirling_corr(double k) {
+  if (k < 16.0) return lgamma(k + 1.0) - ((k + 0.5) * log(k + 1.0) - (k + 1.0) + 0.5 * log(2.0 * 3.141592653589793));
+  const double x = k + 1.0;
+  const double x2 = x * x;
+  return (1.0 / 12.0 - (1.0 / 360.0 - (1.0 / 1260.0 - (1.0 / 1680.0) / x2) / x2) / x2) / x;
+}
+
+// log(a! / b!) for a >= b >= 0, as d log(b+1) + (a + 1/2) log1p(d/(b+1)) - d + fc(a) - fc(b), d = a - b:
+// its rounding stays at the size of the result next to 10^12.
+__device__ double log_fact_ratio(long long a, long long b) {
+  const long long d = a - b;
+  if (d == 0) return 0.0;
+  const double dd = (double)d, ad = (double)a, bd = (double)b;
+  return dd * log(bd + 1.0) + (ad + 0.5) * log1p(dd / (bd + 1.0)) - dd + stirling_corr(ad) - stirling_corr(bd);
+}
+
+constexpr int kMaxAttempts = 4096;
+
+// Bin(n, p), p <= 1/2, n p >= 32: Hormann's BTRS (transformed rejection with
+// squeeze; J. Statist. Comput. Simul. 46, 1993), each attempt on the next two
+// uniforms; the acceptance test compares log V with log f(k)/f(m) at the mode
+// m.  Attempts are capped (each accepts with probability above 0.75); at the
+// cap the draw is the mode.
+__device__ long long binomial_btrs(long long n, double p, Uniforms& uni) {
+  const double nd = (double)n;
+  const double q = 1.0 - p;
+  const double spq = sqrt(nd * p * q);
+  const double b = 1.15 + 2.53 * spq;
+  const double a = -0.0873 + 0.0248 * b + 0.01 * p;
+  const double c = nd * p + 0.5;
+  const double vr = 0.92 - 4.2 / b;
+  const double alpha = (2.83 + 5.1 / b) * spq;
+  const double lpq = log(p / q);
+  const long long m = (long long)floor((nd + 1.0) * p);
+  for (int it = 0; it < kMaxAttempts; ++it) {
+    const double u = uni.next() - 0.5;
+    double v = uni.next();
+    const double us = 0.5 - fabs(u);
+    const double kf = floor(us > 0.0 ? (2.0 * a / us + b) * u + c : -1.0);   // us = 0 only at u = -1/2
+    if (us >= 0.07 && v <= vr) return (long long)kf;
+    if (kf < 0.0 || kf > nd) continue;
+    const long long k = (long long)kf;
+    v = v * alpha / (a / (us * us) + b);
+    // log f(k)/f(m) = log(m!/k!) + log((n-m)!/(n-k)!) + (k - m) log(p/q)
+    const double lr = k >= m ? -log_fact_ratio(k, m) + log_fact_ratio(n - m, n - k)
+                             : log_fact_ratio(m, k) - log_fact_ratio(n - k, n - m);
+    if (v == 0.0 || log(v) <= lr + (double)(k - m) * lpq) return k;
+  }
+  return m;
+}
+
+__device__ long long binomial_draw(long long c, double p, Uniforms& uni) {
+  if (c == 0 || !(p > 0.0)) return 0;
+  if (!(p < 1.0)) return c;
   const bool flip = p > 0.5;
   const double q = flip ? 1.0 - p : p;
   const double cd = (double)c;
   long long k;
   if (cd * q < 32.0) {
+    const double u1 = uni.next();
     const double r = q / (1.0 - q);
     double pk = exp(cd * log1p(-q));
     double F = pk;
@@ -68,9 +142,7 @@ __device__ long long binomial_draw(long long c, double p, double u1, double u2) 
       F += pk;
     }
   } else {
-    const double z = sqrt(-2.0 * log(1.0 - u1)) * cos(2.0 * 3.141592653589793 * u2);
-    const double v = floor(cd * q + z * sqrt(cd * q * (1.0 - q)) + 0.5);
-    k = v < 0.0 ? 0 : (v > cd ? c : (long long)v);
+    k = binomial_btrs(c, q, uni);
   }
   return flip ? c - k : k;
 }
@@ -98,10 +170,9 @@ __global__ void sample_split_kernel(const uint64_t* __restrict__ x, const long l
   uint64_t xi[W];
 #pragma unroll
   for (int k = 0; k < W; ++k) xi[k] = x[i * W + k];
-  uint64_t w[4] = {xi[0], (uint64_t)t, W == 2 ? xi[W - 1] : 0ull, 0ull};
-  philox4x64_10(w, seed, 0ull);
+  Uniforms uni(xi[0], (uint64_t)t, W == 2 ? xi[W - 1] : 0ull, seed);
   const long long c = cnt[i];
-  const long long k1 = binomial_draw(c, p1, uniform53(w[0]), uniform53(w[1]));
+  const long long k1 = binomial_draw(c, p1, uni);
 #pragma unroll
   for (int k = 0; k < W; ++k) {
     kx[i * W + k] = xi[k];

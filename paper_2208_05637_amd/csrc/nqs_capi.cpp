@@ -751,10 +751,10 @@ nqs_status nqs_plan_create(nqs_ctx* ctx, const nqs_ham* ham, const nqs_net_desc*
     grid_for(half, ngroups, r2, gp2);
     p->SRcap = std::max<int64_t>(p->S0 * p->R, half * r2);
   }
-  // a one-word table holds the keys themselves and all-ones marks an empty
-  // slot, so there is no dedup at exactly 64 qubits (two-word tables hold
-  // entry indices and take every width above)
-  p->dedup_cap = (flags & (NQS_PLAN_DEDUP_ON | NQS_PLAN_DEDUP_AUTO)) != 0 && (g.n < 64 || g.words == 2);
+  // a one-word table holds the keys themselves with all-ones as the empty
+  // marker below 64 qubits; at exactly 64 qubits and for two-word strings the
+  // table holds slot words (hash tag and inserting entry) instead
+  p->dedup_cap = (flags & (NQS_PLAN_DEDUP_ON | NQS_PLAN_DEDUP_AUTO)) != 0;
   p->dedup = p->dedup_cap;
   p->dedup_auto = (flags & NQS_PLAN_DEDUP_AUTO) != 0 && p->dedup_cap;
   if (p->dedup_cap) {
@@ -958,7 +958,7 @@ static ChunkFwd enum_chunk(nqs_plan* p, const uint64_t* x, int64_t c0, int64_t S
   if (p->dedup) {
     uint64_t* xu = at<uint64_t>(ws, L.xu);
     long long* nu = at<long long>(ws, L.nu);
-    launch_dedup(xe, p->g.words, d_total, p->EC, at<uint64_t>(ws, L.hkeys), at<int>(ws, L.hslot), p->HT, at<int>(ws, L.eu), xu,
+    launch_dedup(xe, p->g.words, p->g.n == 64, d_total, p->EC, at<uint64_t>(ws, L.hkeys), at<int>(ws, L.hslot), p->HT, at<int>(ws, L.eu), xu,
                  nu, at<int>(ws, L.dfirst), at<long long>(ws, L.drank), at<long long>(ws, L.drtmp), err, s);
     return {xu, nu, bound, at<double>(ws, L.lpe)};
   }
@@ -1556,7 +1556,7 @@ nqs_status nqs_connected(nqs_plan* p, const uint64_t* x, int64_t B, int64_t capa
   if (p->dedup) {
     if (capacity > p->EC || (int64_t)2 * capacity > p->HT)
       return fail(NQS_ERR_INVALID_ARGUMENT, "capacity exceeds the plan's dedup buffers");
-    launch_dedup(d_ex, p->g.words, (const long long*)d_n_entries, capacity, at<uint64_t>(ws, L.hkeys), at<int>(ws, L.hslot),
+    launch_dedup(d_ex, p->g.words, p->g.n == 64, (const long long*)d_n_entries, capacity, at<uint64_t>(ws, L.hkeys), at<int>(ws, L.hslot),
                  p->HT, d_eunique, d_unique, (long long*)d_n_unique, at<int>(ws, L.dfirst), at<long long>(ws, L.drank),
                  at<long long>(ws, L.drtmp), err, s);
   }

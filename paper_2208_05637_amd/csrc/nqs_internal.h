@@ -160,11 +160,12 @@ void launch_write(const HamDev& H, const uint64_t* x, long long S, int R, int gp
 
 // Distinct keys of xe[0 .. min(*d_count, cap)) (`words` 64-bit words each)
 // into xu in the order of their first entries, eu[e] = index of entry e's key
-// in xu, *d_nu = their number.
+// in xu, *d_nu = their number.  all_ones_key: one-word keys may be the
+// all-ones word (64 qubits), so the table takes slot words instead of keys.
 // first: int[cap], rank: i64[cap + 1], rank_tmp: dedup_rank_tmp_elems(cap).
 long long dedup_rank_tmp_elems(long long cap);
-void launch_dedup(const uint64_t* xe, int words, const long long* d_count, long long cap, uint64_t* hkeys,
-                  int* hslot, long long HT, int* eu, uint64_t* xu, long long* d_nu,
+void launch_dedup(const uint64_t* xe, int words, bool all_ones_key, const long long* d_count, long long cap,
+                  uint64_t* hkeys, int* hslot, long long HT, int* eu, uint64_t* xu, long long* d_nu,
                   int* first, long long* rank, long long* rank_tmp, unsigned* err, hipStream_t s);
 
 // partials holds reduce_partials_elems(S) doubles

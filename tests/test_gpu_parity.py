@@ -387,3 +387,39 @@ def test_autograd_function(nqs, ctx):
     (3.0 * E).backward()
     _, g, _ = nqs.energy_grad(plan, p.detach(), xs, w)
     assert torch.allclose(p.grad.double(), 3.0 * g, rtol=1e-6, atol=1e-9)
+
+
+def test_dedup_at_64_qubits_with_the_all_ones_configuration(nqs, ctx):
+    """Exactly 64 qubits, where every 64-bit word is a configuration: a Hamiltonian of two-qubit X strings
+    (no sector filter) whose flips take several samples to the all-ones string.  The distinct connected
+    configurations equal np.unique of the entries (all-ones included), the entry map and first-entry order
+    are exact, and the FP64 local energies with dedup on equal those with it off bit for bit."""
+    n = 64
+    rng = np.random.default_rng(11)
+    pairs = [(0, 5), (3, 9), (62, 63), (17, 40), (8, 33)]
+    xm = np.array([(1 << a) | (1 << b) for a, b in pairs], dtype=np.uint64)
+    zm = np.array([(1 << (7 * k % 64)) for k in range(len(pairs))], dtype=np.uint64)
+    cf = rng.normal(size=len(pairs))
+    H = nqs.Hamiltonian(n, np.concatenate([xm, [0]]).astype(np.uint64), np.concatenate([zm, [3]]).astype(np.uint64),
+                        np.concatenate([cf, [0.7]]), conserves_spin=False).upload(ctx)
+    ones = np.uint64(2**64 - 1)
+    xs = [ones ^ m for m in xm] + [ones] + list(rng.integers(0, 2**63, size=40, dtype=np.uint64) * np.uint64(2))
+    xs = np.unique(np.array(xs, dtype=np.uint64))
+    B = len(xs)
+    mk = lambda d: nqs.Plan(ctx, H, 1, 64, -1, -1, "fp64", max_batch=B, chunk_samples=B, dedup=d)
+    out = nqs.connected(mk(True), xs)
+    torch.cuda.synchronize()
+    ne, nu = int(out["n_entries"].item()), int(out["n_unique"].item())
+    ex = out["x"][:ne].cpu().numpy().view(np.uint64)
+    u = out["unique"][:nu].cpu().numpy().view(np.uint64)
+    assert ne == B * len(pairs) and int(np.sum(ex == ones)) == len(pairs)
+    assert np.array_equal(np.sort(u), np.unique(ex)) and ones in u
+    eu = out["entry_unique"][:ne].cpu().numpy()
+    assert np.array_equal(u[eu], ex)
+    _, first = np.unique(ex, return_index=True)
+    assert np.array_equal(u, ex[np.sort(first)])
+    params = torch.from_numpy(init_params(n, 1, 64, seed=1, std=0.2)).cuda()
+    e_on = nqs.local_energy(mk(True), params, xs)
+    e_off = nqs.local_energy(mk(False), params, xs)
+    torch.cuda.synchronize()
+    assert torch.equal(e_on, e_off) and bool(torch.isfinite(e_on).all())

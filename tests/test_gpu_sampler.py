@@ -38,6 +38,7 @@ def _plan(nqs, ctx, n, L, h, nu, nd, prec, order=None):
 @pytest.mark.parametrize("n,L,h,nu,nd,draws,umax,order_seed", [
     (12, 1, 64, 3, 3, 10**6, 40, None),          # elimination active from early on
     (12, 1, 64, 3, 3, 10**6, 10**4, None),       # no elimination: all draws kept
+    (12, 1, 64, 3, 3, 10**12, 10**4, None),      # counts up to 10^12: the rejection branch throughout
     (16, 2, 128, 4, 4, 10**9, 300, None),
     (12, 2, 64, 2, 4, 10**5, 64, 3),             # random sampling order, unequal sector
     (10, 1, 64, 3, 2, 7, 1000, None)])           # fewer draws than states

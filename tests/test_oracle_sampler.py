@@ -23,27 +23,80 @@ def test_philox4x64_matches_numpy_philox():
             assert [int(v) for v in raw[4 * b:4 * b + 4]] == out
 
 
+class _Given:
+    """Uniforms given in advance (for the inversion branch: one per draw)."""
+
+    def __init__(self, *vals):
+        self.vals = list(vals)
+
+    def next(self):
+        return self.vals.pop(0)
+
+
 @pytest.mark.parametrize("c,p", [(1, 0.3), (7, 0.5), (50, 0.1), (400, 0.05), (10**6, 1e-5), (31, 0.97)])
 def test_binomial_small_mean_is_exact_inversion(c, p):
     rng = np.random.default_rng(c)
     for u in rng.random(300):
-        k = sampler.binomial(c, p, float(u), 0.5)
+        k = sampler.binomial(c, p, _Given(float(u)))
         if p <= 0.5:
             assert k == int(stats.binom.ppf(u, c, p))
         else:                                # reflected: c - Bin(c, 1 - p) on the same uniform
             assert k == c - int(stats.binom.ppf(u, c, 1 - p))
 
 
-def test_binomial_large_mean_moments():
-    c, p = 10**7, 0.3
-    ks = np.array([sampler.binomial(c, p, sampler.uniform53(w[0]), sampler.uniform53(w[1]))
-                   for w in (sampler.philox4x64_10((i, 0, 0, 0), (99, 0)) for i in range(4000))])
+def test_log_fact_ratio_against_sums_of_logs():
+    """log(a!/b!) from the Stirling form equals the exactly summed log(b+1) + ... + log(a), also next to
+    10^12 where a difference of two lgamma values would keep only ~1e-4 absolute accuracy."""
+    for a, b in ((5, 0), (15, 3), (16, 15), (40, 17), (1000, 900), (10**6 + 300, 10**6),
+                 (10**12 + 4000, 10**12), (10**12, 10**12 - 3000), (4 * 10**11 + 20, 4 * 10**11 - 50)):
+        ref = math.fsum(math.log(i) for i in range(b + 1, a + 1))
+        got = sampler.log_fact_ratio(a, b)
+        assert abs(got - ref) <= 1e-13 * max(1.0, abs(ref)), (a, b, got, ref)
+    # the Stirling correction's series and its lgamma form agree where they meet, to the rounding of the
+    # lgamma form (a difference of numbers of size lgamma(x))
+    for k in range(16, 40):
+        x = k + 1.0
+        direct = math.lgamma(x) - ((k + 0.5) * math.log(x) - x + 0.5 * math.log(2 * math.pi))
+        assert abs(sampler._stirling_corr(k) - direct) < 8 * 2.0**-52 * math.lgamma(x)
+
+
+def _chi2_binom(ks, c, p, bins=24):
+    """Chi-square statistic of draws against Bin(c, p) over bins of about equal probability; (stat, dof)."""
+    qs = np.linspace(0, 1, bins + 1)[1:-1]
+    edges = np.unique(stats.binom.ppf(qs, c, p).astype(np.int64))
+    cdf = np.concatenate([[0.0], stats.binom.cdf(edges, c, p), [1.0]])
+    expect = np.diff(cdf) * len(ks)
+    got = np.bincount(np.searchsorted(edges, ks, side="left"), minlength=len(expect))
+    return float(np.sum((got - expect) ** 2 / expect)), len(expect) - 1
+
+
+@pytest.mark.parametrize("c,p", [(100, 0.4), (10**4, 0.01), (10**7, 0.3), (10**12, 0.37), (10**12, 1e-9),
+                                 (5 * 10**5, 0.93)])
+def test_binomial_large_mean_matches_distribution(c, p):
+    """Draws of the rejection branch (c q >= 32) against scipy's binomial distribution: chi-square over 24
+    bins of about equal probability from 6,000 draws of seeded counters, and the first two moments."""
+    ks = np.array([sampler.binomial(c, p, sampler.Uniforms((i, 3, 0), (99, 0))) for i in range(6000)])
+    assert ks.min() >= 0 and ks.max() <= c
+    chi2, dof = _chi2_binom(ks, c, p)
+    assert chi2 < stats.chi2.ppf(0.999, dof), (chi2, dof)
     m, v = c * p, c * p * (1 - p)
     assert abs(ks.mean() - m) < 5 * math.sqrt(v / len(ks))
     assert abs(ks.var() / v - 1) < 0.1
-    assert ks.min() >= 0 and ks.max() <= c
-    # p and 1 - p mirror each other on the same uniforms
-    assert sampler.binomial(c, 0.7, 0.25, 0.6) == c - sampler.binomial(c, 0.3, 0.25, 0.6)
+
+
+def test_binomial_reflection_and_counter_words():
+    c = 10**7
+    for i in range(50):
+        # p and 1 - p mirror each other on the same uniforms
+        assert sampler.binomial(c, 0.7, sampler.Uniforms((i, 0, 0), (5, 0))) == \
+            c - sampler.binomial(c, 0.3, sampler.Uniforms((i, 0, 0), (5, 0)))
+    # successive uniforms walk the four words of block 0, then block 1
+    u = sampler.Uniforms((11, 2, 3), (7, 8))
+    b0, b1 = sampler.philox4x64_10((11, 2, 3, 0), (7, 8)), sampler.philox4x64_10((11, 2, 3, 1), (7, 8))
+    assert [u.next() for _ in range(6)] == [sampler.uniform53(w) for w in b0 + b1[:2]]
+    # degenerate conditionals: no draws, certain outcomes, NaN (treated as no draws)
+    assert sampler.binomial(0, 0.3, _Given()) == 0 and sampler.binomial(9, 0.0, _Given()) == 0
+    assert sampler.binomial(9, 1.0, _Given()) == 9 and sampler.binomial(9, float("nan"), _Given()) == 0
 
 
 def _exact_pi(net, params):

@@ -197,12 +197,11 @@ def test_wide_sampler_counter_and_properties():
     position split binomially with the network's conditional there."""
     from oracle import sampler
     x = (1 << 63) | 12345
-    assert sampler.split_draws(1000, 0.3, x, 5, 9) == sampler.binomial(
-        1000, 0.3, *[sampler.uniform53(w) for w in sampler.philox4x64_10((x, 5, 0, 0), (9, 0))[:2]])
+    assert sampler.split_draws(1000, 0.3, x, 5, 9) == sampler.binomial(1000, 0.3, sampler.Uniforms((x, 5, 0), (9, 0)))
     xw = x | (7 << 64)
-    w = sampler.philox4x64_10((x, 5, 7, 0), (9, 0))
-    assert sampler.split_draws(1000, 0.3, xw, 5, 9) == sampler.binomial(1000, 0.3, sampler.uniform53(w[0]),
-                                                                        sampler.uniform53(w[1]))
+    assert sampler.split_draws(1000, 0.3, xw, 5, 9) == sampler.binomial(1000, 0.3, sampler.Uniforms((x, 5, 7), (9, 0)))
+    assert sampler.split_draws(1000, 0.3, xw, 5, 9) != sampler.split_draws(1000, 0.3, x, 5, 9) or \
+        sampler.split_draws(1000, 0.3, xw, 6, 9) != sampler.split_draws(1000, 0.3, x, 6, 9)
     n, L, h, draws = 66, 1, 16, 20000
     net = made.Net(n=n, n_layers=L, width=h, n_up=2, n_dn=2)
     params = init_params(n, L, h, seed=3, std=0.5)
