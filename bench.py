@@ -394,11 +394,12 @@ def main():
     tune = tuned(plan, x)
     kinfo = plan.kernel_info()
     log(f"K={K} G={H.G} entries/sample={plan.entries_per_sample} chunk={plan.chunk_samples} "
-        f"dedup={plan.dedup} waves={kinfo['waves_per_block']} tuned={kinfo['tuned']} "
+        f"dedup={plan.dedup} waves={kinfo['waves_per_block']} resident={kinfo['resident']} tuned={kinfo['tuned']} "
         f"workspace={plan.workspace_size(B) / 2**30:.2f} GiB")
     if tune is not None and not tune["from_cache"]:
-        log("autotune: " + ", ".join(f"{c['waves_per_block']}w/dedup{int(c['dedup'])}/S{c['chunk_samples']}: "
-                                    f"{c['ms']:.1f} ms" for c in tune["candidates"]))
+        log("autotune: " + ", ".join(f"{c['waves_per_block']}w/dedup{int(c['dedup'])}/S{c['chunk_samples']}/"
+                                    f"{'resident' if c['resident'] else 'tiles'}: {c['ms']:.1f} ms"
+                                    for c in tune["candidates"]))
 
     # first warm-up step, which also prices one step for the budget
     t = time.time()
@@ -480,6 +481,7 @@ def main():
             "dedup": plan.dedup,
             "forward_waves_per_block": kinfo["waves_per_block"],
             "forward_rows_per_block": kinfo["rows_per_block"],
+            "forward_resident_grid": kinfo["resident"],
             "tuned": kinfo["tuned"],
             "tune_from_db": bool(tune is not None and tune["from_cache"] and not args.tune),
             "energy": float(E_main[0]),
@@ -638,7 +640,7 @@ def main():
                                                       phase_mode=1)).to(dev)
                 pl = nqs.Plan(ctx, H, cfg["L"], cfg["h"], cfg["n_up"], cfg["n_dn"], prec, max_batch=P,
                               dedup=plan.dedup, chunk_samples=min(plan.chunk_samples, P), **kw)
-                pl.configure(waves_per_block=kinfo["waves_per_block"])
+                pl.configure(waves_per_block=kinfo["waves_per_block"], resident=kinfo["resident"])
                 nqs.local_energy(pl, vp, xp[:64])
                 torch.cuda.synchronize()
                 pl.profile(True)

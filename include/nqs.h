@@ -248,28 +248,35 @@ void       nqs_plan_destroy(nqs_plan* plan);
 /* Sets what the autotuner chooses: waves per workgroup of the forward (one
    of the values nqs_plan_autotune reports; <= 0 keeps the current one),
    dedup (1 on, 0 off, < 0 keep; on needs a plan created with DEDUP_ON or
-   DEDUP_AUTO) and the chunk (between half the created chunk and the created
-   chunk; <= 0 keeps).  Host only. */
-nqs_status nqs_plan_configure(nqs_plan* plan, int waves_per_block, int dedup, int64_t chunk_samples);
+   DEDUP_AUTO), the chunk (between half the created chunk and the created
+   chunk; <= 0 keeps) and the forward's grid (resident: 1 = as many
+   workgroups as the device holds at once, each looping over tiles of rows;
+   0 = one workgroup per tile; < 0 keep).  Host only. */
+nqs_status nqs_plan_configure(nqs_plan* plan, int waves_per_block, int dedup, int64_t chunk_samples,
+                              int resident);
 
 /* Workgroup shape of the plan's connected-configuration forward: waves per
-   workgroup, configurations per workgroup, and whether the plan was tuned. */
+   workgroup, configurations per workgroup, whether the plan was tuned, and
+   whether the forward runs a resident grid (each output may be NULL). */
 nqs_status nqs_plan_kernel_info(const nqs_plan* plan, int* waves_per_block, int* rows_per_block,
-                                int* tuned);
+                                int* tuned, int* resident);
 
 /* Autotuner for the chunked local-energy path (the paper's mini-batches,
    Sec. 5.2 and Sec. 6): times the local-energy phase on the first
    min(B, 2 * chunk) samples of d_samples for every candidate
      forward variant (waves per workgroup) x dedup on/off (only with
      NQS_PLAN_DEDUP_AUTO) x chunk in {plan chunk, plan chunk / 2}
+     x forward grid (one workgroup per tile, or resident workgroups
+     looping over tiles)
    and keeps the fastest in the plan.  The choice is cached per process,
    keyed by the network shape, the Hamiltonian's term and group counts and
    the plan's chunk; a later call with the same key applies it without timing
    (NQS_TUNE_FORCE re-times; NQS_TUNE_CACHE_ONLY applies a cached choice if
    there is one and otherwise returns NQS_OK with n_candidates = 0 and the
-   plan unchanged, without timing or touching the device).  Every candidate computes the same local
-   energies up to the forward's rounding (dedup and chunking change nothing;
-   the two variants split the head's k sum differently).  Synchronises the
+   plan unchanged, without timing or touching the device).  Every candidate
+   computes the same local energies up to the forward's rounding (dedup,
+   chunking and the grid change nothing; the two workgroup shapes split the
+   head's k sum differently).  Synchronises the
    context's stream; not for use under graph capture.  d_ws must hold
    nqs_plan_workspace_size(plan, B) bytes.  report may be NULL. */
 #define NQS_TUNE_FORCE 1u
@@ -279,6 +286,7 @@ typedef struct {
   int     waves_per_block;
   int     dedup;
   int64_t chunk_samples;
+  int     resident;        /* 1: resident grid looping over tiles */
   double  ms;              /* one local-energy pass over the probe samples */
 } nqs_tune_candidate;
 typedef struct {

@@ -45,7 +45,7 @@ class Profile(C.Structure):
 
 class TuneCandidate(C.Structure):
     _fields_ = [("waves_per_block", C.c_int), ("dedup", C.c_int), ("chunk_samples", C.c_int64),
-                ("ms", C.c_double)]
+                ("resident", C.c_int), ("ms", C.c_double)]
 
 
 class TuneReport(C.Structure):
@@ -84,8 +84,9 @@ SIGNATURES = {
     "nqs_plan_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(C.c_int),
                                 C.POINTER(_I64)]),
     "nqs_plan_destroy": (None, [_P]),
-    "nqs_plan_configure": (C.c_int, [_P, C.c_int, C.c_int, _I64]),
-    "nqs_plan_kernel_info": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "nqs_plan_configure": (C.c_int, [_P, C.c_int, C.c_int, _I64, C.c_int]),
+    "nqs_plan_kernel_info": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                       C.POINTER(C.c_int)]),
     "nqs_plan_autotune": (C.c_int, [_P, _P, _P, _I64, _P, _SZ, C.c_uint32, C.POINTER(TuneReport)]),
     "nqs_tune_db_save": (C.c_int, [C.c_char_p]),
     "nqs_tune_db_load": (C.c_int, [C.c_char_p, C.POINTER(C.c_int)]),

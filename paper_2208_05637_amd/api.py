@@ -211,19 +211,21 @@ class Plan:
         self.entries_per_sample, self.chunk_samples = e.value, cs.value
         self.dedup, self.n_params = bool(dd.value), npar.value
 
-    def configure(self, waves_per_block=0, dedup=None, chunk_samples=0):
-        """Set the forward variant (by waves per workgroup), dedup and chunk by hand."""
+    def configure(self, waves_per_block=0, dedup=None, chunk_samples=0, resident=None):
+        """Set the forward variant (by waves per workgroup), dedup, chunk and the
+        forward's grid (resident workgroups looping over tiles) by hand."""
         d = -1 if dedup is None else (1 if dedup else 0)
-        L.check(self.lib.nqs_plan_configure(self.handle, int(waves_per_block), d, int(chunk_samples)),
+        r = -1 if resident is None else (1 if resident else 0)
+        L.check(self.lib.nqs_plan_configure(self.handle, int(waves_per_block), d, int(chunk_samples), r),
                 "nqs_plan_configure")
         self._refresh()
 
     def kernel_info(self):
-        """(waves per workgroup, configurations per workgroup, tuned) of the forward."""
-        w, r, t = C.c_int(), C.c_int(), C.c_int()
-        L.check(self.lib.nqs_plan_kernel_info(self.handle, C.byref(w), C.byref(r), C.byref(t)),
+        """(waves per workgroup, configurations per workgroup, tuned, resident grid) of the forward."""
+        w, r, t, g = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        L.check(self.lib.nqs_plan_kernel_info(self.handle, C.byref(w), C.byref(r), C.byref(t), C.byref(g)),
                 "nqs_plan_kernel_info")
-        return dict(waves_per_block=w.value, rows_per_block=r.value, tuned=bool(t.value))
+        return dict(waves_per_block=w.value, rows_per_block=r.value, tuned=bool(t.value), resident=bool(g.value))
 
     def autotune(self, params, samples, force=False, cache_only=False):
         """Time the candidate kernel variants / dedup / chunk sizes on a prefix of
@@ -238,7 +240,7 @@ class Plan:
                 "nqs_plan_autotune")
         self._refresh()
         cands = [dict(waves_per_block=c.waves_per_block, dedup=bool(c.dedup), chunk_samples=c.chunk_samples,
-                      ms=c.ms) for c in rep.cand[:rep.n_candidates]]
+                      resident=bool(c.resident), ms=c.ms) for c in rep.cand[:rep.n_candidates]]
         return dict(candidates=cands, chosen=rep.chosen, from_cache=bool(rep.from_cache),
                     probe_samples=rep.probe_samples)
 

@@ -831,8 +831,13 @@ __device__ __forceinline__ long long seg_rows(const Seg& sg) {
   return rows;
 }
 
-// One workgroup per tile of M rows.  The grid covers the row bounds; tiles
-// past a segment's device-side row count exit at once.
+// Tiles of M rows.  Workgroup b takes tiles tile_base + b, then + tile_stride,
+// ... below ntiles: one tile each when the grid covers every tile
+// (tile_stride = ntiles), several when only a resident grid is launched.
+// Tiles past a segment's device-side row count are skipped (a single segment
+// ends its loop there).  Consecutive tiles of one workgroup are separated by
+// a barrier: the previous tile's epilogue reads the LDS the next prologue
+// writes.
 // MULTI = false: one segment, geometry in the kernel arguments.
 // MULTI = true: up to kMaxSeg segments (a work list of tiles from several
 // networks); a tile's segment is found from the tile index and its geometry
@@ -844,26 +849,34 @@ __global__ __launch_bounds__(64 * NW) void fused_forward(Geom g0, FwdLaunch la) 
   constexpr int M = Sh::M;
   extern __shared__ uint4 smem[];
   char* act = (char*)smem;
-  const long long t = la.tile_base + blockIdx.x;
-  if constexpr (!MULTI) {
-    const FwdSeg& sg = la.seg[0];
-    const long long rows = seg_rows(sg);
-    if (t * M < rows)
+  bool again = false;
+  for (long long t = la.tile_base + blockIdx.x; t < la.ntiles; t += la.tile_stride) {
+    if constexpr (!MULTI) {
+      const FwdSeg& sg = la.seg[0];
+      const long long rows = seg_rows(sg);
+      if (t * M >= rows) break;
+      if (again) __syncthreads();
       fwd_tile<P, H, NW, W>(g0, (const uint4*)sg.packed, sg.x, t * M, rows, (double2*)sg.out, act, la.cond_pos);
-  } else {
-    static_assert(W == 1, "multi-segment launches take one-word bit strings");
-    int k = 0;
-    for (int j = 1; j < la.nseg; ++j)
-      if (t >= la.seg[j].tile0) k = j;
-    const FwdSeg& sg = la.seg[k];
-    const long long rows = seg_rows(sg);
-    const long long row0 = (t - sg.tile0) * M;
-    // the geometry is read in place: nothing in this kernel writes global
-    // memory before the tile's outputs, so its loads stay scalar
-    if (row0 < rows)
-      fwd_tile<P, H, NW, W>(*sg.geom, (const uint4*)sg.packed, sg.x, row0, rows, (double2*)sg.out, act, la.cond_pos);
+      again = true;
+    } else {
+      static_assert(W == 1, "multi-segment launches take one-word bit strings");
+      int k = 0;
+      for (int j = 1; j < la.nseg; ++j)
+        if (t >= la.seg[j].tile0) k = j;
+      const FwdSeg& sg = la.seg[k];
+      const long long rows = seg_rows(sg);
+      const long long row0 = (t - sg.tile0) * M;
+      // the geometry is read in place: nothing in this kernel writes global
+      // memory before the tile's outputs, so its loads stay scalar
+      if (row0 < rows) {
+        if (again) __syncthreads();
+        fwd_tile<P, H, NW, W>(*sg.geom, (const uint4*)sg.packed, sg.x, row0, rows, (double2*)sg.out, act,
+                              la.cond_pos);
+        again = true;
+      }
+    }
   }
-  if (t == 0 && threadIdx.x == 0) {
+  if (blockIdx.x == 0 && la.tile_base == 0 && threadIdx.x == 0) {
     for (int k = 0; k < la.nseg; ++k)
       if (la.seg[k].prof_slot) *la.seg[k].prof_slot = seg_rows(la.seg[k]);
   }
@@ -880,7 +893,7 @@ void launch_store_geom(const Geom& g, Geom* dst, hipStream_t s) {
 }
 
 template <int P, int H, int V, bool MULTI, int W>
-static void launch_one(const Geom& g, FwdLaunch& la, hipStream_t s) {
+static void launch_one(const Geom& g, FwdLaunch& la, bool resident, int cu_count, hipStream_t s) {
   constexpr int NW = variant_waves<P, H, V>();
   using Sh = Shape<P, H, NW, W>;
   if constexpr (!Sh::FITS) {
@@ -904,7 +917,25 @@ static void launch_one(const Geom& g, FwdLaunch& la, hipStream_t s) {
   }
   la.ntiles = tiles;
   if (tiles <= 0) return;
+  if (resident) {
+    // workgroups that fit on the device at once (per device ordinal, queried once)
+    static std::atomic<int> per_cu[64];
+    int occ = per_cu[dev & 63].load(std::memory_order_acquire);
+    if (occ <= 0) {
+      int n = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)kern, 64 * NW, LDS) != hipSuccess || n < 1)
+        n = 1;
+      occ = n;
+      per_cu[dev & 63].store(occ, std::memory_order_release);
+    }
+    const long long grid = std::min<long long>(tiles, (long long)std::max(cu_count, 1) * occ);
+    la.tile_base = 0;
+    la.tile_stride = grid;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * NW), LDS, s, g, la);
+    return;
+  }
   // a dispatch counts its work-items in 32 bits: larger launches are split
+  la.tile_stride = tiles;
   const long long max_tiles = 0xFFFFFFFFLL / (64 * NW);
   for (long long t0 = 0; t0 < tiles; t0 += max_tiles) {
     la.tile_base = t0;
@@ -959,14 +990,14 @@ int forward_variant_waves(int prec, int h, int v) {
 }
 
 template <bool MULTI, int W>
-static void dispatch(const Geom& g, int prec, int h, int v, FwdLaunch& la, hipStream_t s) {
-#define NQS_CASE(P, H)                                                  \
-  if (prec == P && h == H) {                                            \
-    if constexpr (P != P_F64) {                                         \
-      if (v == 1) { launch_one<P, H, 1, MULTI, W>(g, la, s); return; }  \
-    }                                                                   \
-    launch_one<P, H, 0, MULTI, W>(g, la, s);                            \
-    return;                                                             \
+static void dispatch(const Geom& g, int prec, int h, int v, bool res, int cus, FwdLaunch& la, hipStream_t s) {
+#define NQS_CASE(P, H)                                                              \
+  if (prec == P && h == H) {                                                        \
+    if constexpr (P != P_F64) {                                                     \
+      if (v == 1) { launch_one<P, H, 1, MULTI, W>(g, la, res, cus, s); return; }    \
+    }                                                                               \
+    launch_one<P, H, 0, MULTI, W>(g, la, res, cus, s);                              \
+    return;                                                                         \
   }
   NQS_CASE(P_BF16, 256) NQS_CASE(P_BF16, 512) NQS_CASE(P_BF16, 1024)
   NQS_CASE(P_BF16X3, 256) NQS_CASE(P_BF16X3, 512) NQS_CASE(P_BF16X3, 1024)
@@ -977,32 +1008,34 @@ static void dispatch(const Geom& g, int prec, int h, int v, FwdLaunch& la, hipSt
 #undef NQS_CASE
 }
 
-void launch_forward(const Geom& g, int variant, const void* packed, const uint64_t* x, long long rows_bound,
-                    const long long* d_count, double* out, long long* prof_slot, hipStream_t s) {
+void launch_forward(const Geom& g, int variant, bool resident, int cu_count, const void* packed,
+                    const uint64_t* x, long long rows_bound, const long long* d_count, double* out,
+                    long long* prof_slot, hipStream_t s) {
   FwdLaunch la{};
   la.nseg = 1;
   la.cond_pos = -1;
   la.seg[0] = FwdSeg{nullptr, packed, x, d_count, out, rows_bound, 0, prof_slot};
-  if (g.words == 2) dispatch<false, 2>(g, g.prec, g.h, variant, la, s);
-  else dispatch<false, 1>(g, g.prec, g.h, variant, la, s);
+  if (g.words == 2) dispatch<false, 2>(g, g.prec, g.h, variant, resident, cu_count, la, s);
+  else dispatch<false, 1>(g, g.prec, g.h, variant, resident, cu_count, la, s);
 }
 
-void launch_forward_cond(const Geom& g, int variant, const void* packed, const uint64_t* x,
-                         long long rows_bound, const long long* d_count, double* out, int t,
+void launch_forward_cond(const Geom& g, int variant, bool resident, int cu_count, const void* packed,
+                         const uint64_t* x, long long rows_bound, const long long* d_count, double* out, int t,
                          hipStream_t s) {
   FwdLaunch la{};
   la.nseg = 1;
   la.cond_pos = t;
   la.seg[0] = FwdSeg{nullptr, packed, x, d_count, out, rows_bound, 0, nullptr};
-  if (g.words == 2) dispatch<false, 2>(g, g.prec, g.h, variant, la, s);
-  else dispatch<false, 1>(g, g.prec, g.h, variant, la, s);
+  if (g.words == 2) dispatch<false, 2>(g, g.prec, g.h, variant, resident, cu_count, la, s);
+  else dispatch<false, 1>(g, g.prec, g.h, variant, resident, cu_count, la, s);
 }
 
-void launch_forward_multi(int prec, int h, int variant, FwdLaunch la, hipStream_t s) {
+void launch_forward_multi(int prec, int h, int variant, bool resident, int cu_count, FwdLaunch la,
+                          hipStream_t s) {
   if (la.nseg < 1 || la.nseg > kMaxSeg) return;
   la.cond_pos = -1;
   Geom unused{};
-  dispatch<true, 1>(unused, prec, h, variant, la, s);
+  dispatch<true, 1>(unused, prec, h, variant, resident, cu_count, la, s);
 }
 
 }  // namespace nqs

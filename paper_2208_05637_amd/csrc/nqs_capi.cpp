@@ -160,6 +160,7 @@ struct nqs_plan {
   bool dedup_cap = false;  // workspace holds the dedup tables
   bool dedup_auto = false; // the autotuner may switch dedup
   int variant = 0;         // forward kernel variant
+  bool resident = false;   // forward grid: resident workgroups looping over tiles
   bool tuned = false;
   int64_t HT = 0;          // dedup hash slots
   int64_t Sb = 0;          // backward chunk
@@ -912,9 +913,11 @@ static void pack_net(const nqs_plan* p, const float* params, void* packed, hipSt
 // network, then phase network over the same rows) for a separate phase network.
 static void forward_net(const nqs_plan* p, const void* packed, const uint64_t* x, long long bound,
                         const long long* d_count, double* out, long long* slot, hipStream_t s) {
-  launch_forward(p->g, p->variant, packed, x, bound, d_count, out, slot, s);
+  const int cus = p->ctx->cu_count;
+  launch_forward(p->g, p->variant, p->resident, cus, packed, x, bound, d_count, out, slot, s);
   if (p->two)
-    launch_forward(p->gp, p->variant, (const char*)packed + p->packed_phase, x, bound, d_count, out, nullptr, s);
+    launch_forward(p->gp, p->variant, p->resident, cus, (const char*)packed + p->packed_phase, x, bound, d_count,
+                   out, nullptr, s);
 }
 
 static void forward_profiled(nqs_plan* p, void* ws, const WsLayout& L, const void* packed,
@@ -1177,25 +1180,28 @@ nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* ws,
       if (done[a]) continue;
       const Geom& ga = inst[ids[a]].plan->g;
       const int va = inst[ids[a]].plan->variant;
+      const bool ra = inst[ids[a]].plan->resident;
+      const int cus = inst[ids[a]].plan->ctx->cu_count;
       if (ga.words != 1) {
         const FwdSeg& sg = segs[a];
-        launch_forward(*hg[a], va, sg.packed, sg.x, sg.rows_bound, sg.d_count, sg.out, nullptr, s);
+        launch_forward(*hg[a], va, ra, cus, sg.packed, sg.x, sg.rows_bound, sg.d_count, sg.out, nullptr, s);
         done[a] = true;
         continue;
       }
       FwdLaunch la{};
       for (size_t b = a; b < ids.size(); ++b) {
         const Geom& gb = inst[ids[b]].plan->g;
-        if (done[b] || gb.words != 1 || gb.prec != ga.prec || gb.h != ga.h || inst[ids[b]].plan->variant != va)
+        if (done[b] || gb.words != 1 || gb.prec != ga.prec || gb.h != ga.h || inst[ids[b]].plan->variant != va ||
+            inst[ids[b]].plan->resident != ra)
           continue;
         la.seg[la.nseg++] = segs[b];
         done[b] = true;
         if (la.nseg == kMaxSeg) {
-          launch_forward_multi(ga.prec, ga.h, va, la, s);
+          launch_forward_multi(ga.prec, ga.h, va, ra, cus, la, s);
           la = FwdLaunch{};
         }
       }
-      if (la.nseg > 0) launch_forward_multi(ga.prec, ga.h, va, la, s);
+      if (la.nseg > 0) launch_forward_multi(ga.prec, ga.h, va, ra, cus, la, s);
     }
   };
   std::vector<int> ids;
@@ -1239,7 +1245,7 @@ nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* ws,
 // ------------------------------------------------------------- autotuner
 namespace {
 using TuneKey = std::tuple<int, int, int, int, int64_t, int64_t, int64_t, int64_t, int, int, int>;
-struct TuneVal { int variant; bool dedup; int64_t S; double ms; };
+struct TuneVal { int variant; bool dedup; int64_t S; bool resident; double ms; };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune_cache;
 
@@ -1279,18 +1285,19 @@ nqs_status nqs_plan_autotune(nqs_plan* p, const float* params, const uint64_t* x
     if (it != g_tune_cache.end() && (!it->second.dedup || p->dedup_cap) && it->second.S <= p->S0) {
       p->variant = it->second.variant;
       p->dedup = it->second.dedup;
+      p->resident = it->second.resident;
       set_chunk(p, it->second.S);
       p->tuned = true;
       R.from_cache = 1;
       R.n_candidates = 1;
       R.chosen = 0;
       R.cand[0] = nqs_tune_candidate{forward_variant_waves(p->g.prec, p->g.h, p->variant), p->dedup ? 1 : 0, p->S,
-                                     it->second.ms};
+                                     p->resident ? 1 : 0, it->second.ms};
       return NQS_OK;
     }
   }
   if (flags & NQS_TUNE_CACHE_ONLY) return NQS_OK;
-  struct Cand { int v; bool d; int64_t S; };
+  struct Cand { int v; bool d; int64_t S; bool r; };
   std::vector<Cand> cands;
   const int nv = forward_variants(p->g.prec, p->g.h);
   std::vector<bool> dd = p->dedup_auto ? std::vector<bool>{false, true} : std::vector<bool>{p->dedup};
@@ -1298,7 +1305,8 @@ nqs_status nqs_plan_autotune(nqs_plan* p, const float* params, const uint64_t* x
   if (p->S0 >= 2) ss.push_back(p->S0 / 2);
   for (int v = 0; v < nv; ++v)
     for (bool d : dd)
-      for (int64_t S : ss) cands.push_back({v, d, S});
+      for (int64_t S : ss)
+        for (bool r : {false, true}) cands.push_back({v, d, S, r});
   if ((int)cands.size() > NQS_TUNE_MAX_CANDIDATES) cands.resize(NQS_TUNE_MAX_CANDIDATES);
   const int64_t probe = std::min<int64_t>(B, 2 * p->S0);
   const bool prof = p->prof;
@@ -1313,6 +1321,7 @@ nqs_status nqs_plan_autotune(nqs_plan* p, const float* params, const uint64_t* x
   for (size_t c = 0; c < cands.size(); ++c) {
     p->variant = cands[c].v;
     p->dedup = cands[c].d;
+    p->resident = cands[c].r;
     set_chunk(p, cands[c].S);
     launch_fill_u32(at<void>(ws, L.err), 0u, 1, s);
     st = run_local_energy(p, params, x, probe, el, ws, L);   // warm-up
@@ -1326,7 +1335,7 @@ nqs_status nqs_plan_autotune(nqs_plan* p, const float* params, const uint64_t* x
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
     R.cand[c] = nqs_tune_candidate{forward_variant_waves(p->g.prec, p->g.h, cands[c].v), cands[c].d ? 1 : 0,
-                                   cands[c].S, ms / 2.0};
+                                   cands[c].S, cands[c].r ? 1 : 0, ms / 2.0};
     if (best < 0 || ms / 2.0 < best_ms) { best = (int)c; best_ms = ms / 2.0; }
   }
   (void)hipEventDestroy(e0);
@@ -1338,11 +1347,12 @@ nqs_status nqs_plan_autotune(nqs_plan* p, const float* params, const uint64_t* x
   R.probe_samples = probe;
   p->variant = cands[best].v;
   p->dedup = cands[best].d;
+  p->resident = cands[best].r;
   set_chunk(p, cands[best].S);
   p->tuned = true;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = TuneVal{p->variant, p->dedup, p->S, best_ms};
+    g_tune_cache[key] = TuneVal{p->variant, p->dedup, p->S, p->resident, best_ms};
   }
   return NQS_OK;
 }
@@ -1355,18 +1365,18 @@ nqs_status nqs_tune_db_save(const char* path) {
   std::string tmp = std::string(path) + ".tmp";
   FILE* f = fopen(tmp.c_str(), "w");
   if (!f) return fail(NQS_ERR_INVALID_ARGUMENT, "cannot write %s", tmp.c_str());
-  fprintf(f, "# nqs tuner database v1: n L h precision K G entries_per_sample chunk dedup_auto device phase_mode"
-             " | waves dedup chunk ms\n");
+  fprintf(f, "# nqs tuner database v2: n L h precision K G entries_per_sample chunk dedup_auto device phase_mode"
+             " | waves dedup chunk resident ms\n");
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (const auto& kv : g_tune_cache) {
       const TuneKey& k = kv.first;
       const TuneVal& v = kv.second;
-      fprintf(f, "%d %d %d %d %lld %lld %lld %lld %d %d %d | %d %d %lld %.6f\n", std::get<0>(k), std::get<1>(k),
+      fprintf(f, "%d %d %d %d %lld %lld %lld %lld %d %d %d | %d %d %lld %d %.6f\n", std::get<0>(k), std::get<1>(k),
               std::get<2>(k), std::get<3>(k), (long long)std::get<4>(k), (long long)std::get<5>(k),
               (long long)std::get<6>(k), (long long)std::get<7>(k), std::get<8>(k), std::get<9>(k), std::get<10>(k),
               forward_variant_waves(std::get<3>(k), std::get<2>(k), v.variant), v.dedup ? 1 : 0, (long long)v.S,
-              v.ms);
+              v.resident ? 1 : 0, v.ms);
     }
   }
   const bool ok = fclose(f) == 0;
@@ -1385,15 +1395,29 @@ nqs_status nqs_tune_db_load(const char* path, int* n_loaded) {
   while (fgets(line, sizeof(line), f)) {
     ++lineno;
     if (line[0] == '#' || line[0] == '\n') continue;
-    int a[11] = {};
-    long long b[4] = {};
-    int waves = 0, dedup = 0;
-    long long S = 0;
+    // 11 key fields, "|", then waves, dedup, chunk, resident (integers) and ms
+    long long iv[15] = {};
     double ms = 0.0;
-    const int got = sscanf(line, "%d %d %d %d %lld %lld %lld %lld %d %d %d | %d %d %lld %lf", &a[0], &a[1], &a[2],
-                           &a[3], &b[0], &b[1], &b[2], &b[3], &a[8], &a[9], &a[10], &waves, &dedup, &S, &ms);
+    int ntok = 0;
+    bool whole = true;
+    char* save = nullptr;
+    for (char* tok = strtok_r(line, " \t\r\n", &save); tok && whole; tok = strtok_r(nullptr, " \t\r\n", &save)) {
+      char* end = nullptr;
+      if (ntok == 11) whole = strcmp(tok, "|") == 0;
+      else if (ntok == 16) ms = strtod(tok, &end);
+      else if (ntok < 16) iv[ntok < 11 ? ntok : ntok - 1] = strtoll(tok, &end, 10);
+      else whole = false;
+      if (end) whole = whole && end != tok && *end == 0;
+      ++ntok;
+    }
+    whole = whole && ntok == 17;
+    int a[11];
+    long long b[4] = {iv[4], iv[5], iv[6], iv[7]};
+    for (int k = 0; k < 11; ++k) a[k] = (int)iv[k];
+    const int waves = (int)iv[11], dedup = (int)iv[12], res = (int)iv[14];
+    const long long S = iv[13];
     int v = -1;
-    if (got == 15 && a[3] >= 0 && a[3] <= NQS_BF16W && a[2] > 0)
+    if (whole && a[3] >= 0 && a[3] <= NQS_BF16W && a[2] > 0 && (res == 0 || res == 1))
       for (int k = 0; k < forward_variants(a[3], a[2]); ++k)
         if (forward_variant_waves(a[3], a[2], k) == waves) v = k;
     if (v < 0 || S < 1 || S > b[3]) {
@@ -1403,7 +1427,7 @@ nqs_status nqs_tune_db_load(const char* path, int* n_loaded) {
     const TuneKey key{a[0], a[1], a[2], a[3], (int64_t)b[0], (int64_t)b[1], (int64_t)b[2], (int64_t)b[3], a[8], a[9],
                       a[10]};
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = TuneVal{v, dedup != 0, (int64_t)S, ms};
+    g_tune_cache[key] = TuneVal{v, dedup != 0, (int64_t)S, res != 0, ms};
     ++n;
   }
   fclose(f);
@@ -1411,7 +1435,7 @@ nqs_status nqs_tune_db_load(const char* path, int* n_loaded) {
   return st;
 }
 
-nqs_status nqs_plan_configure(nqs_plan* p, int waves_per_block, int dedup, int64_t chunk_samples) {
+nqs_status nqs_plan_configure(nqs_plan* p, int waves_per_block, int dedup, int64_t chunk_samples, int resident) {
   if (!p) return fail(NQS_ERR_INVALID_ARGUMENT, "plan is NULL");
   int v = -1;
   if (waves_per_block <= 0) v = p->variant;
@@ -1428,12 +1452,15 @@ nqs_status nqs_plan_configure(nqs_plan* p, int waves_per_block, int dedup, int64
                 (long long)p->S0);
   p->variant = v;
   if (dedup >= 0) p->dedup = dedup > 0;
+  if (resident >= 0) p->resident = resident > 0;
   if (chunk_samples > 0) set_chunk(p, chunk_samples);
   return NQS_OK;
 }
 
-nqs_status nqs_plan_kernel_info(const nqs_plan* p, int* waves_per_block, int* rows_per_block, int* tuned) {
+nqs_status nqs_plan_kernel_info(const nqs_plan* p, int* waves_per_block, int* rows_per_block, int* tuned,
+                                int* resident) {
   if (!p) return fail(NQS_ERR_INVALID_ARGUMENT, "plan is NULL");
+  if (resident) *resident = p->resident ? 1 : 0;
   if (waves_per_block) *waves_per_block = forward_variant_waves(p->g.prec, p->g.h, p->variant);
   if (rows_per_block) *rows_per_block = forward_rows_per_block(p->g.prec, p->g.h);
   if (tuned) *tuned = p->tuned ? 1 : 0;
@@ -1509,7 +1536,8 @@ nqs_status nqs_sample(nqs_plan* p, const float* params, int64_t n_draws, uint64_
   launch_pack_fused(p->g, params, packed, s);
   launch_sample_init(b.x, b.words, b.cnt, n_draws, b.d_u, s);
   for (int t = 0; t < p->g.n; ++t) {
-    launch_forward_cond(p->g, p->variant, packed, b.x, max_unique, b.d_u, b.cond, t, s);
+    launch_forward_cond(p->g, p->variant, p->resident, p->ctx->cu_count, packed, b.x, max_unique, b.d_u, b.cond, t,
+                        s);
     launch_sample_step(b, max_unique, t, (int)p->g.order[t], seed, s);
   }
   launch_sample_finish(b, max_unique, d_x, d_w, (long long*)d_n_unique, s);

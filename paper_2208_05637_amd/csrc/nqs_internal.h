@@ -124,25 +124,30 @@ struct FwdLaunch {
   int nseg;
   int cond_pos;   // -1: (log|psi|, phi); >= 0: (logit at that sampling position, forcing code)
   long long ntiles;
-  long long tile_base;   // tile of workgroup 0 (a launch too large for one dispatch is split)
+  long long tile_base;     // tile of workgroup 0 (a launch too large for one dispatch is split)
+  long long tile_stride;   // tiles between a workgroup's successive tiles
   FwdSeg seg[kMaxSeg];
 };
 
-// Fused forward, one workgroup per tile of forward_rows_per_block rows.
-// variant selects the workgroup shape (forward_variants /
-// forward_variant_waves).
-void launch_forward(const Geom& g, int variant, const void* packed, const uint64_t* x,
-                    long long rows_bound, const long long* d_count, double* out,
+// Fused forward over tiles of forward_rows_per_block rows.  variant selects
+// the workgroup shape (forward_variants / forward_variant_waves).  resident:
+// false = one workgroup per tile (the grid covers the row bound); true = as
+// many workgroups as fit on the device's cu_count CUs at once, each looping
+// over tiles with a stride of the grid size.  The rows and their arithmetic
+// are the same either way.
+void launch_forward(const Geom& g, int variant, bool resident, int cu_count, const void* packed,
+                    const uint64_t* x, long long rows_bound, const long long* d_count, double* out,
                     long long* prof_slot, hipStream_t s);
 // Several segments of networks with equal (precision, width); each segment's
 // geometry is read from seg.geom, a device copy written by launch_store_geom.
 // la.seg[*].tile0 and la.ntiles are filled in here.
-void launch_forward_multi(int prec, int h, int variant, FwdLaunch la, hipStream_t s);
+void launch_forward_multi(int prec, int h, int variant, bool resident, int cu_count, FwdLaunch la,
+                          hipStream_t s);
 // Conditional form for the sampler: out[row] = (o_t, code) with o_t the
 // conditional logit at sampling position t and code 0 (free), 1 (forced to
 // 0) or 2 (forced to 1) by the Hamming-weight modifier.
-void launch_forward_cond(const Geom& g, int variant, const void* packed, const uint64_t* x,
-                         long long rows_bound, const long long* d_count, double* out, int t,
+void launch_forward_cond(const Geom& g, int variant, bool resident, int cu_count, const void* packed,
+                         const uint64_t* x, long long rows_bound, const long long* d_count, double* out, int t,
                          hipStream_t s);
 void launch_store_geom(const Geom& g, Geom* dst, hipStream_t s);
 int forward_variants(int prec, int h);

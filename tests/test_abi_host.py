@@ -281,8 +281,8 @@ def test_tune_db_round_trip(lib, tmp_path):
     # one entry per precision kind with a workgroup shape every width offers
     src = tmp_path / "in.txt"
     lines = ["# comment line",
-             "60 4 1024 4 1189663 244771 73125 3670 1 0 0 | 8 1 3670 987.500000",
-             "24 2 256 1 29737 5479 1818 147669 0 0 0 | 8 0 73834 12.250000"]
+             "60 4 1024 4 1189663 244771 73125 3670 1 0 0 | 8 1 3670 1 987.500000",
+             "24 2 256 1 29737 5479 1818 147669 0 0 0 | 8 0 73834 0 12.250000"]
     src.write_text("\n".join(lines) + "\n")
     assert nqs.tune_db_load(src) == 2
     out = tmp_path / "out.txt"
@@ -295,7 +295,14 @@ def test_tune_db_round_trip(lib, tmp_path):
     with pytest.raises(nqs.NQSError):
         nqs.tune_db_load(bad)
     # a workgroup shape the kernel does not have is rejected
-    bad.write_text("60 4 1024 4 1189663 244771 73125 3670 1 0 0 | 5 1 3670 1.0\n")
+    bad.write_text("60 4 1024 4 1189663 244771 73125 3670 1 0 0 | 5 1 3670 0 1.0\n")
+    with pytest.raises(nqs.NQSError):
+        nqs.tune_db_load(bad)
+    # a grid field other than 0 or 1, and the earlier format without the grid field
+    bad.write_text("60 4 1024 4 1189663 244771 73125 3670 1 0 0 | 8 1 3670 2 1.0\n")
+    with pytest.raises(nqs.NQSError):
+        nqs.tune_db_load(bad)
+    bad.write_text("60 4 1024 4 1189663 244771 73125 3670 1 0 0 | 8 1 3670 1.0\n")
     with pytest.raises(nqs.NQSError):
         nqs.tune_db_load(bad)
     with pytest.raises(nqs.NQSError):

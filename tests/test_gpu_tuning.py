@@ -6,6 +6,8 @@
   bit-identical local energies (they change only which rows are evaluated
   together, never a row's arithmetic or a sample's summation order);
 * the autotuner times every candidate, applies the fastest and caches it;
+* the forward's two grids (one workgroup per tile; resident workgroups
+  looping over tiles) give bit-identical rows;
 * the multi-instance call with instances of different precisions (several
   forward launch groups) equals single-instance calls bit for bit.
 """
@@ -114,8 +116,10 @@ def test_autotune_times_candidates_and_caches(nqs, ctx):
     p = torch.from_numpy(params).cuda()
     rep = plan.autotune(p, xs, force=True)
     cands = rep["candidates"]
-    # 2 variants x dedup on/off x chunk {128, 64}
-    assert len(cands) == 8 and not rep["from_cache"]
+    # 2 variants x dedup on/off x chunk {128, 64} x grid (one workgroup per tile, resident)
+    assert len(cands) == 16 and not rep["from_cache"]
+    assert sorted({(c["waves_per_block"], c["dedup"], c["chunk_samples"], c["resident"]) for c in cands}) == \
+        sorted((w_, d_, c_, r_) for w_ in (8, 16) for d_ in (False, True) for c_ in (128, 64) for r_ in (False, True))
     assert rep["probe_samples"] == min(len(xs), 256)
     assert all(c["ms"] > 0 for c in cands)
     best = cands[rep["chosen"]]
@@ -123,13 +127,15 @@ def test_autotune_times_candidates_and_caches(nqs, ctx):
     info = plan.kernel_info()
     assert info["tuned"] and info["waves_per_block"] == best["waves_per_block"]
     assert plan.dedup == best["dedup"] and plan.chunk_samples == best["chunk_samples"]
-    print("autotune:", [(c["waves_per_block"], c["dedup"], c["chunk_samples"], round(c["ms"], 3))
+    assert info["resident"] == best["resident"]
+    print("autotune:", [(c["waves_per_block"], c["dedup"], c["chunk_samples"], c["resident"], round(c["ms"], 3))
                         for c in cands], "chosen", rep["chosen"])
     # a second plan of the same shape takes the cached choice without timing
     plan2 = nqs.Plan(ctx, H, 2, 512, N // 2, N // 2, "bf16x3", max_batch=len(xs), dedup="auto",
                      chunk_samples=128)
     rep2 = plan2.autotune(p, xs)
     assert rep2["from_cache"] and plan2.kernel_info()["waves_per_block"] == best["waves_per_block"]
+    assert plan2.kernel_info()["resident"] == best["resident"]
     # the tuned plan is still correct
     el = nqs.local_energy(plan2, p, xs).cpu().numpy()
     net = made.Net(n=n, n_layers=2, width=512, n_up=N // 2, n_dn=N // 2)
@@ -145,12 +151,14 @@ def test_multi_mixed_precisions_equal_single(nqs, ctx):
     specs = [(6, 0, "fp32", 256, 2, 300), (7, 1, "bf16x3", 512, 2, 200), (8, 2, "bf16x3", 512, 2, 150),
              (5, 3, "fp64", 128, 1, 100)]
     keep = []
-    for N, seed, prec, h, L, B in specs:
+    for k, (N, seed, prec, h, L, B) in enumerate(specs):
         n = 2 * N
         terms = hamiltonian(N, seed)
         H = nqs.Hamiltonian.from_terms(terms).upload(ctx)
         xs, w = unique_with_counts(sector_samples(n, N // 2, N // 2, B, seed=seed + 10))
         plan = nqs.Plan(ctx, H, L, h, N // 2, N // 2, prec, max_batch=len(xs), chunk_samples=max(8, len(xs) // 3))
+        # the two split-BF16 instances differ only in the forward's grid: two launch groups
+        plan.configure(resident=(k in (1, 3)))
         dev = ctx.device
         it = dict(plan=plan, params=torch.from_numpy(init_params(n, L, h, seed=seed)).to(dev),
                   samples=torch.from_numpy(xs.view(np.int64)).to(dev), weights=torch.from_numpy(w).to(dev),
@@ -170,8 +178,10 @@ def test_multi_mixed_precisions_equal_single(nqs, ctx):
 @pytest.mark.parametrize("N,B,order_seed", [(22, 24, None), (32, 12, None), (20, 24, 5)])
 def test_forward_launch_grouping_invariance(nqs, ctx, N, B, order_seed):
     """The connected-configuration rows give bit-identical log psi whether one
-    launch evaluates all of them or several launches evaluate slices (every
-    row's arithmetic is independent of the others and of the grid)."""
+    launch evaluates all of them or several launches evaluate slices, and
+    whether the grid holds one workgroup per tile or resident workgroups that
+    loop over tiles (every row's arithmetic is independent of the others and
+    of the grid)."""
     n = 2 * N
     terms = hamiltonian(N, 3)
     H = nqs.Hamiltonian.from_terms(terms).upload(ctx)
@@ -187,8 +197,13 @@ def test_forward_launch_grouping_invariance(nqs, ctx, N, B, order_seed):
         whole = nqs.log_psi(plan, p, ent)
         step = 37 * M + 5          # ragged slices: tile boundaries shift between launches
         parts = torch.cat([nqs.log_psi(plan, p, ent[i:i + step]) for i in range(0, ne, step)])
+        plan.configure(resident=True)
+        assert plan.kernel_info()["resident"]
+        res = nqs.log_psi(plan, p, ent)
+        res_parts = torch.cat([nqs.log_psi(plan, p, ent[i:i + step]) for i in range(0, ne, step)])
         torch.cuda.synchronize()
         assert torch.equal(whole, parts), (prec, N)
+        assert torch.equal(whole, res) and torch.equal(whole, res_parts), (prec, N, "resident")
 
 
 def test_forward_launch_split_beyond_32_bit_work_items(nqs, ctx):
@@ -212,4 +227,9 @@ def test_forward_launch_split_beyond_32_bit_work_items(nqs, ctx):
     la_ref, ph_ref, _ = made.forward(made.Net(n=n, n_layers=L, width=h), params, np.arange(4096, dtype=np.uint64))
     f = first.cpu().numpy()
     assert np.max(np.abs(f[:, 0] - la_ref)) <= 5e-4 and np.max(np.abs(f[:, 1] - ph_ref)) <= 5e-4
-    del out, xs
+    # the resident grid takes all 2^22 + 384 tiles in one dispatch
+    plan.configure(resident=True)
+    out2 = nqs.log_psi(plan, torch.from_numpy(params).cuda(), xs)
+    torch.cuda.synchronize()
+    assert torch.equal(out, out2)
+    del out, out2, xs

@@ -367,7 +367,8 @@ def test_wide_autotune_choices(nqs, ctx, h76):
     assert len(rep["candidates"]) >= 4
     by_shape = {}
     for c in rep["candidates"]:
-        plan.configure(waves_per_block=c["waves_per_block"], dedup=c["dedup"], chunk_samples=c["chunk_samples"])
+        plan.configure(waves_per_block=c["waves_per_block"], dedup=c["dedup"], chunk_samples=c["chunk_samples"],
+                       resident=c["resident"])
         el = nqs.local_energy(plan, params, xs).clone()
         first = by_shape.setdefault(c["waves_per_block"], el)
         assert torch.equal(el, first), c
