@@ -299,6 +299,8 @@ def main():
     ap.add_argument("--dedup", default=None, choices=["on", "off", "auto"],
                     help="override the workload's dedup setting")
     ap.add_argument("--waves", type=int, default=0, help="force the forward's waves per workgroup")
+    ap.add_argument("--resident", type=int, default=None, choices=[0, 1],
+                    help="with --waves: force the forward's grid (1 resident workgroups, 0 one per tile)")
     ap.add_argument("--samples", default="psi", choices=["psi", "sector"],
                     help="psi: the batch is drawn from the network with the GPU unique-sample sampler "
                          "(1e12 draws, the batch size as buffer capacity); sector: uniform sector draws")
@@ -356,7 +358,7 @@ def main():
     def tuned(pl, xs):
         """Apply the database's choice for this plan (or time the candidates with --tune)."""
         if args.waves:
-            pl.configure(waves_per_block=args.waves)
+            pl.configure(waves_per_block=args.waves, resident=None if args.resident is None else bool(args.resident))
             return None
         if args.tune:
             return pl.autotune(params, xs, force=True)
