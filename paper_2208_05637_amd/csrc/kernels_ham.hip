@@ -459,7 +459,7 @@ __global__ __launch_bounds__(512) void dedup_insert_kernel(const uint64_t* __res
 // Keys of any width (two-word keys, and one-word keys at exactly 64 qubits,
 // where every word is a configuration): one lane per entry, straight into the
 // global table.  A slot word holds (tag << 32) | the entry that inserted the
-// key (entries < 2^28, so a slot word is never the all-ones empty marker); a
+// key (entries < 2^30, so a slot word is never the all-ones empty marker); a
 // probe whose tag matches compares the full key with that entry's words in
 // xe, which earlier kernels wrote, so no lane waits on another.
 // eu[e] <- global slot of entry e's key; owner[slot] <- smallest entry holding it.

@@ -105,12 +105,12 @@ def test_energy_bar_40_qubits(nqs, ctx):
 
 def test_energy_bar_60_qubits(nqs, ctx):
     """The benchmark's workload at full size in its launch configuration (65,536 sampled configurations,
-    3,670-sample chunks, the tuned workgroup shape and dedup of the committed tuner database)."""
+    14,683-sample chunks, the tuned workgroup shape, grid and dedup of the committed tuner database)."""
     import os
     terms, H, params_np, p, cfg, x, w, plan = _workload(nqs, ctx, "c4")
     N = cfg["N"]
     assert plan.entries_per_sample == _closed_conn(N, N // 2, N // 2) - 1
-    assert plan.chunk_samples == (256 << 20) // 73125
+    assert plan.chunk_samples == (1 << 30) // 73125
     db = os.path.join(os.path.dirname(nqs.LIB_PATH), "tune_db.txt")
     nqs.tune_db_load(db)
     assert plan.autotune(p, x[:1], cache_only=True)["from_cache"]
