@@ -326,6 +326,8 @@ def main():
               "all-reduce of the gradient sums per step).", file=sys.stderr)
         sys.exit(2)
 
+    if args.tune:
+        os.environ.setdefault("NQS_TUNE_LOG", "1")   # the tuner reports each candidate as it is timed
     import numpy as np
     import torch
     import paper_2208_05637_amd as nqs

@@ -278,7 +278,9 @@ nqs_status nqs_plan_kernel_info(const nqs_plan* plan, int* waves_per_block, int*
    chunking and the grid change nothing; the two workgroup shapes split the
    head's k sum differently).  Synchronises the
    context's stream; not for use under graph capture.  d_ws must hold
-   nqs_plan_workspace_size(plan, B) bytes.  report may be NULL. */
+   nqs_plan_workspace_size(plan, B) bytes.  report may be NULL.  With the
+   environment variable NQS_TUNE_LOG set, each timed candidate is also
+   reported as one line on stderr. */
 #define NQS_TUNE_FORCE 1u
 #define NQS_TUNE_CACHE_ONLY 2u
 #define NQS_TUNE_MAX_CANDIDATES 16

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -1322,6 +1323,8 @@ nqs_status nqs_plan_autotune(nqs_plan* p, const float* params, const uint64_t* x
   HIP_TRY(hipEventCreate(&e1));
   int best = -1;
   double best_ms = 0.0;
+  // NQS_TUNE_LOG set: one line per timed candidate on stderr (a long tuning run shows its progress)
+  const bool log = getenv("NQS_TUNE_LOG") != nullptr;
   for (size_t c = 0; c < cands.size(); ++c) {
     p->variant = cands[c].v;
     p->dedup = cands[c].d;
@@ -1340,6 +1343,12 @@ nqs_status nqs_plan_autotune(nqs_plan* p, const float* params, const uint64_t* x
     HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
     R.cand[c] = nqs_tune_candidate{forward_variant_waves(p->g.prec, p->g.h, cands[c].v), cands[c].d ? 1 : 0,
                                    cands[c].S, cands[c].r ? 1 : 0, ms / 2.0};
+    if (log) {
+      fprintf(stderr, "nqs tuner: candidate %zu/%zu: %d waves, dedup %d, chunk %lld, %s grid: %.1f ms\n", c + 1,
+              cands.size(), R.cand[c].waves_per_block, R.cand[c].dedup, (long long)R.cand[c].chunk_samples,
+              cands[c].r ? "resident" : "one-tile", ms / 2.0);
+      fflush(stderr);
+    }
     if (best < 0 || ms / 2.0 < best_ms) { best = (int)c; best_ms = ms / 2.0; }
   }
   (void)hipEventDestroy(e0);
