@@ -483,6 +483,10 @@ nqs_status nqs_plan_profile_read(nqs_plan* plan, void* d_ws, nqs_profile* out);
    workspace d_ws into *flags (NQS_DEV_* bits) and clears it.  Not for use
    inside graph capture. */
 nqs_status nqs_device_status(nqs_ctx* ctx, void* d_ws, uint32_t* flags);
+/* The same for a multi-instance call's workspace d_ws: reads and clears the
+   error word of every instance of inst (the list given to
+   nqs_energy_grad_multi) and sets *flags to their bitwise or. */
+nqs_status nqs_multi_device_status(int n_inst, const nqs_instance* inst, void* d_ws, uint32_t* flags);
 
 #ifdef __cplusplus
 }

@@ -103,6 +103,7 @@ SIGNATURES = {
     "nqs_adam_step": (C.c_int, [_P, _I64, _P, _P, _P, _P, _I64, C.c_double, C.c_double, C.c_double,
                                 C.c_double]),
     "nqs_device_status": (C.c_int, [_P, _P, C.POINTER(C.c_uint32)]),
+    "nqs_multi_device_status": (C.c_int, [C.c_int, C.POINTER(Instance), _P, C.POINTER(C.c_uint32)]),
     "nqs_plan_profile": (C.c_int, [_P, C.c_int]),
     "nqs_plan_profile_read": (C.c_int, [_P, _P, C.POINTER(Profile)]),
 }

@@ -398,6 +398,17 @@ def energy_grad_multi(items, workspace=None):
     L.check(lib.nqs_energy_grad_multi(len(items), _instances(items), ws, nb), "nqs_energy_grad_multi")
 
 
+def multi_device_status(items, workspace):
+    """Device error words (or-ed) of a multi-instance call's instances, read and cleared."""
+    _, ws, _ = workspace
+    lib = L.load()
+    flags = C.c_uint32()
+    st = lib.nqs_multi_device_status(len(items), _instances(items), ws, C.byref(flags))
+    if st not in (L.NQS_OK, 6):
+        L.check(st, "nqs_multi_device_status")
+    return flags.value
+
+
 def sample(plan, params, n_draws, seed, max_unique):
     """Unique-sample autoregressive sampling (Sec. 4): (x int64 [U] or [U, W], weights f64 [U])."""
     params = _params(plan, params)

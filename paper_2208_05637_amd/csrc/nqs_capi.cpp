@@ -1658,4 +1658,26 @@ nqs_status nqs_device_status(nqs_ctx* ctx, void* ws, uint32_t* flags) {
   return v ? fail(NQS_ERR_DEVICE, "device error word 0x%x", v) : NQS_OK;
 }
 
+nqs_status nqs_multi_device_status(int n_inst, const nqs_instance* inst, void* ws, uint32_t* flags) {
+  if (!ws || !flags) return fail(NQS_ERR_INVALID_ARGUMENT, "NULL argument");
+  std::vector<size_t> base;
+  size_t total = 0;
+  nqs_status st = multi_layout(n_inst, inst, base, total);
+  if (st != NQS_OK) return st;
+  *flags = 0;
+  if (n_inst == 0) return NQS_OK;
+  HIP_TRY(hipStreamSynchronize(inst[0].plan->ctx->stream));
+  unsigned acc = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    char* w = (char*)ws + base[i] + layout(inst[i].plan, inst[i].B).err;
+    unsigned v = 0;
+    HIP_TRY(hipMemcpy(&v, w, 4, hipMemcpyDeviceToHost));
+    const unsigned zero = 0;
+    HIP_TRY(hipMemcpy(w, &zero, 4, hipMemcpyHostToDevice));
+    acc |= v;
+  }
+  *flags = acc;
+  return acc ? fail(NQS_ERR_DEVICE, "device error word 0x%x", acc) : NQS_OK;
+}
+
 }  // extern "C"

@@ -141,9 +141,10 @@ def test_energy_bar_four_instances_one_call(nqs, ctx):
     ws = nqs.multi_workspace(items)
     nqs.energy_grad_multi(items, ws)
     torch.cuda.synchronize()
+    assert nqs.multi_device_status(items, ws) == 0
     for it, (terms, H, params_np, cfg) in zip(items, refs):
-        assert nqs.device_status(it["plan"]) == 0
         e1, g1, l1 = nqs.energy_grad(it["plan"], it["params"], it["samples"], it["weights"])
+        assert nqs.device_status(it["plan"]) == 0
         assert torch.equal(l1, it["eloc"]) and torch.equal(g1, it["grad"]) and torch.equal(e1, it["energy"])
         _bar(nqs, ctx, terms, H, cfg, params_np, it["params"], it["samples"], it["weights"],
              it["eloc"].cpu().numpy(), f"{cfg['n']} qubits in the four-instance call, {it['samples'].shape[0]}")
