@@ -231,11 +231,11 @@ def multi_instances(nqs, ctx):
     e1.record(ctx.stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
+    status = nqs.multi_device_status(items, ws)
     for r, it in zip(rows, items):
         r["energy"] = float(it["energy"][0].item())
-        r["device_status"] = nqs.device_status(it["plan"])
     st = sum(r["samples"] * r["terms"] for r in rows)
-    res = {"ms_per_call": ms, "samples_terms_per_s": st / (ms / 1e3), "instances": rows,
+    res = {"ms_per_call": ms, "samples_terms_per_s": st / (ms / 1e3), "instances": rows, "device_status": status,
            "samples_kind": "unique configurations drawn from each instance's network (10^12 draws)"}
     log(f"four instances, one call: {ms:.1f} ms, {res['samples_terms_per_s']:.3e} samples*terms/s")
     return res
