@@ -225,7 +225,11 @@ nqs_status nqs_net_param_count(const nqs_net_desc* net, int64_t* n_params);
 
 /* --------------------------------------------------------------------- plan */
 /* Dedup applies at every width (Sec. 5.2, local removal of replicated
-   configurations). */
+   configurations).  Below 64 qubits (one-word strings whose table holds the
+   strings themselves) it also looks back one chunk: a chunk's distinct
+   configurations that the previous chunk of the same call evaluated take that
+   chunk's log psi instead of a forward row (the same values; the workspace
+   then holds two hash tables and two log psi sets). */
 #define NQS_PLAN_DEDUP_ON   1u   /* deduplicate connected configurations per chunk */
 #define NQS_PLAN_DEDUP_OFF  2u   /* never deduplicate (default when no flag is set) */
 #define NQS_PLAN_DEDUP_AUTO 4u   /* size the workspace for dedup, start with it on and

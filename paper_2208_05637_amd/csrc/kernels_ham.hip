@@ -551,6 +551,88 @@ __global__ void dedup_remap_kernel(const long long* __restrict__ d_count, long l
 
 long long dedup_rank_tmp_elems(long long cap) { return scan_tiles(cap) + 1; }
 
+// Look-back to the previous chunk (one-word keys below 64 qubits, whose
+// table holds the keys themselves): the previous chunk's table maps a key to
+// its rank among that chunk's distinct configurations (its slot words hold
+// the ranks after the remap), so a distinct configuration of this chunk that
+// the previous chunk already evaluated takes that value instead of a forward
+// row.  src[u] = the previous rank or -1; isnew[u] = 1 where src[u] < 0 (0
+// past the count, for the scan).
+__global__ void lookback_probe_kernel(const uint64_t* __restrict__ xu, const long long* __restrict__ d_nu,
+                                      long long cap, const unsigned long long* __restrict__ pkeys,
+                                      const int* __restrict__ prank, long long HT, int* __restrict__ src,
+                                      int* __restrict__ isnew) {
+  const long long nu = *d_nu < cap ? *d_nu : cap;
+  const unsigned long long hmask = (unsigned long long)HT - 1;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x; u < cap; u += stride) {
+    if (u >= nu) {
+      isnew[u] = 0;
+      continue;
+    }
+    const unsigned long long key = xu[u];
+    unsigned long long gs = mix64(key) & hmask;
+    int r = -1;
+    for (long long probe = 0; probe < HT; ++probe) {
+      const unsigned long long k = pkeys[gs];
+      if (k == key) { r = prank[gs]; break; }
+      if (k == kEmpty) break;
+      gs = (gs + 1) & hmask;
+    }
+    src[u] = r;
+    isnew[u] = r < 0 ? 1 : 0;
+  }
+}
+
+// The new configurations in order: xnew[rank[u]] = xu[u] (rank: the exclusive
+// scan of isnew); *d_nnew = their number.
+__global__ void lookback_compact_kernel(const uint64_t* __restrict__ xu, const long long* __restrict__ d_nu,
+                                        long long cap, const int* __restrict__ isnew,
+                                        const long long* __restrict__ rank, uint64_t* __restrict__ xnew,
+                                        long long* __restrict__ d_nnew) {
+  const long long nu = *d_nu < cap ? *d_nu : cap;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i0 == 0) *d_nnew = rank[cap];
+  for (long long u = i0; u < nu; u += stride)
+    if (isnew[u]) xnew[rank[u]] = xu[u];
+}
+
+// lp[u] = lp_prev[src[u]] for a configuration the previous chunk evaluated,
+// lp_new[rank[u]] for a new one (pairs of doubles).
+__global__ void lookback_gather_kernel(const long long* __restrict__ d_nu, long long cap, const int* __restrict__ src,
+                                       const long long* __restrict__ rank, const double2* __restrict__ lp_prev,
+                                       const double2* __restrict__ lp_new, double2* __restrict__ lp) {
+  const long long nu = *d_nu < cap ? *d_nu : cap;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x; u < nu; u += stride) {
+    const int r = src[u];
+    lp[u] = r >= 0 ? lp_prev[r] : lp_new[rank[u]];
+  }
+}
+
+static long long lookback_blocks(long long cap) {
+  long long blocks = (cap + 255) / 256;
+  return blocks > 16384 ? 16384 : (blocks < 1 ? 1 : blocks);
+}
+
+void launch_lookback(const uint64_t* xu, const long long* d_nu, long long cap, const uint64_t* pkeys,
+                     const int* prank, long long HT, int* src, int* isnew, long long* rank, long long* rank_tmp,
+                     uint64_t* xnew, long long* d_nnew, hipStream_t s) {
+  const long long blocks = lookback_blocks(cap);
+  hipLaunchKernelGGL(lookback_probe_kernel, dim3((unsigned)blocks), dim3(256), 0, s, xu, d_nu, cap,
+                     (const unsigned long long*)pkeys, prank, HT, src, isnew);
+  launch_scan(isnew, cap, rank, rank_tmp, s);
+  hipLaunchKernelGGL(lookback_compact_kernel, dim3((unsigned)blocks), dim3(256), 0, s, xu, d_nu, cap, isnew, rank,
+                     xnew, d_nnew);
+}
+
+void launch_lookback_gather(const long long* d_nu, long long cap, const int* src, const long long* rank,
+                            const double* lp_prev, const double* lp_new, double* lp, hipStream_t s) {
+  hipLaunchKernelGGL(lookback_gather_kernel, dim3((unsigned)lookback_blocks(cap)), dim3(256), 0, s, d_nu, cap, src,
+                     rank, (const double2*)lp_prev, (const double2*)lp_new, (double2*)lp);
+}
+
 void launch_dedup(const uint64_t* xe, int words, bool all_ones_key, const long long* d_count, long long cap,
                   uint64_t* hkeys, int* hslot, long long HT, int* eu, uint64_t* xu, long long* d_nu,
                   int* first, long long* rank, long long* rank_tmp, unsigned* err, hipStream_t s) {

@@ -159,6 +159,7 @@ struct nqs_plan {
   int R = 1, gper = 0;     // group ranges of the enumeration grid for S
   bool dedup = false;      // dedup on for this plan's calls
   bool dedup_cap = false;  // workspace holds the dedup tables
+  bool lookback = false;   // with dedup: a chunk reuses the previous chunk's log psi (one-word keys below 64 qubits)
   bool dedup_auto = false; // the autotuner may switch dedup
   int variant = 0;         // forward kernel variant
   bool resident = false;   // forward grid: resident workgroups looping over tiles
@@ -182,7 +183,7 @@ constexpr int kProfSlots = 8192;
 
 struct WsLayout {
   size_t err, prof, geom, packed, wm, lps, eloc, energy, cnt, off, stmp, rpart, diag, xe, he, lpe, hkeys, hslot,
-      eu, xu, nu, dfirst, drank, drtmp, bscratch, total;
+      eu, xu, nu, dfirst, drank, drtmp, hkeys2, hslot2, lp2, lpn, src, nnew, bscratch, total;
 };
 
 // Enumeration grid for chunks of S samples: R ranges of gper flip groups.
@@ -224,6 +225,14 @@ static WsLayout layout(const nqs_plan* p, int64_t B) {
     L.dfirst = take((size_t)p->EC * 4);
     L.drank = take(((size_t)p->EC + 1) * 8);
     L.drtmp = take((size_t)dedup_rank_tmp_elems(p->EC) * 8);
+    if (p->lookback) {   // the second table and log psi set, the new rows' log psi, the look-back map
+      L.hkeys2 = take((size_t)p->HT * 8);
+      L.hslot2 = take((size_t)p->HT * 4);
+      L.lp2 = take((size_t)p->EC * 16);
+      L.lpn = take((size_t)p->EC * 16);
+      L.src = take((size_t)p->EC * 4);
+      L.nnew = take(8);
+    }
   }
   L.bscratch = take((size_t)backward_scratch_elems(p->g, p->Sb) * p->bw);
   L.total = o;
@@ -767,6 +776,7 @@ nqs_status nqs_plan_create(nqs_ctx* ctx, const nqs_ham* ham, const nqs_net_desc*
     int64_t ht = 4096;
     while (ht < 2 * p->EC) ht <<= 1;
     p->HT = ht;
+    p->lookback = g.words == 1 && g.n < 64;
   }
   p->Sb = std::min<int64_t>(max_batch, 4096);
   p->bw = g.prec == P_F64 ? 8 : 4;
@@ -944,11 +954,18 @@ struct ChunkFwd {
   const long long* d_count;   // their number (device)
   long long bound;            // host bound on that number
   double* out;                // log psi of each
+  double* lp;                 // log psi the reduce reads: per entry, or per distinct configuration with dedup
+  bool gather;                // out holds only the configurations new to this chunk (look-back)
 };
 
 // Enumerate (and optionally deduplicate) the connected configurations of
-// samples [c0, c0 + Sc).
-static ChunkFwd enum_chunk(nqs_plan* p, const uint64_t* x, int64_t c0, int64_t Sc, void* ws, const WsLayout& L) {
+// samples [c0, c0 + Sc), chunk k of the call.  With look-back, chunks
+// alternate between two tables and two log psi sets: chunk k probes chunk
+// k - 1's table for its distinct configurations and evaluates only those the
+// previous chunk did not (each row's log psi depends on that row alone, so the
+// reused values are the ones the forward would give).
+static ChunkFwd enum_chunk(nqs_plan* p, const uint64_t* x, int64_t c0, int64_t Sc, int64_t k, void* ws,
+                           const WsLayout& L) {
   hipStream_t s = p->ctx->stream;
   const HamDev H = ham_dev(p);
   const int hs = p->ham->has_imag ? 2 : 1;
@@ -963,22 +980,41 @@ static ChunkFwd enum_chunk(nqs_plan* p, const uint64_t* x, int64_t c0, int64_t S
   launch_write(H, xc, Sc, p->R, p->gper, off, p->EC, xe, at<double>(ws, L.he), nullptr, hs, err, s);
   const long long* d_total = off + Sc * p->R;
   const int64_t bound = std::min<int64_t>(Sc * p->Emax, p->EC);
-  if (p->dedup) {
-    uint64_t* xu = at<uint64_t>(ws, L.xu);
-    long long* nu = at<long long>(ws, L.nu);
-    launch_dedup(xe, p->g.words, p->g.n == 64, d_total, p->EC, at<uint64_t>(ws, L.hkeys), at<int>(ws, L.hslot), p->HT, at<int>(ws, L.eu), xu,
-                 nu, at<int>(ws, L.dfirst), at<long long>(ws, L.drank), at<long long>(ws, L.drtmp), err, s);
-    return {xu, nu, bound, at<double>(ws, L.lpe)};
-  }
-  return {xe, d_total, bound, at<double>(ws, L.lpe)};
+  double* lpe = at<double>(ws, L.lpe);
+  if (!p->dedup) return {xe, d_total, bound, lpe, lpe, false};
+  uint64_t* xu = at<uint64_t>(ws, L.xu);
+  long long* nu = at<long long>(ws, L.nu);
+  const bool odd = p->lookback && (k & 1);
+  uint64_t* hkeys = at<uint64_t>(ws, odd ? L.hkeys2 : L.hkeys);
+  int* hslot = at<int>(ws, odd ? L.hslot2 : L.hslot);
+  double* lp = odd ? at<double>(ws, L.lp2) : lpe;
+  launch_dedup(xe, p->g.words, p->g.n == 64, d_total, p->EC, hkeys, hslot, p->HT, at<int>(ws, L.eu), xu, nu,
+               at<int>(ws, L.dfirst), at<long long>(ws, L.drank), at<long long>(ws, L.drtmp), err, s);
+  if (!p->lookback || k == 0) return {xu, nu, bound, lp, lp, false};
+  // the entries are dead once deduplicated: xe takes the new configurations
+  long long* nnew = at<long long>(ws, L.nnew);
+  launch_lookback(xu, nu, p->EC, at<uint64_t>(ws, odd ? L.hkeys : L.hkeys2), at<int>(ws, odd ? L.hslot : L.hslot2),
+                  p->HT, at<int>(ws, L.src), at<int>(ws, L.dfirst), at<long long>(ws, L.drank),
+                  at<long long>(ws, L.drtmp), xe, nnew, s);
+  return {xe, nnew, bound, at<double>(ws, L.lpn), lp, true};
+}
+
+// After the chunk's forward: with look-back, the distinct configurations' log
+// psi from the previous chunk's set and the new rows.
+static void finish_chunk(nqs_plan* p, const ChunkFwd& cf, void* ws, const WsLayout& L) {
+  if (!cf.gather) return;
+  const double* prev = cf.lp == at<double>(ws, L.lpe) ? at<double>(ws, L.lp2) : at<double>(ws, L.lpe);
+  launch_lookback_gather(at<long long>(ws, L.nu), p->EC, at<int>(ws, L.src), at<long long>(ws, L.drank), prev,
+                         cf.out, cf.lp, p->ctx->stream);
 }
 
 // Ratio-and-reduce of the chunk into eloc[c0 .. c0 + Sc).
-static void reduce_chunk(nqs_plan* p, int64_t c0, int64_t Sc, void* ws, const WsLayout& L, double* eloc) {
+static void reduce_chunk(nqs_plan* p, int64_t c0, int64_t Sc, const ChunkFwd& cf, void* ws, const WsLayout& L,
+                         double* eloc) {
   const int hs = p->ham->has_imag ? 2 : 1;
   launch_reduce(Sc, p->R, at<long long>(ws, L.off), p->EC, at<double>(ws, L.diag), at<double>(ws, L.he), hs,
-                p->dedup ? at<int>(ws, L.eu) : nullptr, at<double>(ws, L.lpe), at<double>(ws, L.lps) + 2 * c0,
-                eloc + 2 * c0, at<double>(ws, L.rpart), at<unsigned>(ws, L.err), p->ctx->stream);
+                p->dedup ? at<int>(ws, L.eu) : nullptr, cf.lp, at<double>(ws, L.lps) + 2 * c0, eloc + 2 * c0,
+                at<double>(ws, L.rpart), at<unsigned>(ws, L.err), p->ctx->stream);
 }
 
 // local energies of B samples into eloc; lps (sample log psi) computed first.
@@ -987,11 +1023,12 @@ static nqs_status run_local_energy(nqs_plan* p, const float* params, const uint6
   void* packed = at<void>(ws, L.packed);
   pack_net(p, params, packed, p->ctx->stream);
   forward_profiled(p, ws, L, packed, x, B, nullptr, at<double>(ws, L.lps));
-  for (int64_t c0 = 0; c0 < B; c0 += p->S) {
+  for (int64_t c0 = 0, k = 0; c0 < B; c0 += p->S, ++k) {
     const int64_t Sc = std::min<int64_t>(p->S, B - c0);
-    const ChunkFwd cf = enum_chunk(p, x, c0, Sc, ws, L);
+    const ChunkFwd cf = enum_chunk(p, x, c0, Sc, k, ws, L);
     forward_profiled(p, ws, L, packed, cf.x, cf.bound, cf.d_count, cf.out);
-    reduce_chunk(p, c0, Sc, ws, L, eloc);
+    finish_chunk(p, cf, ws, L);
+    reduce_chunk(p, c0, Sc, cf, ws, L, eloc);
   }
   return launch_check("local energy");
 }
@@ -1221,20 +1258,25 @@ nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* ws,
     hg.clear();
     std::vector<int> rid;
     std::vector<int64_t> c0s, scs;
+    std::vector<ChunkFwd> cfs;
     for (int i = 0; i < n_inst; ++i) {
       nqs_plan* p = inst[i].plan;
       const int64_t c0 = r * p->S;
       if (c0 >= inst[i].B) continue;
       const int64_t Sc = std::min<int64_t>(p->S, inst[i].B - c0);
-      const ChunkFwd cf = enum_chunk(p, inst[i].d_samples, c0, Sc, W[i], L[i]);
+      const ChunkFwd cf = enum_chunk(p, inst[i].d_samples, c0, Sc, r, W[i], L[i]);
       rid.push_back(i);
       c0s.push_back(c0);
       scs.push_back(Sc);
+      cfs.push_back(cf);
       add_segs(i, cf.x, cf.d_count, cf.out, cf.bound, ids, segs);
     }
     if (ids.empty()) break;
     launch_groups(ids, segs);
-    for (size_t k = 0; k < rid.size(); ++k) reduce_chunk(inst[rid[k]].plan, c0s[k], scs[k], W[rid[k]], L[rid[k]], EL[rid[k]]);
+    for (size_t k = 0; k < rid.size(); ++k) {
+      finish_chunk(inst[rid[k]].plan, cfs[k], W[rid[k]], L[rid[k]]);
+      reduce_chunk(inst[rid[k]].plan, c0s[k], scs[k], cfs[k], W[rid[k]], L[rid[k]], EL[rid[k]]);
+    }
   }
   for (int i = 0; i < n_inst; ++i) {
     const nqs_instance& I = inst[i];

@@ -9,7 +9,10 @@
 * the forward's two grids (one workgroup per tile; resident workgroups
   looping over tiles) give bit-identical rows;
 * the multi-instance call with instances of different precisions (several
-  forward launch groups) equals single-instance calls bit for bit.
+  forward launch groups) equals single-instance calls bit for bit;
+* dedup's look-back to the previous chunk evaluates exactly the distinct
+  connected configurations that chunk did not (counted here from the oracle's
+  connected sets) and changes no local energy, in single and multi calls.
 """
 import numpy as np
 import pytest
@@ -233,3 +236,81 @@ def test_forward_launch_split_beyond_32_bit_work_items(nqs, ctx):
     torch.cuda.synchronize()
     assert torch.equal(out, out2)
     del out, out2, xs
+
+
+def _lookback_rows(ref, xs, chunk):
+    """Forward rows of a dedup call with look-back: the B sample rows, then
+    per chunk its distinct connected configurations less those of the chunk
+    before it (connected sets from the oracle, spin-sector filtered)."""
+    _, ent = vmc.connected(ref, xs, sector_filter=True)
+    rows, prev = len(xs), set()
+    for c0 in range(0, len(xs), chunk):
+        cur = set()
+        for gi, xp, hv in ent[c0:c0 + chunk]:
+            cur.update(int(v) for v in xp)
+        rows += len(cur - prev)
+        prev = cur
+    return rows
+
+
+@pytest.mark.parametrize("N,B,chunk,seed", [(6, 400, 40, 1), (6, 400, 7, 2), (10, 600, 64, 3), (12, 256, 30, 4)])
+def test_dedup_look_back_rows_and_values(nqs, ctx, N, B, chunk, seed):
+    """Samples in an order that makes neighbouring chunks share connected
+    configurations: every sector configuration of 12 qubits, shuffled, and
+    sampler-like streams at 20 and 24 qubits (each sample one excitation away
+    from the one before)."""
+    n = 2 * N
+    terms = hamiltonian(N, 0)
+    ref = pauli.canonical_terms(terms.x_mask, terms.z_mask, terms.coeff)
+    H = nqs.Hamiltonian.from_terms(terms, conserves_spin=True).upload(ctx)
+    rng = np.random.default_rng(seed)
+    if N == 6:
+        xs = pauli.sector_basis(n, 3, 3).astype(np.uint64)
+        xs = xs[rng.permutation(len(xs))][:B]
+    else:
+        x = sector_samples(n, N // 2, N // 2, 1, seed=seed)[0]
+        seen, out = set(), []
+        while len(out) < B:           # a walk over single same-spin hops
+            if int(x) not in seen:
+                seen.add(int(x))
+                out.append(x)
+            bits = [b for b in range(n) if (int(x) >> b) & 1]
+            i = int(rng.choice(bits))
+            holes = [b for b in range(i % 2, n, 2) if not (int(x) >> b) & 1]
+            j = int(rng.choice(holes))
+            x = np.uint64(int(x) ^ (1 << i) ^ (1 << j))
+        xs = np.array(out, dtype=np.uint64)
+    B = len(xs)
+    w = np.full(B, 1.0 / B)
+    p = torch.from_numpy(init_params(n, 1, 64, seed=seed)).cuda()
+    on = nqs.Plan(ctx, H, 1, 64, N // 2, N // 2, "fp64", max_batch=B, chunk_samples=chunk, dedup=True)
+    off = nqs.Plan(ctx, H, 1, 64, N // 2, N // 2, "fp64", max_batch=B, chunk_samples=chunk, dedup=False)
+    on.profile(True)
+    e_on = nqs.local_energy(on, p, xs)
+    torch.cuda.synchronize()
+    prof = on.profile_read()
+    on.profile(False)
+    e_off = nqs.local_energy(off, p, xs)
+    torch.cuda.synchronize()
+    assert nqs.device_status(on) == 0 and nqs.device_status(off) == 0
+    assert torch.equal(e_on, e_off)
+    nchunks = (B + chunk - 1) // chunk
+    assert prof["forward_launches"] == 1 + nchunks
+    expect = _lookback_rows(ref, xs, chunk)
+    print(f"N={N} B={B} chunk={chunk}: {int(prof['forward_rows'])} forward rows, expected {expect}")
+    assert int(prof["forward_rows"]) == expect
+    # the multi-instance form: two instances with different chunkings, one with look-back
+    dev = ctx.device
+    items = []
+    for plan in (on, off):
+        items.append(dict(plan=plan, params=p, samples=torch.from_numpy(xs.view(np.int64)).to(dev),
+                          weights=torch.from_numpy(w).to(dev),
+                          eloc=torch.empty((B, 2), dtype=torch.float64, device=dev),
+                          energy=torch.empty(3, dtype=torch.float64, device=dev),
+                          grad=torch.empty(on.n_params, dtype=torch.float64, device=dev)))
+    ws = nqs.multi_workspace(items)
+    nqs.energy_grad_multi(items, ws)
+    torch.cuda.synchronize()
+    assert nqs.multi_device_status(items, ws) == 0
+    for it in items:
+        assert torch.equal(it["eloc"], e_off)
