@@ -374,19 +374,36 @@ void launch_seg_offsets(const int* esample, long long n_entries, long long B, lo
 }
 
 // ------------------------------------------------------------------ dedup
-// Two-level open addressing: each workgroup first collapses its tile of
-// entries in an LDS table, then inserts only the tile-unique keys into the
-// global table.  Keys are x' values; the all-ones word marks an empty slot,
-// which below 64 qubits is no configuration (at exactly 64 qubits, and for
-// two-word keys, the slot-word insert below is used instead).  Each global slot also records the first entry that
-// holds its key; the distinct configurations are then listed in the order of
-// their first entries (sample-major, as the entries are), so rows that follow
-// each other in the forward stay alike, and the list does not depend on the
-// hash layout or on scheduling.
+// Open addressing with linear probing over a table of 16-byte records (a key
+// word and an int: the owner or rank of the key), so that a probe and the
+// update of its slot touch one cache line.  Keys are x' values; the all-ones
+// word marks an empty slot, which below 64 qubits is no configuration.  At
+// exactly 64 qubits, and for two-word keys, a key word is a slot word instead:
+// (hash tag << 32) | the entry that inserted the key (entries < 2^30, so a
+// slot word is never the all-ones marker), and a probe whose tag matches
+// compares the full key with that entry's words.
+//
+// Two orders of the distinct configurations:
+//  - first-entry order (the connected-set call, whose output lists them): each
+//    slot records the smallest entry holding its key, then a scan over the
+//    first holders ranks them, sample-major as the entries are, independent
+//    of the hash layout and of scheduling;
+//  - insertion order (the local-energy chunks): the entry whose insert filled
+//    a slot ranks it, each workgroup taking a block of ranks for its inserts
+//    in entry order.  One pass and one table line per entry; the ranks follow
+//    the entries' order up to the interleaving of workgroups.  Every row's log
+//    psi depends on that row alone, so the order changes no value.
 constexpr unsigned long long kEmpty = ~0ull;
 constexpr int kDedupTile = 2048;
 constexpr int kDedupLds = 4096;
 constexpr int kNoEntry = 0x7FFFFFFF;
+
+struct __align__(16) HRec {
+  unsigned long long key;
+  int rank;   // the owner (smallest entry) while inserting in first-entry order, then the rank
+  int pad;
+};
+static_assert(sizeof(HRec) == kHashRecBytes, "hash record size");
 
 __device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
   z ^= z >> 30; z *= 0xbf58476d1ce4e5b9ull;
@@ -395,12 +412,22 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
   return z;
 }
 
-// eu[e] <- global slot of entry e's key; owner[slot] <- smallest entry holding it.
+__global__ void fill_rec_kernel(HRec* __restrict__ t, long long count) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  HRec e;
+  e.key = kEmpty;
+  e.rank = kNoEntry;
+  e.pad = 0;
+  for (; i < count; i += stride) t[i] = e;
+}
+
+// First-entry order, one-word keys below 64 qubits: each workgroup collapses
+// its tile of entries in an LDS table first, then inserts the tile-unique keys.
+// eu[e] <- global slot of entry e's key; rank field <- smallest entry holding it.
 __global__ __launch_bounds__(512) void dedup_insert_kernel(const uint64_t* __restrict__ xe,
                                                            const long long* __restrict__ d_count,
-                                                           long long cap,
-                                                           unsigned long long* __restrict__ hkeys,
-                                                           int* __restrict__ owner,
+                                                           long long cap, HRec* __restrict__ tab,
                                                            long long HT, int* __restrict__ eu,
                                                            unsigned* err) {
   __shared__ unsigned long long lkeys[kDedupLds];
@@ -440,12 +467,12 @@ __global__ __launch_bounds__(512) void dedup_insert_kernel(const uint64_t* __res
     unsigned long long gs = mix64(key) & hmask;
     int found = -1;
     for (long long probe = 0; probe < HT; ++probe) {
-      unsigned long long prev = atomicCAS(&hkeys[gs], kEmpty, key);
+      unsigned long long prev = atomicCAS(&tab[gs].key, kEmpty, key);
       if (prev == kEmpty || prev == key) { found = (int)gs; break; }
       gs = (gs + 1) & hmask;
     }
     if (found < 0) atomicOr(err, kErrHashOverflow);
-    else atomicMin(&owner[found], lmin[s]);
+    else atomicMin(&tab[found].rank, lmin[s]);
     lglob[s] = found;
   }
   __syncthreads();
@@ -456,20 +483,49 @@ __global__ __launch_bounds__(512) void dedup_insert_kernel(const uint64_t* __res
   }
 }
 
-// Keys of any width (two-word keys, and one-word keys at exactly 64 qubits,
-// where every word is a configuration): one lane per entry, straight into the
-// global table.  A slot word holds (tag << 32) | the entry that inserted the
-// key (entries < 2^30, so a slot word is never the all-ones empty marker); a
-// probe whose tag matches compares the full key with that entry's words in
-// xe, which earlier kernels wrote, so no lane waits on another.
-// eu[e] <- global slot of entry e's key; owner[slot] <- smallest entry holding it.
+// Probe for entry e's key (W words, key: its words, hsh: its hash); inserts it
+// when absent.  Returns the slot (or -1 when the table is full) and sets won
+// when this call filled the slot.
+template <int W, bool SLOT>
+__device__ __forceinline__ int dedup_probe_insert(const uint64_t* __restrict__ xe, long long e,
+                                                  const uint64_t (&key)[W], unsigned long long hsh,
+                                                  HRec* __restrict__ tab, long long HT, bool& won) {
+  const unsigned long long mine = SLOT ? ((hsh & 0xFFFFFFFF00000000ull) | (unsigned long long)e) : key[0];
+  const unsigned long long hmask = (unsigned long long)HT - 1;
+  unsigned long long gs = hsh & hmask;
+  won = false;
+  for (long long probe = 0; probe < HT; ++probe) {
+    const unsigned long long prev = atomicCAS(&tab[gs].key, kEmpty, mine);
+    if (prev == kEmpty) { won = true; return (int)gs; }
+    if constexpr (SLOT) {
+      if ((prev >> 32) == (mine >> 32)) {
+        const long long pe = (long long)(prev & 0xFFFFFFFFull);
+        bool same = true;
+#pragma unroll
+        for (int k = 0; k < W; ++k) same = same && xe[W * pe + k] == key[k];
+        if (same) return (int)gs;
+      }
+    } else {
+      if (prev == mine) return (int)gs;
+    }
+    gs = (gs + 1) & hmask;
+  }
+  return -1;
+}
+
+template <int W>
+__device__ __forceinline__ unsigned long long key_hash(const uint64_t (&key)[W]) {
+  return W == 2 ? mix64(key[0] ^ mix64(key[W - 1])) : mix64(key[0]);
+}
+
+// First-entry order, slot words: one lane per entry, straight into the table.
+// eu[e] <- global slot of entry e's key; rank field <- smallest entry holding it.
 template <int W>
 __global__ __launch_bounds__(256) void dedup_insert_slot_kernel(const uint64_t* __restrict__ xe,
                                                                 const long long* __restrict__ d_count,
-                                                                long long cap,
-                                                                unsigned long long* __restrict__ hkeys,
-                                                                int* __restrict__ owner, long long HT,
-                                                                int* __restrict__ eu, unsigned* err) {
+                                                                long long cap, HRec* __restrict__ tab,
+                                                                long long HT, int* __restrict__ eu,
+                                                                unsigned* err) {
   long long count = *d_count;
   if (count > cap) count = cap;
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -477,31 +533,64 @@ __global__ __launch_bounds__(256) void dedup_insert_slot_kernel(const uint64_t* 
   uint64_t key[W];
 #pragma unroll
   for (int k = 0; k < W; ++k) key[k] = xe[W * e + k];
-  const unsigned long long hsh = W == 2 ? mix64(key[0] ^ mix64(key[W - 1])) : mix64(key[0]);
-  const unsigned long long mine = (hsh & 0xFFFFFFFF00000000ull) | (unsigned long long)e;
-  const unsigned long long hmask = (unsigned long long)HT - 1;
-  unsigned long long gs = hsh & hmask;
-  int found = -1;
-  for (long long probe = 0; probe < HT; ++probe) {
-    const unsigned long long prev = atomicCAS(&hkeys[gs], kEmpty, mine);
-    if (prev == kEmpty) { found = (int)gs; break; }
-    if ((prev >> 32) == (mine >> 32)) {
-      const long long pe = (long long)(prev & 0xFFFFFFFFull);
-      bool same = true;
-#pragma unroll
-      for (int k = 0; k < W; ++k) same = same && xe[W * pe + k] == key[k];
-      if (same) { found = (int)gs; break; }
-    }
-    gs = (gs + 1) & hmask;
-  }
+  bool won;
+  const int found = dedup_probe_insert<W, true>(xe, e, key, key_hash<W>(key), tab, HT, won);
   if (found < 0) atomicOr(err, kErrHashOverflow);
-  else atomicMin(&owner[found], (int)e);
+  else atomicMin(&tab[found].rank, (int)e);
   eu[e] = found;
+}
+
+// Insertion order: one lane per entry.  eu[e] <- global slot of entry e's key;
+// the lane that fills a slot writes the key's rank into it and the key into
+// xu[rank]; *d_nu counts the distinct keys (it starts at zero).
+constexpr int kRankedThreads = 1024;
+template <int W, bool SLOT>
+__global__ __launch_bounds__(kRankedThreads) void dedup_insert_ranked_kernel(const uint64_t* __restrict__ xe,
+                                                                  const long long* __restrict__ d_count,
+                                                                  long long cap, HRec* __restrict__ tab,
+                                                                  long long HT, int* __restrict__ eu,
+                                                                  uint64_t* __restrict__ xu,
+                                                                  long long* __restrict__ d_nu, unsigned* err) {
+  constexpr int NWV = kRankedThreads / 64;
+  __shared__ int wsum[NWV];
+  __shared__ long long base;
+  long long count = *d_count;
+  if (count > cap) count = cap;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t key[W];
+  bool won = false;
+  int found = -1;
+  if (e < count) {
+#pragma unroll
+    for (int k = 0; k < W; ++k) key[k] = xe[W * e + k];
+    found = dedup_probe_insert<W, SLOT>(xe, e, key, key_hash<W>(key), tab, HT, won);
+    if (found < 0) atomicOr(err, kErrHashOverflow);
+    eu[e] = found;
+  }
+  // one block of ranks per workgroup, in entry order inside it
+  const unsigned long long bal = __ballot(won);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) wsum[wv] = __popcll(bal);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int w = 0; w < NWV; ++w) tot += wsum[w];
+    base = tot ? (long long)atomicAdd((unsigned long long*)d_nu, (unsigned long long)tot) : 0;
+  }
+  __syncthreads();
+  if (won) {
+    int before = 0;
+    for (int w = 0; w < wv; ++w) before += wsum[w];
+    const long long r = base + before + __popcll(bal & ((1ull << lane) - 1));
+    tab[found].rank = (int)r;
+#pragma unroll
+    for (int k = 0; k < W; ++k) xu[r * W + k] = key[k];
+  }
 }
 
 // first[e] = 1 where entry e is the first holder of its key (0 beyond the count).
 __global__ void dedup_first_kernel(const long long* __restrict__ d_count, long long cap,
-                                   const int* __restrict__ eu, const int* __restrict__ owner,
+                                   const int* __restrict__ eu, const HRec* __restrict__ tab,
                                    int* __restrict__ first) {
   long long count = *d_count;
   if (count > cap) count = cap;
@@ -510,18 +599,18 @@ __global__ void dedup_first_kernel(const long long* __restrict__ d_count, long l
     int f = 0;
     if (e < count) {
       const int g = eu[e];
-      f = (g >= 0 && owner[g] == (int)e) ? 1 : 0;
+      f = (g >= 0 && tab[g].rank == (int)e) ? 1 : 0;
     }
     first[e] = f;
   }
 }
 
-// The first holders, in entry order: xu[rank] = key, slot_id[slot] = rank.
+// The first holders, in entry order: xu[rank] = key, the slot's rank field = rank.
 template <int W>
 __global__ void dedup_place_kernel(const long long* __restrict__ d_count, long long cap,
                                    const int* __restrict__ first, const long long* __restrict__ rank,
                                    const uint64_t* __restrict__ xe, const int* __restrict__ eu,
-                                   int* __restrict__ slot_id, uint64_t* __restrict__ xu,
+                                   HRec* __restrict__ tab, uint64_t* __restrict__ xu,
                                    long long* __restrict__ d_nu) {
   long long count = *d_count;
   if (count > cap) count = cap;
@@ -533,19 +622,20 @@ __global__ void dedup_place_kernel(const long long* __restrict__ d_count, long l
     const long long id = rank[e];
 #pragma unroll
     for (int k = 0; k < W; ++k) xu[id * W + k] = xe[e * W + k];
-    slot_id[eu[e]] = (int)id;
+    tab[eu[e]].rank = (int)id;
   }
 }
 
+// eu[e] <- the rank of its slot's key.
 __global__ void dedup_remap_kernel(const long long* __restrict__ d_count, long long cap,
-                                   const int* __restrict__ slot_id, int* __restrict__ eu) {
+                                   const HRec* __restrict__ tab, int* __restrict__ eu) {
   long long count = *d_count;
   if (count > cap) count = cap;
   long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (; e < count; e += stride) {
     const int s = eu[e];
-    eu[e] = s >= 0 ? slot_id[s] : -1;
+    eu[e] = s >= 0 ? tab[s].rank : -1;
   }
 }
 
@@ -553,15 +643,13 @@ long long dedup_rank_tmp_elems(long long cap) { return scan_tiles(cap) + 1; }
 
 // Look-back to the previous chunk (one-word keys below 64 qubits, whose
 // table holds the keys themselves): the previous chunk's table maps a key to
-// its rank among that chunk's distinct configurations (its slot words hold
-// the ranks after the remap), so a distinct configuration of this chunk that
-// the previous chunk already evaluated takes that value instead of a forward
-// row.  src[u] = the previous rank or -1; isnew[u] = 1 where src[u] < 0 (0
-// past the count, for the scan).
+// its rank among that chunk's distinct configurations, so a distinct
+// configuration of this chunk that the previous chunk already evaluated takes
+// that value instead of a forward row.  src[u] = the previous rank or -1;
+// isnew[u] = 1 where src[u] < 0 (0 past the count, for the scan).
 __global__ void lookback_probe_kernel(const uint64_t* __restrict__ xu, const long long* __restrict__ d_nu,
-                                      long long cap, const unsigned long long* __restrict__ pkeys,
-                                      const int* __restrict__ prank, long long HT, int* __restrict__ src,
-                                      int* __restrict__ isnew) {
+                                      long long cap, const HRec* __restrict__ ptab, long long HT,
+                                      int* __restrict__ src, int* __restrict__ isnew) {
   const long long nu = *d_nu < cap ? *d_nu : cap;
   const unsigned long long hmask = (unsigned long long)HT - 1;
   const long long stride = (long long)gridDim.x * blockDim.x;
@@ -574,8 +662,8 @@ __global__ void lookback_probe_kernel(const uint64_t* __restrict__ xu, const lon
     unsigned long long gs = mix64(key) & hmask;
     int r = -1;
     for (long long probe = 0; probe < HT; ++probe) {
-      const unsigned long long k = pkeys[gs];
-      if (k == key) { r = prank[gs]; break; }
+      const unsigned long long k = ptab[gs].key;
+      if (k == key) { r = ptab[gs].rank; break; }
       if (k == kEmpty) break;
       gs = (gs + 1) & hmask;
     }
@@ -616,12 +704,12 @@ static long long lookback_blocks(long long cap) {
   return blocks > 16384 ? 16384 : (blocks < 1 ? 1 : blocks);
 }
 
-void launch_lookback(const uint64_t* xu, const long long* d_nu, long long cap, const uint64_t* pkeys,
-                     const int* prank, long long HT, int* src, int* isnew, long long* rank, long long* rank_tmp,
-                     uint64_t* xnew, long long* d_nnew, hipStream_t s) {
+void launch_lookback(const uint64_t* xu, const long long* d_nu, long long cap, const void* ptable, long long HT,
+                     int* src, int* isnew, long long* rank, long long* rank_tmp, uint64_t* xnew, long long* d_nnew,
+                     hipStream_t s) {
   const long long blocks = lookback_blocks(cap);
   hipLaunchKernelGGL(lookback_probe_kernel, dim3((unsigned)blocks), dim3(256), 0, s, xu, d_nu, cap,
-                     (const unsigned long long*)pkeys, prank, HT, src, isnew);
+                     (const HRec*)ptable, HT, src, isnew);
   launch_scan(isnew, cap, rank, rank_tmp, s);
   hipLaunchKernelGGL(lookback_compact_kernel, dim3((unsigned)blocks), dim3(256), 0, s, xu, d_nu, cap, isnew, rank,
                      xnew, d_nnew);
@@ -634,32 +722,52 @@ void launch_lookback_gather(const long long* d_nu, long long cap, const int* src
 }
 
 void launch_dedup(const uint64_t* xe, int words, bool all_ones_key, const long long* d_count, long long cap,
-                  uint64_t* hkeys, int* hslot, long long HT, int* eu, uint64_t* xu, long long* d_nu,
-                  int* first, long long* rank, long long* rank_tmp, unsigned* err, hipStream_t s) {
-  launch_fill_u64(hkeys, kEmpty, HT, s);
-  launch_fill_u32(hslot, (unsigned)kNoEntry, HT, s);   // owners first, then slot ranks
+                  void* table, long long HT, bool first_order, int* eu, uint64_t* xu, long long* d_nu, int* first,
+                  long long* rank, long long* rank_tmp, unsigned* err, hipStream_t s) {
+  HRec* tab = (HRec*)table;
+  {
+    long long blocks = (HT + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(fill_rec_kernel, dim3((unsigned)blocks), dim3(256), 0, s, tab, HT);
+  }
   launch_fill_u64(d_nu, 0ull, 1, s);
-  long long tiles = (cap + kDedupTile - 1) / kDedupTile;
-  if (tiles <= 0) return;
-  if (words == 2)
-    hipLaunchKernelGGL(dedup_insert_slot_kernel<2>, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, xe,
-                       d_count, cap, (unsigned long long*)hkeys, hslot, HT, eu, err);
-  else if (all_ones_key)
-    hipLaunchKernelGGL(dedup_insert_slot_kernel<1>, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, xe,
-                       d_count, cap, (unsigned long long*)hkeys, hslot, HT, eu, err);
-  else
-    hipLaunchKernelGGL(dedup_insert_kernel, dim3((unsigned)tiles), dim3(512), 0, s, xe, d_count, cap,
-                       (unsigned long long*)hkeys, hslot, HT, eu, err);
+  if (cap <= 0) return;
   long long blocks = (cap + 255) / 256;
   if (blocks > 16384) blocks = 16384;
+  const bool slot = words == 2 || all_ones_key;
+  const unsigned lane_blocks = (unsigned)((cap + 255) / 256);
+  if (!first_order) {
+    const dim3 g((unsigned)((cap + kRankedThreads - 1) / kRankedThreads)), b(kRankedThreads);
+    if (words == 2)
+      hipLaunchKernelGGL((dedup_insert_ranked_kernel<2, true>), g, b, 0, s, xe, d_count, cap, tab, HT, eu, xu, d_nu,
+                         err);
+    else if (slot)
+      hipLaunchKernelGGL((dedup_insert_ranked_kernel<1, true>), g, b, 0, s, xe, d_count, cap, tab, HT, eu, xu, d_nu,
+                         err);
+    else
+      hipLaunchKernelGGL((dedup_insert_ranked_kernel<1, false>), g, b, 0, s, xe, d_count, cap, tab, HT, eu, xu, d_nu,
+                         err);
+    hipLaunchKernelGGL(dedup_remap_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d_count, cap,
+                       (const HRec*)tab, eu);
+    return;
+  }
+  if (words == 2)
+    hipLaunchKernelGGL(dedup_insert_slot_kernel<2>, dim3(lane_blocks), dim3(256), 0, s, xe, d_count, cap, tab, HT,
+                       eu, err);
+  else if (slot)
+    hipLaunchKernelGGL(dedup_insert_slot_kernel<1>, dim3(lane_blocks), dim3(256), 0, s, xe, d_count, cap, tab, HT,
+                       eu, err);
+  else
+    hipLaunchKernelGGL(dedup_insert_kernel, dim3((unsigned)((cap + kDedupTile - 1) / kDedupTile)), dim3(512), 0, s,
+                       xe, d_count, cap, tab, HT, eu, err);
   hipLaunchKernelGGL(dedup_first_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d_count, cap, eu,
-                     (const int*)hslot, first);
+                     (const HRec*)tab, first);
   launch_scan(first, cap, rank, rank_tmp, s);
   auto place = words == 2 ? dedup_place_kernel<2> : dedup_place_kernel<1>;
-  hipLaunchKernelGGL(place, dim3((unsigned)blocks), dim3(256), 0, s, d_count, cap, first, rank,
-                     xe, eu, hslot, xu, d_nu);
+  hipLaunchKernelGGL(place, dim3((unsigned)blocks), dim3(256), 0, s, d_count, cap, first, rank, xe, eu, tab, xu,
+                     d_nu);
   hipLaunchKernelGGL(dedup_remap_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d_count, cap,
-                     (const int*)hslot, eu);
+                     (const HRec*)tab, eu);
 }
 
 // ------------------------------------------------------- ratio-and-reduce

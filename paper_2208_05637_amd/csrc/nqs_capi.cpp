@@ -182,8 +182,8 @@ struct nqs_plan {
 constexpr int kProfSlots = 8192;
 
 struct WsLayout {
-  size_t err, prof, geom, packed, wm, lps, eloc, energy, cnt, off, stmp, rpart, diag, xe, he, lpe, hkeys, hslot,
-      eu, xu, nu, dfirst, drank, drtmp, hkeys2, hslot2, lp2, lpn, src, nnew, bscratch, total;
+  size_t err, prof, geom, packed, wm, lps, eloc, energy, cnt, off, stmp, rpart, diag, xe, he, lpe, htab,
+      eu, xu, nu, dfirst, drank, drtmp, htab2, lp2, lpn, src, nnew, bscratch, total;
 };
 
 // Enumeration grid for chunks of S samples: R ranges of gper flip groups.
@@ -217,8 +217,7 @@ static WsLayout layout(const nqs_plan* p, int64_t B) {
   L.he = take((size_t)p->EC * 8 * hs);
   L.lpe = take((size_t)p->EC * 16);
   if (p->dedup_cap) {
-    L.hkeys = take((size_t)p->HT * 8);
-    L.hslot = take((size_t)p->HT * 4);
+    L.htab = take((size_t)p->HT * kHashRecBytes);
     L.eu = take((size_t)p->EC * 4);
     L.xu = take((size_t)p->EC * 8 * p->g.words);
     L.nu = take(8);
@@ -226,8 +225,7 @@ static WsLayout layout(const nqs_plan* p, int64_t B) {
     L.drank = take(((size_t)p->EC + 1) * 8);
     L.drtmp = take((size_t)dedup_rank_tmp_elems(p->EC) * 8);
     if (p->lookback) {   // the second table and log psi set, the new rows' log psi, the look-back map
-      L.hkeys2 = take((size_t)p->HT * 8);
-      L.hslot2 = take((size_t)p->HT * 4);
+      L.htab2 = take((size_t)p->HT * kHashRecBytes);
       L.lp2 = take((size_t)p->EC * 16);
       L.lpn = take((size_t)p->EC * 16);
       L.src = take((size_t)p->EC * 4);
@@ -985,17 +983,15 @@ static ChunkFwd enum_chunk(nqs_plan* p, const uint64_t* x, int64_t c0, int64_t S
   uint64_t* xu = at<uint64_t>(ws, L.xu);
   long long* nu = at<long long>(ws, L.nu);
   const bool odd = p->lookback && (k & 1);
-  uint64_t* hkeys = at<uint64_t>(ws, odd ? L.hkeys2 : L.hkeys);
-  int* hslot = at<int>(ws, odd ? L.hslot2 : L.hslot);
   double* lp = odd ? at<double>(ws, L.lp2) : lpe;
-  launch_dedup(xe, p->g.words, p->g.n == 64, d_total, p->EC, hkeys, hslot, p->HT, at<int>(ws, L.eu), xu, nu,
-               at<int>(ws, L.dfirst), at<long long>(ws, L.drank), at<long long>(ws, L.drtmp), err, s);
+  launch_dedup(xe, p->g.words, p->g.n == 64, d_total, p->EC, at<void>(ws, odd ? L.htab2 : L.htab), p->HT, false,
+               at<int>(ws, L.eu), xu, nu, at<int>(ws, L.dfirst), at<long long>(ws, L.drank),
+               at<long long>(ws, L.drtmp), err, s);
   if (!p->lookback || k == 0) return {xu, nu, bound, lp, lp, false};
   // the entries are dead once deduplicated: xe takes the new configurations
   long long* nnew = at<long long>(ws, L.nnew);
-  launch_lookback(xu, nu, p->EC, at<uint64_t>(ws, odd ? L.hkeys : L.hkeys2), at<int>(ws, odd ? L.hslot : L.hslot2),
-                  p->HT, at<int>(ws, L.src), at<int>(ws, L.dfirst), at<long long>(ws, L.drank),
-                  at<long long>(ws, L.drtmp), xe, nnew, s);
+  launch_lookback(xu, nu, p->EC, at<void>(ws, odd ? L.htab : L.htab2), p->HT, at<int>(ws, L.src),
+                  at<int>(ws, L.dfirst), at<long long>(ws, L.drank), at<long long>(ws, L.drtmp), xe, nnew, s);
   return {xe, nnew, bound, at<double>(ws, L.lpn), lp, true};
 }
 
@@ -1639,9 +1635,9 @@ nqs_status nqs_connected(nqs_plan* p, const uint64_t* x, int64_t B, int64_t capa
   if (p->dedup) {
     if (capacity > p->EC || (int64_t)2 * capacity > p->HT)
       return fail(NQS_ERR_INVALID_ARGUMENT, "capacity exceeds the plan's dedup buffers");
-    launch_dedup(d_ex, p->g.words, p->g.n == 64, (const long long*)d_n_entries, capacity, at<uint64_t>(ws, L.hkeys), at<int>(ws, L.hslot),
-                 p->HT, d_eunique, d_unique, (long long*)d_n_unique, at<int>(ws, L.dfirst), at<long long>(ws, L.drank),
-                 at<long long>(ws, L.drtmp), err, s);
+    launch_dedup(d_ex, p->g.words, p->g.n == 64, (const long long*)d_n_entries, capacity, at<void>(ws, L.htab),
+                 p->HT, true, d_eunique, d_unique, (long long*)d_n_unique, at<int>(ws, L.dfirst),
+                 at<long long>(ws, L.drank), at<long long>(ws, L.drtmp), err, s);
   }
   return launch_check("connected");
 }

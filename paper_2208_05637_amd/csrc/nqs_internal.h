@@ -164,26 +164,31 @@ void launch_write(const HamDev& H, const uint64_t* x, long long S, int R, int gp
                   int hstride, unsigned* err, hipStream_t s);
 
 // Distinct keys of xe[0 .. min(*d_count, cap)) (`words` 64-bit words each)
-// into xu in the order of their first entries, eu[e] = index of entry e's key
-// in xu, *d_nu = their number.  all_ones_key: one-word keys may be the
-// all-ones word (64 qubits), so the table takes slot words instead of keys.
-// first: int[cap], rank: i64[cap + 1], rank_tmp: dedup_rank_tmp_elems(cap).
+// into xu, eu[e] = index of entry e's key in xu, *d_nu = their number, through
+// `table`: HT records of kHashRecBytes (HT a power of two above the count).
+// first_order: xu in the order of the keys' first entries (first: int[cap],
+// rank: i64[cap + 1], rank_tmp: dedup_rank_tmp_elems(cap)); otherwise in the
+// order their inserts filled the table (first, rank, rank_tmp unused).
+// all_ones_key: one-word keys may be the all-ones word (64 qubits), so the
+// table takes slot words instead of keys.  After the call the table maps each
+// key (one-word keys below 64 qubits) to its index in xu.
+constexpr size_t kHashRecBytes = 16;
 long long dedup_rank_tmp_elems(long long cap);
+void launch_dedup(const uint64_t* xe, int words, bool all_ones_key, const long long* d_count, long long cap,
+                  void* table, long long HT, bool first_order, int* eu, uint64_t* xu, long long* d_nu, int* first,
+                  long long* rank, long long* rank_tmp, unsigned* err, hipStream_t s);
 // Look-back of a chunk's distinct configurations xu[0 .. *d_nu) into the
-// previous chunk's one-word table (pkeys, prank: keys and, after that chunk's
-// dedup, their ranks): src[u] = previous rank or -1; the new ones compacted in
-// order into xnew, *d_nnew = their number, rank[u] = the position of a new
-// one.  isnew: int[cap], rank: i64[cap + 1], rank_tmp: dedup_rank_tmp_elems(cap).
-void launch_lookback(const uint64_t* xu, const long long* d_nu, long long cap, const uint64_t* pkeys,
-                     const int* prank, long long HT, int* src, int* isnew, long long* rank, long long* rank_tmp,
-                     uint64_t* xnew, long long* d_nnew, hipStream_t s);
+// previous chunk's one-word table (ptable, after that chunk's launch_dedup):
+// src[u] = the previous index or -1; the new ones compacted in order into
+// xnew, *d_nnew = their number, rank[u] = the position of a new one.
+// isnew: int[cap], rank: i64[cap + 1], rank_tmp: dedup_rank_tmp_elems(cap).
+void launch_lookback(const uint64_t* xu, const long long* d_nu, long long cap, const void* ptable, long long HT,
+                     int* src, int* isnew, long long* rank, long long* rank_tmp, uint64_t* xnew, long long* d_nnew,
+                     hipStream_t s);
 // lp[u] = lp_prev[src[u]] where src[u] >= 0, else lp_new[rank[u]] (pairs of
 // doubles), u < *d_nu.
 void launch_lookback_gather(const long long* d_nu, long long cap, const int* src, const long long* rank,
                             const double* lp_prev, const double* lp_new, double* lp, hipStream_t s);
-void launch_dedup(const uint64_t* xe, int words, bool all_ones_key, const long long* d_count, long long cap,
-                  uint64_t* hkeys, int* hslot, long long HT, int* eu, uint64_t* xu, long long* d_nu,
-                  int* first, long long* rank, long long* rank_tmp, unsigned* err, hipStream_t s);
 
 // partials holds reduce_partials_elems(S) doubles
 long long reduce_partials_elems(long long S);
