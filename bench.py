@@ -58,7 +58,7 @@ def log(*a):
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("paper_2208_05637_amd/csrc/kernels_forward.hip", "paper_2208_05637_amd/csrc/nqs_internal.h"):
+    for f in ("paper_2208_05637_amd/csrc/kernels_forward.hip", "paper_2208_05637_amd/csrc/net.h"):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

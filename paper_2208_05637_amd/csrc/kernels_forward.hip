@@ -27,7 +27,7 @@
 #include <algorithm>
 #include <atomic>
 
-#include "nqs_internal.h"
+#include "net.h"
 
 namespace nqs {
 
