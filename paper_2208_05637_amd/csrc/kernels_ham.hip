@@ -329,6 +329,124 @@ __global__ void write_kernel(HamDev H, const uint64_t* __restrict__ xs, long lon
   if (over) atomicOr(err, kErrEntryOverflow);
 }
 
+// The same entries from the term list, with the work turned around: a
+// workgroup takes kWsSamples samples and one group range, stages the range's
+// groups and terms in LDS in batches (coalesced loads, shared by its samples),
+// and each wave walks its samples one at a time with its lanes on 64
+// consecutive groups.  A ballot over the kept groups and a prefix count give
+// every kept group its place in the sample's segment, so each store
+// instruction writes consecutive entries.  h_g(x) is the same sequential sum
+// over the group's terms as group_h.
+constexpr int kWsSamples = 64;              // samples per workgroup
+constexpr int kWsWaves = 4;                 // waves per workgroup
+constexpr int kWsGroups = 512;              // groups per staged batch
+constexpr int kWsTerms = 2048;              // terms per staged batch (and the largest group it takes)
+
+template <bool IMAG, int W>
+__global__ __launch_bounds__(64 * kWsWaves) void write_staged_kernel(
+    HamDev H, const uint64_t* __restrict__ xs, long long S, int R, int gper, const long long* __restrict__ off,
+    long long cap, uint64_t* __restrict__ xe, double* __restrict__ he, int* __restrict__ esample, int hstride,
+    unsigned* err) {
+  __shared__ uint64_t lgx[kWsGroups * W];
+  __shared__ int loff[kWsGroups + 1];
+  __shared__ uint64_t ltz[kWsTerms * W];
+  __shared__ double lre[kWsTerms];
+  __shared__ double lim[IMAG ? kWsTerms : 1];
+  __shared__ int lge;
+  constexpr int SPW = kWsSamples / kWsWaves;   // samples per wave
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = blockIdx.y;
+  const int g0 = H.gfirst + r * gper;
+  const int g1 = min(H.G, g0 + gper);
+  // lane j < SPW holds sample j of this wave: its bits and its write position
+  const long long i_l = (long long)blockIdx.x * kWsSamples + wv * SPW + (lane < SPW ? lane : 0);
+  const bool live_l = lane < SPW && i_l < S;
+  Bits<W> x_l = load_bits<W>(xs, live_l ? i_l : 0);
+  long long pos_l = live_l ? off[i_l * R + r] : 0;
+  bool over = false;
+  for (int gb = g0; gb < g1;) {
+    // the batch: groups [gb, ge) whose terms fit (a group alone always fits: the host checks)
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const long long kb = H.goff[gb];
+      int lo = gb + 1, hi = min(g1, gb + kWsGroups);   // largest ge in [lo, hi] with goff[ge] - kb <= kWsTerms
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (H.goff[mid] - kb <= kWsTerms) lo = mid;
+        else hi = mid - 1;
+      }
+      lge = lo;
+    }
+    __syncthreads();
+    const int ge = lge, ng = ge - gb;
+    const long long kb = H.goff[gb];
+    const int nt = (int)(H.goff[ge] - kb);
+    for (int t = threadIdx.x; t < ng * W; t += blockDim.x) lgx[t] = H.gx[(long long)gb * W + t];
+    for (int t = threadIdx.x; t <= ng; t += blockDim.x) loff[t] = (int)(H.goff[gb + t] - kb);
+    for (int t = threadIdx.x; t < nt * W; t += blockDim.x) ltz[t] = H.tz[kb * W + t];
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+      lre[t] = H.tre[kb + t];
+      if constexpr (IMAG) lim[t] = H.tim[kb + t];
+    }
+    __syncthreads();
+    for (int j = 0; j < SPW; ++j) {
+      const long long i = (long long)blockIdx.x * kWsSamples + wv * SPW + j;
+      if (i >= S) break;
+      Bits<W> x;
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        const unsigned lo32 = __builtin_amdgcn_readlane((unsigned)x_l.w[k], j);
+        const unsigned hi32 = __builtin_amdgcn_readlane((unsigned)(x_l.w[k] >> 32), j);
+        x.w[k] = ((uint64_t)hi32 << 32) | lo32;
+      }
+      long long pos;
+      {
+        const unsigned lo32 = __builtin_amdgcn_readlane((unsigned)pos_l, j);
+        const unsigned hi32 = __builtin_amdgcn_readlane((unsigned)((unsigned long long)pos_l >> 32), j);
+        pos = (long long)(((unsigned long long)hi32 << 32) | lo32);
+      }
+      for (int q0 = 0; q0 < ng; q0 += 64) {
+        const int q = q0 + lane;
+        const bool act = q < ng;
+        Bits<W> f;
+#pragma unroll
+        for (int k = 0; k < W; ++k) f.w[k] = act ? lgx[q * W + k] : 0;
+        bool ok = act && (!H.filter || sector_ok<W>(x, f));
+        double a = 0.0, b = 0.0;
+        if (ok) {
+          const int k1 = loff[q + 1];
+          for (int kk = loff[q]; kk < k1; ++kk) {
+            int c = 0;
+#pragma unroll
+            for (int k = 0; k < W; ++k) c += __popcll(x.w[k] & ltz[kk * W + k]);
+            const unsigned long long par = (unsigned long long)(c & 1) << 63;
+            a += __longlong_as_double(__double_as_longlong(lre[kk]) ^ par);
+            if constexpr (IMAG) b += __longlong_as_double(__double_as_longlong(lim[kk]) ^ par);
+          }
+          if (!H.filter) ok = (a != 0.0) || (b != 0.0);
+        }
+        const unsigned long long bal = __ballot(ok);
+        if (ok) {
+          const long long p = pos + __popcll(bal & ((1ull << lane) - 1));
+          if (p < cap) {
+#pragma unroll
+            for (int k = 0; k < W; ++k) xe[p * W + k] = x.w[k] ^ f.w[k];
+            he[p * hstride] = a;
+            if (hstride == 2) he[p * 2 + 1] = b;
+            if (esample) esample[p] = (int)i;
+          } else {
+            over = true;
+          }
+        }
+        pos += __popcll(bal);
+      }
+      if (lane == j) pos_l = pos;
+    }
+    gb = ge;
+  }
+  if (over) atomicOr(err, kErrEntryOverflow);
+}
+
 template <int W>
 static void launch_write_w(const HamDev& H, const uint64_t* x, long long S, int R, int gper,
                            const long long* off, long long cap, uint64_t* xe, double* he, int* esample,
@@ -346,6 +464,21 @@ void launch_write(const HamDev& H, const uint64_t* x, long long S, int R, int gp
                   const long long* off, long long cap, uint64_t* xe, double* he, int* esample,
                   int hstride, unsigned* err, hipStream_t s) {
   if (S <= 0) return;
+  if (!H.tables && H.max_gterms <= kWsTerms) {
+    const dim3 grid((unsigned)((S + kWsSamples - 1) / kWsSamples), (unsigned)R), block(64 * kWsWaves);
+    if (H.words == 2) {
+      if (H.tim) hipLaunchKernelGGL((write_staged_kernel<true, 2>), grid, block, 0, s, H, x, S, R, gper, off, cap, xe,
+                                    he, esample, hstride, err);
+      else hipLaunchKernelGGL((write_staged_kernel<false, 2>), grid, block, 0, s, H, x, S, R, gper, off, cap, xe,
+                              he, esample, hstride, err);
+    } else {
+      if (H.tim) hipLaunchKernelGGL((write_staged_kernel<true, 1>), grid, block, 0, s, H, x, S, R, gper, off, cap, xe,
+                                    he, esample, hstride, err);
+      else hipLaunchKernelGGL((write_staged_kernel<false, 1>), grid, block, 0, s, H, x, S, R, gper, off, cap, xe,
+                              he, esample, hstride, err);
+    }
+    return;
+  }
   if (H.words == 2) launch_write_w<2>(H, x, S, R, gper, off, cap, xe, he, esample, hstride, err, s);
   else launch_write_w<1>(H, x, S, R, gper, off, cap, xe, he, esample, hstride, err, s);
 }

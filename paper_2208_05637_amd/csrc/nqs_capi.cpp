@@ -76,6 +76,7 @@ struct nqs_ham {
   std::vector<long long> goff;
   std::vector<uint64_t> tz;   // [K][words]
   std::vector<double> tre, tim;
+  long long max_gterms = 0;   // terms of the largest group past the empty flip
   // census of non-empty flips by (up bits, down bits) for the entry bound
   std::map<std::pair<int, int>, long long> census;
   // structured matrix elements (NQS_H_TABLES)
@@ -257,6 +258,7 @@ static HamDev ham_dev(const nqs_plan* p) {
   H.gfirst = ham_has_diag(h) ? 1 : 0;
   H.filter = (h->flags & NQS_H_CONSERVES_SPIN_SECTORS) ? 1 : 0;
   H.words = h->words;
+  H.max_gterms = h->max_gterms;
   H.tables = h->tables ? 1 : 0;
   if (h->tables) {
     H.soff = (const long long*)(h->d_base + h->o_soff);
@@ -444,6 +446,8 @@ nqs_status nqs_ham_create(const nqs_pauli_terms* t, nqs_ham** out) {
   }
   h->goff.push_back((long long)K);
   const size_t G = h->gx.size() / W;
+  for (size_t gi = ham_has_diag(h) ? 1 : 0; gi < G; ++gi)
+    h->max_gterms = std::max(h->max_gterms, h->goff[gi + 1] - h->goff[gi]);
   for (size_t gi = 0; gi < G; ++gi) {
     int up = 0, dn = 0;
     for (int w = 0; w < W; ++w) {

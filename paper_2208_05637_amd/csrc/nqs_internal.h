@@ -17,6 +17,7 @@ struct HamDev {
   int gfirst;          // 1 if group 0 is the empty flip
   int filter;          // spin-sector filter on
   int words;           // 1 or 2
+  long long max_gterms;  // terms of the largest group past the empty flip
   // structured matrix elements (tables != 0): sub-groups soff[g] .. soff[g+1],
   // off-flip masks su[s][words], table of sub-group s at stab[s], 2^m entries
   // indexed by the bits of x at fpos[4g .. 4g+3] (-1 unused)

@@ -423,3 +423,59 @@ def test_dedup_at_64_qubits_with_the_all_ones_configuration(nqs, ctx):
     e_off = nqs.local_energy(mk(False), params, xs)
     torch.cuda.synchronize()
     assert torch.equal(e_on, e_off) and bool(torch.isfinite(e_on).all())
+
+
+@pytest.mark.parametrize("n,K,B", [(12, 400, 90), (70, 500, 40)])
+def test_connected_bit_exact_complex(nqs, ctx, n, K, B):
+    """Random Pauli strings, many with an odd number of Y (imaginary folded coefficients), no sector filter,
+    one and two 64-bit words, on samples that include neighbours of each other: connected sets, h (real and
+    imaginary parts) and the diagonal bit-exact against the oracle; FP64 local energies with dedup on equal
+    those with it off."""
+    rng = np.random.default_rng(n + 3)
+    W = 1 if n <= 64 else 2
+    full = (1 << n) - 1
+
+    def rnd():
+        return (int(rng.integers(0, 2**62)) | (int(rng.integers(0, 2**62)) << 62)) & full
+
+    # few distinct flips (several terms per group), sparse z masks
+    flips = [0] + [rnd() & rnd() & rnd() for _ in range(K // 8)]
+    xm = [flips[int(rng.integers(0, len(flips)))] for _ in range(K)]
+    zm = [rnd() & rnd() for _ in range(K)]
+    cf = rng.normal(size=K)
+    ref = pauli.canonical_terms(np.array(xm, dtype=object), np.array(zm, dtype=object), cf)
+    assert np.any(ref["ct"].imag != 0) and np.any(ref["ct"].real != 0)
+    to_w = (lambda v: np.array(v, dtype=np.uint64)) if W == 1 else \
+        (lambda v: np.array([[(a >> (64 * w)) & ((1 << 64) - 1) for w in range(2)] for a in v], dtype=np.uint64))
+    H = nqs.Hamiltonian(n, to_w(xm), to_w(zm), cf, conserves_spin=False).upload(ctx)
+    base = [rnd() for _ in range(B // 2)]
+    xs_int = base + [b ^ flips[1 + k % (len(flips) - 1)] for k, b in enumerate(base)]
+    xs_int = list(dict.fromkeys(xs_int))
+    B = len(xs_int)
+    xs = to_w(xs_int)
+    plan = nqs.Plan(ctx, H, 1, 64, -1, -1, "fp64", max_batch=B, chunk_samples=B, dedup=True)
+    out = nqs.connected(plan, xs)
+    diag_ref, ent = vmc.connected(ref, np.array(xs_int, dtype=object) if W == 2 else xs, sector_filter=False)
+    torch.cuda.synchronize()
+    ne = int(out["n_entries"].item())
+    assert ne == sum(len(e[0]) for e in ent)
+    diag = out["diag"].cpu().numpy()
+    assert np.array_equal(diag[:, 0], diag_ref.real) and np.array_equal(diag[:, 1], diag_ref.imag)
+    ex = out["x"][:ne].cpu().numpy().view(np.uint64)
+    ex = ex.reshape(-1).tolist() if W == 1 else [int(r[0]) | (int(r[1]) << 64) for r in ex.tolist()]
+    eh = out["h"][:ne].cpu().numpy()
+    es = out["sample"][:ne].cpu().numpy()
+    pos = 0
+    for i, (gi, xp, hv) in enumerate(ent):
+        k = len(gi)
+        assert np.all(es[pos:pos + k] == i)
+        assert ex[pos:pos + k] == [int(v) for v in xp]
+        assert np.array_equal(eh[pos:pos + k, 0], hv.real) and np.array_equal(eh[pos:pos + k, 1], hv.imag)
+        pos += k
+    params = torch.from_numpy(init_params(n, 1, 64, seed=2, std=0.2)).cuda()
+    e_on = nqs.local_energy(plan, params, xs)
+    off = nqs.Plan(ctx, H, 1, 64, -1, -1, "fp64", max_batch=B, chunk_samples=max(1, B // 3), dedup=False)
+    e_off = nqs.local_energy(off, params, xs)
+    torch.cuda.synchronize()
+    assert nqs.device_status(plan) == 0 and nqs.device_status(off) == 0
+    assert torch.equal(e_on, e_off) and bool(torch.isfinite(e_on).all())
