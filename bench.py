@@ -64,7 +64,7 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(workload, prec, waves):
+def measured_traffic(workload, prec, waves, rows):
     """HBM bytes per configuration of the connected-configuration forward from
     the committed counter summary of this workload, or None when there is none
     or it was taken on another kernel source or workgroup shape."""
@@ -78,7 +78,7 @@ def measured_traffic(workload, prec, waves):
                 k, v = line.split(":", 1)
                 kv[k.strip().strip("-* `")] = v.strip().strip("` ")
     try:
-        if kv.get("kernel_source_sha256") != kernel_source_hash():
+        if kv.get("kernel_source_sha256") != kernel_source_hash() or kv.get("rows_per_block") != str(rows):
             return None
         return float(kv[f"traffic_bytes_per_row_w{waves}"])
     except (KeyError, ValueError):
@@ -145,7 +145,7 @@ def wide_76(nqs, ctx, cfg, prec, count):
     return res
 
 
-def tables_side(nqs, ctx, terms, cfg, prec, waves, dedup, x, chunk, xp, params, ref):
+def tables_side(nqs, ctx, terms, cfg, prec, shape, dedup, x, chunk, xp, params, ref):
     """Matrix elements from the structured tables (NQS_H_TABLES) against the term
     list: the enumeration of the batch's first chunk (diagonal, count, scan,
     write; no dedup), and the local energy of the prefix with the tables in
@@ -172,7 +172,7 @@ def tables_side(nqs, ctx, terms, cfg, prec, waves, dedup, x, chunk, xp, params, 
         if tables:
             P = xp.shape[0]
             pl = nqs.Plan(ctx, Hh, cfg["L"], cfg["h"], cfg["n_up"], cfg["n_dn"], prec, max_batch=P, dedup=dedup)
-            pl.configure(waves_per_block=waves)
+            pl.configure(waves_per_block=shape[0], rows_per_block=shape[1])
             nqs.local_energy(pl, params, xp)    # warm
             torch.cuda.synchronize()
             pl.profile(True)
@@ -398,10 +398,12 @@ def main():
     tune = tuned(plan, x)
     kinfo = plan.kernel_info()
     log(f"K={K} G={H.G} entries/sample={plan.entries_per_sample} chunk={plan.chunk_samples} "
-        f"dedup={plan.dedup} waves={kinfo['waves_per_block']} resident={kinfo['resident']} tuned={kinfo['tuned']} "
+        f"dedup={plan.dedup} waves={kinfo['waves_per_block']} rows={kinfo['rows_per_block']} "
+        f"resident={kinfo['resident']} tuned={kinfo['tuned']} "
         f"workspace={plan.workspace_size(B) / 2**30:.2f} GiB")
     if tune is not None and not tune["from_cache"]:
-        log("autotune: " + ", ".join(f"{c['waves_per_block']}w/dedup{int(c['dedup'])}/S{c['chunk_samples']}/"
+        log("autotune: " + ", ".join(f"{c['waves_per_block']}w/{c['rows_per_block']}r/dedup{int(c['dedup'])}/"
+                                    f"S{c['chunk_samples']}/"
                                     f"{'resident' if c['resident'] else 'tiles'}: {c['ms']:.1f} ms"
                                     for c in tune["candidates"]))
 
@@ -455,7 +457,7 @@ def main():
         f"{achieved:.1f} TFLOP/s algorithmic, {issued:.1f} TFLOP/s MFMA issued (peak {peak})")
     el_main = eloc.cpu().numpy()
     E_main = energy.cpu().numpy()
-    bpr = measured_traffic(args.workload, prec, kinfo["waves_per_block"])
+    bpr = measured_traffic(args.workload, prec, kinfo["waves_per_block"], kinfo["rows_per_block"])
     out = {
         "metric": METRIC,
         "value": value,
@@ -644,7 +646,8 @@ def main():
                                                       phase_mode=1)).to(dev)
                 pl = nqs.Plan(ctx, H, cfg["L"], cfg["h"], cfg["n_up"], cfg["n_dn"], prec, max_batch=P,
                               dedup=plan.dedup, chunk_samples=min(plan.chunk_samples, P), **kw)
-                pl.configure(waves_per_block=kinfo["waves_per_block"], resident=kinfo["resident"])
+                pl.configure(waves_per_block=kinfo["waves_per_block"], rows_per_block=kinfo["rows_per_block"],
+                             resident=kinfo["resident"])
                 nqs.local_energy(pl, vp, xp[:64])
                 torch.cuda.synchronize()
                 pl.profile(True)
@@ -664,8 +667,8 @@ def main():
         guarded("wide_76_qubits", lambda: wide_76(nqs, ctx, cfg, prec, args.wide_samples))
     if args.tables and "paths_on_prefix" in out:
         guarded("structured_tables", lambda: tables_side(
-            nqs, ctx, terms, cfg, prec, kinfo["waves_per_block"], plan.dedup, x, plan.chunk_samples,
-            x[:P].contiguous(), params, side[prec]))
+            nqs, ctx, terms, cfg, prec, (kinfo["waves_per_block"], kinfo["rows_per_block"]), plan.dedup, x,
+            plan.chunk_samples, x[:P].contiguous(), params, side[prec]))
     if args.multi:
         guarded("multi_instance", lambda: multi_instances(nqs, ctx))
     if args.save_tune_db:

@@ -249,15 +249,16 @@ nqs_status nqs_plan_info(const nqs_plan* plan, int64_t* entries_per_sample,
                          int64_t* chunk_samples, int* dedup, int64_t* n_params);
 void       nqs_plan_destroy(nqs_plan* plan);
 
-/* Sets what the autotuner chooses: waves per workgroup of the forward (one
-   of the values nqs_plan_autotune reports; <= 0 keeps the current one),
-   dedup (1 on, 0 off, < 0 keep; on needs a plan created with DEDUP_ON or
+/* Sets what the autotuner chooses: the forward's workgroup shape, as waves
+   per workgroup and configurations per workgroup tile (a pair that
+   nqs_plan_autotune reports; each <= 0 keeps the current value), dedup (1 on,
+   0 off, < 0 keep; on needs a plan created with DEDUP_ON or
    DEDUP_AUTO), the chunk (between half the created chunk and the created
    chunk; <= 0 keeps) and the forward's grid (resident: 1 = as many
    workgroups as the device holds at once, each looping over tiles of rows;
    0 = one workgroup per tile; < 0 keep).  Host only. */
-nqs_status nqs_plan_configure(nqs_plan* plan, int waves_per_block, int dedup, int64_t chunk_samples,
-                              int resident);
+nqs_status nqs_plan_configure(nqs_plan* plan, int waves_per_block, int rows_per_block, int dedup,
+                              int64_t chunk_samples, int resident);
 
 /* Workgroup shape of the plan's connected-configuration forward: waves per
    workgroup, configurations per workgroup, whether the plan was tuned, and
@@ -268,7 +269,8 @@ nqs_status nqs_plan_kernel_info(const nqs_plan* plan, int* waves_per_block, int*
 /* Autotuner for the chunked local-energy path (the paper's mini-batches,
    Sec. 5.2 and Sec. 6): times the local-energy phase on the first
    min(B, 2 * chunk) samples of d_samples for every candidate
-     forward variant (waves per workgroup) x dedup on/off (only with
+     forward workgroup shape (waves per workgroup x tile: the full tile,
+     and half of it where that keeps 32 rows or more) x dedup on/off (only with
      NQS_PLAN_DEDUP_AUTO) x chunk in {plan chunk, plan chunk / 2}
      x forward grid (one workgroup per tile, or resident workgroups
      looping over tiles)
@@ -287,9 +289,10 @@ nqs_status nqs_plan_kernel_info(const nqs_plan* plan, int* waves_per_block, int*
    reported as one line on stderr. */
 #define NQS_TUNE_FORCE 1u
 #define NQS_TUNE_CACHE_ONLY 2u
-#define NQS_TUNE_MAX_CANDIDATES 16
+#define NQS_TUNE_MAX_CANDIDATES 32
 typedef struct {
   int     waves_per_block;
+  int     rows_per_block;  /* configurations per workgroup tile */
   int     dedup;
   int64_t chunk_samples;
   int     resident;        /* 1: resident grid looping over tiles */

@@ -17,7 +17,7 @@ NQS_PLAN_DEDUP_AUTO = 4
 NQS_NOALLOC_SCRATCH_BYTES = 256 << 20
 NQS_TUNE_FORCE = 1
 NQS_TUNE_CACHE_ONLY = 2
-NQS_TUNE_MAX_CANDIDATES = 16
+NQS_TUNE_MAX_CANDIDATES = 32
 NQS_DEV_ZERO_AMPLITUDE = 1
 NQS_DEV_ENTRY_OVERFLOW = 2
 NQS_DEV_HASH_OVERFLOW = 4
@@ -44,8 +44,8 @@ class Profile(C.Structure):
 
 
 class TuneCandidate(C.Structure):
-    _fields_ = [("waves_per_block", C.c_int), ("dedup", C.c_int), ("chunk_samples", C.c_int64),
-                ("resident", C.c_int), ("ms", C.c_double)]
+    _fields_ = [("waves_per_block", C.c_int), ("rows_per_block", C.c_int), ("dedup", C.c_int),
+                ("chunk_samples", C.c_int64), ("resident", C.c_int), ("ms", C.c_double)]
 
 
 class TuneReport(C.Structure):
@@ -84,7 +84,7 @@ SIGNATURES = {
     "nqs_plan_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(C.c_int),
                                 C.POINTER(_I64)]),
     "nqs_plan_destroy": (None, [_P]),
-    "nqs_plan_configure": (C.c_int, [_P, C.c_int, C.c_int, _I64, C.c_int]),
+    "nqs_plan_configure": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, _I64, C.c_int]),
     "nqs_plan_kernel_info": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                        C.POINTER(C.c_int)]),
     "nqs_plan_autotune": (C.c_int, [_P, _P, _P, _I64, _P, _SZ, C.c_uint32, C.POINTER(TuneReport)]),

@@ -211,13 +211,14 @@ class Plan:
         self.entries_per_sample, self.chunk_samples = e.value, cs.value
         self.dedup, self.n_params = bool(dd.value), npar.value
 
-    def configure(self, waves_per_block=0, dedup=None, chunk_samples=0, resident=None):
-        """Set the forward variant (by waves per workgroup), dedup, chunk and the
-        forward's grid (resident workgroups looping over tiles) by hand."""
+    def configure(self, waves_per_block=0, dedup=None, chunk_samples=0, resident=None, rows_per_block=0):
+        """Set the forward's workgroup shape (waves per workgroup, rows per tile),
+        dedup, chunk and the forward's grid (resident workgroups looping over
+        tiles) by hand; 0 / None keep the current value."""
         d = -1 if dedup is None else (1 if dedup else 0)
         r = -1 if resident is None else (1 if resident else 0)
-        L.check(self.lib.nqs_plan_configure(self.handle, int(waves_per_block), d, int(chunk_samples), r),
-                "nqs_plan_configure")
+        L.check(self.lib.nqs_plan_configure(self.handle, int(waves_per_block), int(rows_per_block), d,
+                                            int(chunk_samples), r), "nqs_plan_configure")
         self._refresh()
 
     def kernel_info(self):
@@ -239,8 +240,9 @@ class Plan:
         L.check(self.lib.nqs_plan_autotune(self.handle, _ptr(params), _ptr(x), B, ws, nb, flags, C.byref(rep)),
                 "nqs_plan_autotune")
         self._refresh()
-        cands = [dict(waves_per_block=c.waves_per_block, dedup=bool(c.dedup), chunk_samples=c.chunk_samples,
-                      resident=bool(c.resident), ms=c.ms) for c in rep.cand[:rep.n_candidates]]
+        cands = [dict(waves_per_block=c.waves_per_block, rows_per_block=c.rows_per_block, dedup=bool(c.dedup),
+                      chunk_samples=c.chunk_samples, resident=bool(c.resident), ms=c.ms)
+                 for c in rep.cand[:rep.n_candidates]]
         return dict(candidates=cands, chosen=rep.chosen, from_cache=bool(rep.from_cache),
                     probe_samples=rep.probe_samples)
 

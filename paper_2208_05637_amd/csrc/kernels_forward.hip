@@ -64,10 +64,17 @@ template <> struct Tr<P_F64> {
 };
 
 // Configurations per workgroup: the activations of the tile fill 128 KB of
-// LDS (the narrow FP64 nets use half of it so the head staging fits).
-template <int P, int H>
+// LDS (the narrow FP64 nets use half of it so the head staging fits); MD = 2
+// halves the tile (the autotuner's second tile shape: half the LDS, so two
+// workgroups share a CU, at half the reuse of each weight fragment).
+template <int P, int H, int MD = 1>
 constexpr int rows_per_block() {
-  return (P == P_F64 && H < 256) ? 8192 / H : Tr<P>::MH / H;
+  return ((P == P_F64 && H < 256) ? 8192 / H : Tr<P>::MH / H) / MD;
+}
+// The half tile exists where it keeps at least one MFMA block of rows.
+template <int P, int H>
+constexpr bool has_half_tile() {
+  return P != P_F64 && rows_per_block<P, H>() >= 2 * Tr<P>::TB;
 }
 
 // Waves per workgroup of variant 0: 16 (four per SIMD) for the wide BF16
@@ -78,10 +85,14 @@ template <int P, int H>
 constexpr int default_waves() {
   return ((P == P_BF16 || P == P_BF16X3 || P == P_BF16W) && H >= 512) ? 16 : 8;
 }
+// Variant v: waves from its low bit (0: the default count, 1: the other),
+// tile from its second bit (0: the full tile, 1: the half tile).
 template <int P, int H, int V>
 constexpr int variant_waves() {
-  return V == 0 ? default_waves<P, H>() : (default_waves<P, H>() == 16 ? 8 : 16);
+  return (V & 1) == 0 ? default_waves<P, H>() : (default_waves<P, H>() == 16 ? 8 : 16);
 }
+template <int V>
+constexpr int variant_md() { return (V & 2) ? 2 : 1; }
 
 // Head k slices (one LDS staging plane each) when the head has fewer
 // (block, m-block) tiles than waves: a power of two, at most 8, and no more
@@ -91,9 +102,9 @@ constexpr int pow2_floor(int v) { return v >= 8 ? 8 : v >= 4 ? 4 : v >= 2 ? 2 : 
 // with n = 64 W.
 template <int W>
 constexpr int head_rows_max() { return 64 * W + 4; }
-template <int P, int H, int NW, int W>
+template <int P, int H, int NW, int W, int MD = 1>
 constexpr int head_ksplit_max() {
-  constexpr int M = rows_per_block<P, H>();
+  constexpr int M = rows_per_block<P, H, MD>();
   constexpr int MB = M / Tr<P>::TB;
   constexpr int SP = ((head_rows_max<W>() + Tr<P>::TB - 1) / Tr<P>::TB) * Tr<P>::TB + 1;
   constexpr int fit = pow2_floor(131072 / (M * SP * (int)sizeof(typename Tr<P>::S)));
@@ -445,14 +456,14 @@ __device__ __forceinline__ S softplus(S z) {
   else return m + log1p(exp(-a));
 }
 
-// Shape constants of one (precision, width, waves) instance of the kernel.
-template <int P, int H, int NW_, int W = 1>
+// Shape constants of one (precision, width, waves, tile) instance of the kernel.
+template <int P, int H, int NW_, int W = 1, int MD = 1>
 struct Shape {
   using T = Tr<P>;
   using S = typename T::S;
   static constexpr int NW = NW_, NT = 64 * NW;
   static constexpr int TB = T::TB, PL = T::PL;
-  static constexpr int M = rows_per_block<P, H>();
+  static constexpr int M = rows_per_block<P, H, MD>();
   static constexpr int NB = H / TB, MB = M / TB;
   static constexpr int WN = NB < NW ? NB : NW, WM = NW / WN;
   static constexpr int NBW = NB / WN, MBW = MB / WM;
@@ -460,7 +471,7 @@ struct Shape {
   static constexpr int NHBMAX = (head_rows_max<W>() + TB - 1) / TB;
   static constexpr int HP = (NHBMAX * MB + NW - 1) / NW;
   static constexpr int SP = NHBMAX * TB + 1;
-  static constexpr int KSPLIT_MAX = head_ksplit_max<P, H, NW, W>();
+  static constexpr int KSPLIT_MAX = head_ksplit_max<P, H, NW, W, MD>();
   static constexpr long ACT_BYTES = (long)PL * KSH * MB * 1024;
   static constexpr long STAGE_BYTES = (long)M * SP * sizeof(S) * KSPLIT_MAX;
   static constexpr long REGION = ACT_BYTES > STAGE_BYTES ? ACT_BYTES : STAGE_BYTES;
@@ -489,11 +500,11 @@ __device__ __forceinline__ int popc_above2(uint64_t a0, uint64_t a1, int t) {
 
 // Rows [row0, row0 + M) of one batch through the whole network; rows at or
 // beyond count are computed on a copy of row0 and not written.
-template <int P, int H, int NW, int W>
+template <int P, int H, int NW, int W, int MD>
 __device__ __forceinline__ void fwd_tile(const Geom& g, const uint4* __restrict__ wpk,
                                          const uint64_t* __restrict__ xs, long long row0, long long count,
                                          double2* __restrict__ out, char* act, int cond) {
-  using Sh = Shape<P, H, NW, W>;
+  using Sh = Shape<P, H, NW, W, MD>;
   using T = Tr<P>;
   using Acc = typename T::Acc;
   using S = typename T::S;
@@ -843,9 +854,9 @@ __device__ __forceinline__ long long seg_rows(const Seg& sg) {
 // networks); a tile's segment is found from the tile index and its geometry
 // read from the segment's device copy.
 // W: 64-bit words per bit string (2 only with MULTI = false).
-template <int P, int H, int NW, bool MULTI, int W>
+template <int P, int H, int NW, bool MULTI, int W, int MD>
 __global__ __launch_bounds__(64 * NW) void fused_forward(Geom g0, FwdLaunch la) {
-  using Sh = Shape<P, H, NW, W>;
+  using Sh = Shape<P, H, NW, W, MD>;
   constexpr int M = Sh::M;
   extern __shared__ uint4 smem[];
   char* act = (char*)smem;
@@ -856,7 +867,7 @@ __global__ __launch_bounds__(64 * NW) void fused_forward(Geom g0, FwdLaunch la) 
       const long long rows = seg_rows(sg);
       if (t * M >= rows) break;
       if (again) __syncthreads();
-      fwd_tile<P, H, NW, W>(g0, (const uint4*)sg.packed, sg.x, t * M, rows, (double2*)sg.out, act, la.cond_pos);
+      fwd_tile<P, H, NW, W, MD>(g0, (const uint4*)sg.packed, sg.x, t * M, rows, (double2*)sg.out, act, la.cond_pos);
       again = true;
     } else {
       static_assert(W == 1, "multi-segment launches take one-word bit strings");
@@ -870,7 +881,7 @@ __global__ __launch_bounds__(64 * NW) void fused_forward(Geom g0, FwdLaunch la) 
       // memory before the tile's outputs, so its loads stay scalar
       if (row0 < rows) {
         if (again) __syncthreads();
-        fwd_tile<P, H, NW, W>(*sg.geom, (const uint4*)sg.packed, sg.x, row0, rows, (double2*)sg.out, act,
+        fwd_tile<P, H, NW, W, MD>(*sg.geom, (const uint4*)sg.packed, sg.x, row0, rows, (double2*)sg.out, act,
                               la.cond_pos);
         again = true;
       }
@@ -895,12 +906,13 @@ void launch_store_geom(const Geom& g, Geom* dst, hipStream_t s) {
 template <int P, int H, int V, bool MULTI, int W>
 static void launch_one(const Geom& g, FwdLaunch& la, bool resident, int cu_count, hipStream_t s) {
   constexpr int NW = variant_waves<P, H, V>();
-  using Sh = Shape<P, H, NW, W>;
+  constexpr int MD = variant_md<V>();
+  using Sh = Shape<P, H, NW, W, MD>;
   if constexpr (!Sh::FITS) {
     return;   // forward_supported() rejects this shape before any launch
   } else {
   constexpr size_t LDS = Sh::LDS;
-  auto kern = fused_forward<P, H, NW, MULTI, W>;
+  auto kern = fused_forward<P, H, NW, MULTI, W, MD>;
   // the LDS opt-in, once per device (one bit per device ordinal), safe across threads
   static std::atomic<unsigned long long> attr_done{0};
   int dev = 0;
@@ -980,13 +992,17 @@ bool forward_supported(int prec, int h, int words) {
 }
 
 int forward_variants(int prec, int h) {
-  (void)h;
-  return prec == P_F64 ? 1 : 2;
+  if (prec == P_F64) return 1;
+  return forward_rows_per_block(prec, h) >= 64 ? 4 : 2;   // the half tile keeps 32 rows or more
 }
 
 int forward_variant_waves(int prec, int h, int v) {
   const int d = ((prec == P_BF16 || prec == P_BF16X3 || prec == P_BF16W) && h >= 512) ? 16 : 8;
-  return v == 0 ? d : (d == 16 ? 8 : 16);
+  return (v & 1) == 0 ? d : (d == 16 ? 8 : 16);
+}
+
+int forward_variant_rows(int prec, int h, int v) {
+  return forward_rows_per_block(prec, h) / ((v & 2) ? 2 : 1);
 }
 
 template <bool MULTI, int W>
@@ -995,6 +1011,10 @@ static void dispatch(const Geom& g, int prec, int h, int v, bool res, int cus, F
   if (prec == P && h == H) {                                                        \
     if constexpr (P != P_F64) {                                                     \
       if (v == 1) { launch_one<P, H, 1, MULTI, W>(g, la, res, cus, s); return; }    \
+    }                                                                               \
+    if constexpr (has_half_tile<P, H>()) {                                          \
+      if (v == 2) { launch_one<P, H, 2, MULTI, W>(g, la, res, cus, s); return; }    \
+      if (v == 3) { launch_one<P, H, 3, MULTI, W>(g, la, res, cus, s); return; }    \
     }                                                                               \
     launch_one<P, H, 0, MULTI, W>(g, la, res, cus, s);                              \
     return;                                                                         \

@@ -102,8 +102,10 @@ struct FwdLaunch {
   FwdSeg seg[kMaxSeg];
 };
 
-// Fused forward over tiles of forward_rows_per_block rows.  variant selects
-// the workgroup shape (forward_variants / forward_variant_waves).  resident:
+// Fused forward over tiles of rows.  variant selects the workgroup shape:
+// its waves (forward_variant_waves) and its tile (forward_variant_rows: the
+// full tile of forward_rows_per_block rows, or half of it; forward_variants
+// says how many variants a (precision, width) has).  resident:
 // false = one workgroup per tile (the grid covers the row bound); true = as
 // many workgroups as fit on the device's cu_count CUs at once, each looping
 // over tiles with a stride of the grid size.  The rows and their arithmetic
@@ -125,6 +127,7 @@ void launch_forward_cond(const Geom& g, int variant, bool resident, int cu_count
 void launch_store_geom(const Geom& g, Geom* dst, hipStream_t s);
 int forward_variants(int prec, int h);
 int forward_variant_waves(int prec, int h, int variant);
+int forward_variant_rows(int prec, int h, int variant);   // configurations per workgroup tile
 
 int forward_rows_per_block(int prec, int h);
 // (prec, width) has a fused forward for bit strings of `words` 64-bit words

@@ -1338,7 +1338,8 @@ nqs_status nqs_plan_autotune(nqs_plan* p, const float* params, const uint64_t* x
       R.from_cache = 1;
       R.n_candidates = 1;
       R.chosen = 0;
-      R.cand[0] = nqs_tune_candidate{forward_variant_waves(p->g.prec, p->g.h, p->variant), p->dedup ? 1 : 0, p->S,
+      R.cand[0] = nqs_tune_candidate{forward_variant_waves(p->g.prec, p->g.h, p->variant),
+                                     forward_variant_rows(p->g.prec, p->g.h, p->variant), p->dedup ? 1 : 0, p->S,
                                      p->resident ? 1 : 0, it->second.ms};
       return NQS_OK;
     }
@@ -1383,12 +1384,13 @@ nqs_status nqs_plan_autotune(nqs_plan* p, const float* params, const uint64_t* x
     HIP_TRY(hipEventSynchronize(e1));
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    R.cand[c] = nqs_tune_candidate{forward_variant_waves(p->g.prec, p->g.h, cands[c].v), cands[c].d ? 1 : 0,
+    R.cand[c] = nqs_tune_candidate{forward_variant_waves(p->g.prec, p->g.h, cands[c].v),
+                                   forward_variant_rows(p->g.prec, p->g.h, cands[c].v), cands[c].d ? 1 : 0,
                                    cands[c].S, cands[c].r ? 1 : 0, ms / 2.0};
     if (log) {
-      fprintf(stderr, "nqs tuner: candidate %zu/%zu: %d waves, dedup %d, chunk %lld, %s grid: %.1f ms\n", c + 1,
-              cands.size(), R.cand[c].waves_per_block, R.cand[c].dedup, (long long)R.cand[c].chunk_samples,
-              cands[c].r ? "resident" : "one-tile", ms / 2.0);
+      fprintf(stderr, "nqs tuner: candidate %zu/%zu: %d waves, %d-row tiles, dedup %d, chunk %lld, %s grid: %.1f ms\n",
+              c + 1, cands.size(), R.cand[c].waves_per_block, R.cand[c].rows_per_block, R.cand[c].dedup,
+              (long long)R.cand[c].chunk_samples, cands[c].r ? "resident" : "one-tile", ms / 2.0);
       fflush(stderr);
     }
     if (best < 0 || ms / 2.0 < best_ms) { best = (int)c; best_ms = ms / 2.0; }
@@ -1414,23 +1416,25 @@ nqs_status nqs_plan_autotune(nqs_plan* p, const float* params, const uint64_t* x
 
 // Tuner database: the cached choices as text, one entry per line, so a later
 // process applies them without timing.  Fields: the 11 key values, then the
-// forward's waves per workgroup, dedup, chunk and the measured ms.
+// forward's waves per workgroup and rows per tile, dedup, chunk, grid and the
+// measured ms.
 nqs_status nqs_tune_db_save(const char* path) {
   if (!path) return fail(NQS_ERR_INVALID_ARGUMENT, "path is NULL");
   std::string tmp = std::string(path) + ".tmp";
   FILE* f = fopen(tmp.c_str(), "w");
   if (!f) return fail(NQS_ERR_INVALID_ARGUMENT, "cannot write %s", tmp.c_str());
-  fprintf(f, "# nqs tuner database v2: n L h precision K G entries_per_sample chunk dedup_auto device phase_mode"
-             " | waves dedup chunk resident ms\n");
+  fprintf(f, "# nqs tuner database v3: n L h precision K G entries_per_sample chunk dedup_auto device phase_mode"
+             " | waves rows dedup chunk resident ms\n");
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (const auto& kv : g_tune_cache) {
       const TuneKey& k = kv.first;
       const TuneVal& v = kv.second;
-      fprintf(f, "%d %d %d %d %lld %lld %lld %lld %d %d %d | %d %d %lld %d %.6f\n", std::get<0>(k), std::get<1>(k),
-              std::get<2>(k), std::get<3>(k), (long long)std::get<4>(k), (long long)std::get<5>(k),
+      fprintf(f, "%d %d %d %d %lld %lld %lld %lld %d %d %d | %d %d %d %lld %d %.6f\n", std::get<0>(k),
+              std::get<1>(k), std::get<2>(k), std::get<3>(k), (long long)std::get<4>(k), (long long)std::get<5>(k),
               (long long)std::get<6>(k), (long long)std::get<7>(k), std::get<8>(k), std::get<9>(k), std::get<10>(k),
-              forward_variant_waves(std::get<3>(k), std::get<2>(k), v.variant), v.dedup ? 1 : 0, (long long)v.S,
+              forward_variant_waves(std::get<3>(k), std::get<2>(k), v.variant),
+              forward_variant_rows(std::get<3>(k), std::get<2>(k), v.variant), v.dedup ? 1 : 0, (long long)v.S,
               v.resident ? 1 : 0, v.ms);
     }
   }
@@ -1450,8 +1454,8 @@ nqs_status nqs_tune_db_load(const char* path, int* n_loaded) {
   while (fgets(line, sizeof(line), f)) {
     ++lineno;
     if (line[0] == '#' || line[0] == '\n') continue;
-    // 11 key fields, "|", then waves, dedup, chunk, resident (integers) and ms
-    long long iv[15] = {};
+    // 11 key fields, "|", then waves, rows, dedup, chunk, resident (integers) and ms
+    long long iv[16] = {};
     double ms = 0.0;
     int ntok = 0;
     bool whole = true;
@@ -1459,22 +1463,22 @@ nqs_status nqs_tune_db_load(const char* path, int* n_loaded) {
     for (char* tok = strtok_r(line, " \t\r\n", &save); tok && whole; tok = strtok_r(nullptr, " \t\r\n", &save)) {
       char* end = nullptr;
       if (ntok == 11) whole = strcmp(tok, "|") == 0;
-      else if (ntok == 16) ms = strtod(tok, &end);
-      else if (ntok < 16) iv[ntok < 11 ? ntok : ntok - 1] = strtoll(tok, &end, 10);
+      else if (ntok == 17) ms = strtod(tok, &end);
+      else if (ntok < 17) iv[ntok < 11 ? ntok : ntok - 1] = strtoll(tok, &end, 10);
       else whole = false;
       if (end) whole = whole && end != tok && *end == 0;
       ++ntok;
     }
-    whole = whole && ntok == 17;
+    whole = whole && ntok == 18;
     int a[11];
     long long b[4] = {iv[4], iv[5], iv[6], iv[7]};
     for (int k = 0; k < 11; ++k) a[k] = (int)iv[k];
-    const int waves = (int)iv[11], dedup = (int)iv[12], res = (int)iv[14];
-    const long long S = iv[13];
+    const int waves = (int)iv[11], rows = (int)iv[12], dedup = (int)iv[13], res = (int)iv[15];
+    const long long S = iv[14];
     int v = -1;
     if (whole && a[3] >= 0 && a[3] <= NQS_BF16W && a[2] > 0 && (res == 0 || res == 1))
       for (int k = 0; k < forward_variants(a[3], a[2]); ++k)
-        if (forward_variant_waves(a[3], a[2], k) == waves) v = k;
+        if (forward_variant_waves(a[3], a[2], k) == waves && forward_variant_rows(a[3], a[2], k) == rows) v = k;
     if (v < 0 || S < 1 || S > b[3]) {
       st = fail(NQS_ERR_INVALID_ARGUMENT, "%s:%d: not a tuner database entry", path, lineno);
       break;
@@ -1490,13 +1494,18 @@ nqs_status nqs_tune_db_load(const char* path, int* n_loaded) {
   return st;
 }
 
-nqs_status nqs_plan_configure(nqs_plan* p, int waves_per_block, int dedup, int64_t chunk_samples, int resident) {
+nqs_status nqs_plan_configure(nqs_plan* p, int waves_per_block, int rows_per_block, int dedup, int64_t chunk_samples,
+                              int resident) {
   if (!p) return fail(NQS_ERR_INVALID_ARGUMENT, "plan is NULL");
+  const int prec = p->g.prec, h = p->g.h;
+  const int want_w = waves_per_block > 0 ? waves_per_block : forward_variant_waves(prec, h, p->variant);
+  const int want_r = rows_per_block > 0 ? rows_per_block : forward_variant_rows(prec, h, p->variant);
   int v = -1;
-  if (waves_per_block <= 0) v = p->variant;
-  for (int k = 0; v < 0 && k < forward_variants(p->g.prec, p->g.h); ++k)
-    if (forward_variant_waves(p->g.prec, p->g.h, k) == waves_per_block) v = k;
-  if (v < 0) return fail(NQS_ERR_UNSUPPORTED, "no forward variant with %d waves per workgroup", waves_per_block);
+  for (int k = 0; v < 0 && k < forward_variants(prec, h); ++k)
+    if (forward_variant_waves(prec, h, k) == want_w && forward_variant_rows(prec, h, k) == want_r) v = k;
+  if (v < 0)
+    return fail(NQS_ERR_UNSUPPORTED, "no forward variant with %d waves per workgroup and %d-row tiles", want_w,
+                want_r);
   if (dedup > 0 && !p->dedup_cap)
     return fail(NQS_ERR_INVALID_ARGUMENT, "plan was not created for dedup (DEDUP_ON or DEDUP_AUTO)");
   if (chunk_samples > p->S0)
@@ -1517,7 +1526,7 @@ nqs_status nqs_plan_kernel_info(const nqs_plan* p, int* waves_per_block, int* ro
   if (!p) return fail(NQS_ERR_INVALID_ARGUMENT, "plan is NULL");
   if (resident) *resident = p->resident ? 1 : 0;
   if (waves_per_block) *waves_per_block = forward_variant_waves(p->g.prec, p->g.h, p->variant);
-  if (rows_per_block) *rows_per_block = forward_rows_per_block(p->g.prec, p->g.h);
+  if (rows_per_block) *rows_per_block = forward_variant_rows(p->g.prec, p->g.h, p->variant);
   if (tuned) *tuned = p->tuned ? 1 : 0;
   return NQS_OK;
 }

@@ -280,9 +280,10 @@ def test_tune_db_round_trip(lib, tmp_path):
     import paper_2208_05637_amd as nqs
     # one entry per precision kind with a workgroup shape every width offers
     src = tmp_path / "in.txt"
+    # (the FP32 entry takes the half tile: 64 rows of the 128 an FP32 tile holds at h = 256)
     lines = ["# comment line",
-             "60 4 1024 4 1189663 244771 73125 3670 1 0 0 | 8 1 3670 1 987.500000",
-             "24 2 256 1 29737 5479 1818 147669 0 0 0 | 8 0 73834 0 12.250000"]
+             "60 4 1024 4 1189663 244771 73125 3670 1 0 0 | 8 32 1 3670 1 987.500000",
+             "24 2 256 1 29737 5479 1818 147669 0 0 0 | 16 64 0 73834 0 12.250000"]
     src.write_text("\n".join(lines) + "\n")
     assert nqs.tune_db_load(src) == 2
     out = tmp_path / "out.txt"
@@ -294,17 +295,16 @@ def test_tune_db_round_trip(lib, tmp_path):
     bad.write_text("60 4 1024 4 | 8\n")
     with pytest.raises(nqs.NQSError):
         nqs.tune_db_load(bad)
-    # a workgroup shape the kernel does not have is rejected
-    bad.write_text("60 4 1024 4 1189663 244771 73125 3670 1 0 0 | 5 1 3670 0 1.0\n")
-    with pytest.raises(nqs.NQSError):
-        nqs.tune_db_load(bad)
-    # a grid field other than 0 or 1, and the earlier format without the grid field
-    bad.write_text("60 4 1024 4 1189663 244771 73125 3670 1 0 0 | 8 1 3670 2 1.0\n")
-    with pytest.raises(nqs.NQSError):
-        nqs.tune_db_load(bad)
-    bad.write_text("60 4 1024 4 1189663 244771 73125 3670 1 0 0 | 8 1 3670 1.0\n")
-    with pytest.raises(nqs.NQSError):
-        nqs.tune_db_load(bad)
+    # workgroup shapes the kernel does not have are rejected: 5 waves; a half tile of 16 rows at h = 1024
+    for shape in ("5 32", "8 16", "16 64"):
+        bad.write_text(f"60 4 1024 4 1189663 244771 73125 3670 1 0 0 | {shape} 1 3670 0 1.0\n")
+        with pytest.raises(nqs.NQSError):
+            nqs.tune_db_load(bad)
+    # a grid field other than 0 or 1, and the earlier formats (no tile field; no grid field)
+    for val in ("8 32 1 3670 2 1.0", "8 1 3670 1 1.0", "8 1 3670 1.0"):
+        bad.write_text(f"60 4 1024 4 1189663 244771 73125 3670 1 0 0 | {val}\n")
+        with pytest.raises(nqs.NQSError):
+            nqs.tune_db_load(bad)
     with pytest.raises(nqs.NQSError):
         nqs.tune_db_load(tmp_path / "missing.txt")
 

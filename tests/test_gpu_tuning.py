@@ -55,15 +55,17 @@ def test_forward_variants_log_psi(nqs, ctx, prec, h, L, tol):
     la_ref, ph_ref, _ = made.forward(made.Net(n=n, n_layers=L, width=h, n_up=3, n_dn=3), params, xs)
     fin = np.isfinite(la_ref)
     p = torch.from_numpy(params).cuda()
-    default = plan.kernel_info()["waves_per_block"]
-    for waves in (default, 8 if default == 16 else 16):
-        plan.configure(waves_per_block=waves)
-        assert plan.kernel_info()["waves_per_block"] == waves
+    info = plan.kernel_info()
+    default, full = info["waves_per_block"], info["rows_per_block"]
+    tiles = [full] + ([full // 2] if full >= 64 else [])          # the half tile keeps 32 rows or more
+    for waves, rows in [(w_, r_) for w_ in (default, 8 if default == 16 else 16) for r_ in tiles]:
+        plan.configure(waves_per_block=waves, rows_per_block=rows)
+        assert plan.kernel_info()["waves_per_block"] == waves and plan.kernel_info()["rows_per_block"] == rows
         out = nqs.log_psi(plan, p, xs).cpu().numpy()
         assert np.array_equal(np.isfinite(out[:, 0]), fin)
         e1 = np.max(np.abs(out[fin, 0] - la_ref[fin]))
         e2 = np.max(np.abs(out[:, 1] - ph_ref))
-        print(f"{prec} h={h} waves={waves}: {e1:.3e} {e2:.3e}")
+        print(f"{prec} h={h} waves={waves} rows={rows}: {e1:.3e} {e2:.3e}")
         assert e1 <= tol and e2 <= tol
 
 
@@ -73,6 +75,8 @@ def test_configure_rejects_bad_values(nqs, ctx):
     plan = nqs.Plan(ctx, H, 1, 64, 3, 3, "fp64", max_batch=64, dedup=False, chunk_samples=40)
     with pytest.raises(nqs.NQSError):
         plan.configure(waves_per_block=16)          # the FP64 forward has one variant
+    with pytest.raises(nqs.NQSError):
+        plan.configure(rows_per_block=8)            # no tile of 8 rows
     with pytest.raises(nqs.NQSError):
         plan.configure(dedup=True)                  # no dedup tables in this plan's workspace
     with pytest.raises(nqs.NQSError):
@@ -119,25 +123,30 @@ def test_autotune_times_candidates_and_caches(nqs, ctx):
     p = torch.from_numpy(params).cuda()
     rep = plan.autotune(p, xs, force=True)
     cands = rep["candidates"]
-    # 2 variants x dedup on/off x chunk {128, 64} x grid (one workgroup per tile, resident)
-    assert len(cands) == 16 and not rep["from_cache"]
-    assert sorted({(c["waves_per_block"], c["dedup"], c["chunk_samples"], c["resident"]) for c in cands}) == \
-        sorted((w_, d_, c_, r_) for w_ in (8, 16) for d_ in (False, True) for c_ in (128, 64) for r_ in (False, True))
+    # workgroup shapes (8 or 16 waves x tiles of 64 or 32 rows) x dedup on/off x chunk {128, 64} x grid (one
+    # workgroup per tile, resident)
+    assert len(cands) == 32 and not rep["from_cache"]
+    assert sorted({(c["waves_per_block"], c["rows_per_block"], c["dedup"], c["chunk_samples"], c["resident"])
+                   for c in cands}) == \
+        sorted((w_, m_, d_, c_, r_) for w_ in (8, 16) for m_ in (64, 32) for d_ in (False, True) for c_ in (128, 64)
+               for r_ in (False, True))
     assert rep["probe_samples"] == min(len(xs), 256)
     assert all(c["ms"] > 0 for c in cands)
     best = cands[rep["chosen"]]
     assert best["ms"] == min(c["ms"] for c in cands)
     info = plan.kernel_info()
     assert info["tuned"] and info["waves_per_block"] == best["waves_per_block"]
+    assert info["rows_per_block"] == best["rows_per_block"]
     assert plan.dedup == best["dedup"] and plan.chunk_samples == best["chunk_samples"]
     assert info["resident"] == best["resident"]
-    print("autotune:", [(c["waves_per_block"], c["dedup"], c["chunk_samples"], c["resident"], round(c["ms"], 3))
-                        for c in cands], "chosen", rep["chosen"])
+    print("autotune:", [(c["waves_per_block"], c["rows_per_block"], c["dedup"], c["chunk_samples"], c["resident"],
+                         round(c["ms"], 3)) for c in cands], "chosen", rep["chosen"])
     # a second plan of the same shape takes the cached choice without timing
     plan2 = nqs.Plan(ctx, H, 2, 512, N // 2, N // 2, "bf16x3", max_batch=len(xs), dedup="auto",
                      chunk_samples=128)
     rep2 = plan2.autotune(p, xs)
     assert rep2["from_cache"] and plan2.kernel_info()["waves_per_block"] == best["waves_per_block"]
+    assert plan2.kernel_info()["rows_per_block"] == best["rows_per_block"]
     assert plan2.kernel_info()["resident"] == best["resident"]
     # the tuned plan is still correct
     el = nqs.local_energy(plan2, p, xs).cpu().numpy()
