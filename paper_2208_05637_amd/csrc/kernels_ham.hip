@@ -628,8 +628,14 @@ __device__ __forceinline__ int dedup_probe_insert(const uint64_t* __restrict__ x
   unsigned long long gs = hsh & hmask;
   won = false;
   for (long long probe = 0; probe < HT; ++probe) {
-    const unsigned long long prev = atomicCAS(&tab[gs].key, kEmpty, mine);
-    if (prev == kEmpty) { won = true; return (int)gs; }
+    // a plain read first: a slot, once filled in this chunk, keeps its key word, so
+    // a key read here is final and needs no atomic; an empty read (possibly stale)
+    // goes to the CAS, which decides
+    unsigned long long prev = __builtin_nontemporal_load(&tab[gs].key);
+    if (prev == kEmpty) {
+      prev = atomicCAS(&tab[gs].key, kEmpty, mine);
+      if (prev == kEmpty) { won = true; return (int)gs; }
+    }
     if constexpr (SLOT) {
       if ((prev >> 32) == (mine >> 32)) {
         const long long pe = (long long)(prev & 0xFFFFFFFFull);
