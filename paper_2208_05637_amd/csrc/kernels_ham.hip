@@ -679,10 +679,14 @@ __global__ __launch_bounds__(256) void dedup_insert_slot_kernel(const uint64_t* 
   eu[e] = found;
 }
 
-// Insertion order: one lane per entry.  eu[e] <- global slot of entry e's key;
-// the lane that fills a slot writes the key's rank into it and the key into
-// xu[rank]; *d_nu counts the distinct keys (it starts at zero).
+// Insertion order: one lane per entry.  The lane that fills a slot writes the
+// key's rank into it and the key into xu[rank]; *d_nu counts the distinct
+// keys (it starts at zero).  eu[e] <- the rank of entry e's key where it is
+// known when the lane finishes (its own insert, or a rank already written by
+// the key's inserter), else -1 - slot for dedup_remap_pending_kernel, and
+// kRankOverflow where the table was full.
 constexpr int kRankedThreads = 1024;
+constexpr int kRankOverflow = 1 << 30;   // above every rank (entries < 2^30)
 template <int W, bool SLOT>
 __global__ __launch_bounds__(kRankedThreads) void dedup_insert_ranked_kernel(const uint64_t* __restrict__ xe,
                                                                   const long long* __restrict__ d_count,
@@ -703,8 +707,10 @@ __global__ __launch_bounds__(kRankedThreads) void dedup_insert_ranked_kernel(con
 #pragma unroll
     for (int k = 0; k < W; ++k) key[k] = xe[W * e + k];
     found = dedup_probe_insert<W, SLOT>(xe, e, key, key_hash<W>(key), tab, HT, won);
-    if (found < 0) atomicOr(err, kErrHashOverflow);
-    eu[e] = found;
+    if (found < 0) {
+      atomicOr(err, kErrHashOverflow);
+      eu[e] = kRankOverflow;
+    }
   }
   // one block of ranks per workgroup, in entry order inside it
   const unsigned long long bal = __ballot(won);
@@ -724,6 +730,27 @@ __global__ __launch_bounds__(kRankedThreads) void dedup_insert_ranked_kernel(con
     tab[found].rank = (int)r;
 #pragma unroll
     for (int k = 0; k < W; ++k) xu[r * W + k] = key[k];
+    eu[e] = (int)r;
+  } else if (found >= 0) {
+    // a rank field is written once, from kNoEntry: a value read here is final
+    const int rk = __builtin_nontemporal_load(&tab[found].rank);
+    eu[e] = rk != kNoEntry ? rk : -1 - found;
+  }
+}
+
+// eu[e] <- the rank of its key for the entries the insert left pending
+// (eu[e] = -1 - slot); -1 for kRankOverflow.
+__global__ void dedup_remap_pending_kernel(const long long* __restrict__ d_count, long long cap,
+                                           const HRec* __restrict__ tab, int* __restrict__ eu) {
+  long long count = *d_count;
+  if (count > cap) count = cap;
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (; e < count; e += stride) {
+    const int v = eu[e];
+    if (v >= 0 && v < kRankOverflow) continue;
+    const int r = v < 0 ? tab[-1 - (long long)v].rank : kNoEntry;
+    eu[e] = r != kNoEntry ? r : -1;
   }
 }
 
@@ -886,7 +913,7 @@ void launch_dedup(const uint64_t* xe, int words, bool all_ones_key, const long l
     else
       hipLaunchKernelGGL((dedup_insert_ranked_kernel<1, false>), g, b, 0, s, xe, d_count, cap, tab, HT, eu, xu, d_nu,
                          err);
-    hipLaunchKernelGGL(dedup_remap_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d_count, cap,
+    hipLaunchKernelGGL(dedup_remap_pending_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d_count, cap,
                        (const HRec*)tab, eu);
     return;
   }
