@@ -339,7 +339,7 @@ __global__ void write_kernel(HamDev H, const uint64_t* __restrict__ xs, long lon
 // over the group's terms as group_h.
 constexpr int kWsSamples = 64;              // samples per workgroup
 constexpr int kWsWaves = 4;                 // waves per workgroup
-constexpr int kWsGroups = 512;              // groups per staged batch
+constexpr int kWsGroups = 448;              // groups per staged batch (four workgroups per CU in LDS)
 constexpr int kWsTerms = 2048;              // terms per staged batch (and the largest group it takes)
 
 template <bool IMAG, int W>
@@ -352,6 +352,7 @@ __global__ __launch_bounds__(64 * kWsWaves) void write_staged_kernel(
   __shared__ uint64_t ltz[kWsTerms * W];
   __shared__ double lre[kWsTerms];
   __shared__ double lim[IMAG ? kWsTerms : 1];
+  __shared__ int lkept[kWsWaves][128];   // per wave: kept groups awaiting evaluation
   __shared__ int lge;
   constexpr int SPW = kWsSamples / kWsWaves;   // samples per wave
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -405,40 +406,85 @@ __global__ __launch_bounds__(64 * kWsWaves) void write_staged_kernel(
         const unsigned hi32 = __builtin_amdgcn_readlane((unsigned)((unsigned long long)pos_l >> 32), j);
         pos = (long long)(((unsigned long long)hi32 << 32) | lo32);
       }
-      for (int q0 = 0; q0 < ng; q0 += 64) {
-        const int q = q0 + lane;
-        const bool act = q < ng;
-        Bits<W> f;
+      // h_g(x) of the group at batch index q, summed over its terms in order
+      auto group_sum = [&](int q, double& a, double& b) {
+        a = 0.0;
+        b = 0.0;
+        const int k1 = loff[q + 1];
+        for (int kk = loff[q]; kk < k1; ++kk) {
+          int c = 0;
 #pragma unroll
-        for (int k = 0; k < W; ++k) f.w[k] = act ? lgx[q * W + k] : 0;
-        bool ok = act && (!H.filter || sector_ok<W>(x, f));
-        double a = 0.0, b = 0.0;
-        if (ok) {
-          const int k1 = loff[q + 1];
-          for (int kk = loff[q]; kk < k1; ++kk) {
-            int c = 0;
-#pragma unroll
-            for (int k = 0; k < W; ++k) c += __popcll(x.w[k] & ltz[kk * W + k]);
-            const unsigned long long par = (unsigned long long)(c & 1) << 63;
-            a += __longlong_as_double(__double_as_longlong(lre[kk]) ^ par);
-            if constexpr (IMAG) b += __longlong_as_double(__double_as_longlong(lim[kk]) ^ par);
-          }
-          if (!H.filter) ok = (a != 0.0) || (b != 0.0);
+          for (int k = 0; k < W; ++k) c += __popcll(x.w[k] & ltz[kk * W + k]);
+          const unsigned long long par = (unsigned long long)(c & 1) << 63;
+          a += __longlong_as_double(__double_as_longlong(lre[kk]) ^ par);
+          if constexpr (IMAG) b += __longlong_as_double(__double_as_longlong(lim[kk]) ^ par);
         }
-        const unsigned long long bal = __ballot(ok);
-        if (ok) {
-          const long long p = pos + __popcll(bal & ((1ull << lane) - 1));
-          if (p < cap) {
+      };
+      auto store = [&](long long p, const Bits<W>& f, double a, double b) {
+        if (p < cap) {
 #pragma unroll
-            for (int k = 0; k < W; ++k) xe[p * W + k] = x.w[k] ^ f.w[k];
-            he[p * hstride] = a;
-            if (hstride == 2) he[p * 2 + 1] = b;
-            if (esample) esample[p] = (int)i;
-          } else {
-            over = true;
+          for (int k = 0; k < W; ++k) xe[p * W + k] = x.w[k] ^ f.w[k];
+          he[p * hstride] = a;
+          if (hstride == 2) he[p * 2 + 1] = b;
+          if (esample) esample[p] = (int)i;
+        } else {
+          over = true;
+        }
+      };
+      if (H.filter) {
+        // the sector test decides which groups the sample keeps; they are listed
+        // in order and evaluated 64 at a time, one per lane, so no lane idles on
+        // a group the sample does not keep
+        int* kept = lkept[wv];
+        int nk = 0;
+        auto evaluate = [&](int cnt) {
+          if (lane < cnt) {
+            const int q = kept[lane];
+            Bits<W> f;
+#pragma unroll
+            for (int k = 0; k < W; ++k) f.w[k] = lgx[q * W + k];
+            double a, b;
+            group_sum(q, a, b);
+            store(pos + lane, f, a, b);
+          }
+          pos += cnt;
+        };
+        for (int q0 = 0; q0 < ng; q0 += 64) {
+          const int q = q0 + lane;
+          const bool act = q < ng;
+          Bits<W> f;
+#pragma unroll
+          for (int k = 0; k < W; ++k) f.w[k] = act ? lgx[q * W + k] : 0;
+          const bool ok = act && sector_ok<W>(x, f);
+          const unsigned long long bal = __ballot(ok);
+          if (ok) kept[nk + __popcll(bal & ((1ull << lane) - 1))] = q;
+          nk += __popcll(bal);
+          __builtin_amdgcn_wave_barrier();
+          if (nk >= 64) {
+            evaluate(64);
+            __builtin_amdgcn_wave_barrier();
+            if (lane < nk - 64) kept[lane] = kept[64 + lane];
+            __builtin_amdgcn_wave_barrier();
+            nk -= 64;
           }
         }
-        pos += __popcll(bal);
+        if (nk > 0) evaluate(nk);
+        __builtin_amdgcn_wave_barrier();
+      } else {
+        // without the sector test a group is kept where h != 0: every group is evaluated
+        for (int q0 = 0; q0 < ng; q0 += 64) {
+          const int q = q0 + lane;
+          const bool act = q < ng;
+          Bits<W> f;
+#pragma unroll
+          for (int k = 0; k < W; ++k) f.w[k] = act ? lgx[q * W + k] : 0;
+          double a = 0.0, b = 0.0;
+          if (act) group_sum(q, a, b);
+          const bool ok = act && ((a != 0.0) || (b != 0.0));
+          const unsigned long long bal = __ballot(ok);
+          if (ok) store(pos + __popcll(bal & ((1ull << lane) - 1)), f, a, b);
+          pos += __popcll(bal);
+        }
       }
       if (lane == j) pos_l = pos;
     }
