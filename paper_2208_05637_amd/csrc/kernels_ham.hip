@@ -664,11 +664,13 @@ __global__ __launch_bounds__(512) void dedup_insert_kernel(const uint64_t* __res
 
 // Probe for entry e's key (W words, key: its words, hsh: its hash); inserts it
 // when absent.  Returns the slot (or -1 when the table is full) and sets won
-// when this call filled the slot.
+// when this call filled the slot; where the key was already there, rank is
+// its slot's rank field, read right away (kNoEntry until its inserter writes
+// it; written once, so any other value is final).
 template <int W, bool SLOT>
 __device__ __forceinline__ int dedup_probe_insert(const uint64_t* __restrict__ xe, long long e,
                                                   const uint64_t (&key)[W], unsigned long long hsh,
-                                                  HRec* __restrict__ tab, long long HT, bool& won) {
+                                                  HRec* __restrict__ tab, long long HT, bool& won, int& rank) {
   const unsigned long long mine = SLOT ? ((hsh & 0xFFFFFFFF00000000ull) | (unsigned long long)e) : key[0];
   const unsigned long long hmask = (unsigned long long)HT - 1;
   unsigned long long gs = hsh & hmask;
@@ -688,10 +690,16 @@ __device__ __forceinline__ int dedup_probe_insert(const uint64_t* __restrict__ x
         bool same = true;
 #pragma unroll
         for (int k = 0; k < W; ++k) same = same && xe[W * pe + k] == key[k];
-        if (same) return (int)gs;
+        if (same) {
+          rank = __builtin_nontemporal_load(&tab[gs].rank);
+          return (int)gs;
+        }
       }
     } else {
-      if (prev == mine) return (int)gs;
+      if (prev == mine) {
+        rank = __builtin_nontemporal_load(&tab[gs].rank);
+        return (int)gs;
+      }
     }
     gs = (gs + 1) & hmask;
   }
@@ -719,7 +727,8 @@ __global__ __launch_bounds__(256) void dedup_insert_slot_kernel(const uint64_t* 
 #pragma unroll
   for (int k = 0; k < W; ++k) key[k] = xe[W * e + k];
   bool won;
-  const int found = dedup_probe_insert<W, true>(xe, e, key, key_hash<W>(key), tab, HT, won);
+  int rank_seen;
+  const int found = dedup_probe_insert<W, true>(xe, e, key, key_hash<W>(key), tab, HT, won, rank_seen);
   if (found < 0) atomicOr(err, kErrHashOverflow);
   else atomicMin(&tab[found].rank, (int)e);
   eu[e] = found;
@@ -748,11 +757,11 @@ __global__ __launch_bounds__(kRankedThreads) void dedup_insert_ranked_kernel(con
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t key[W];
   bool won = false;
-  int found = -1;
+  int found = -1, rank_seen = kNoEntry;
   if (e < count) {
 #pragma unroll
     for (int k = 0; k < W; ++k) key[k] = xe[W * e + k];
-    found = dedup_probe_insert<W, SLOT>(xe, e, key, key_hash<W>(key), tab, HT, won);
+    found = dedup_probe_insert<W, SLOT>(xe, e, key, key_hash<W>(key), tab, HT, won, rank_seen);
     if (found < 0) {
       atomicOr(err, kErrHashOverflow);
       eu[e] = kRankOverflow;
@@ -778,9 +787,7 @@ __global__ __launch_bounds__(kRankedThreads) void dedup_insert_ranked_kernel(con
     for (int k = 0; k < W; ++k) xu[r * W + k] = key[k];
     eu[e] = (int)r;
   } else if (found >= 0) {
-    // a rank field is written once, from kNoEntry: a value read here is final
-    const int rk = __builtin_nontemporal_load(&tab[found].rank);
-    eu[e] = rk != kNoEntry ? rk : -1 - found;
+    eu[e] = rank_seen != kNoEntry ? rank_seen : -1 - found;
   }
 }
 
