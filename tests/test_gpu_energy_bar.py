@@ -8,8 +8,9 @@ path runs over the whole batch in the plan the benchmark uses.  Then, for each
 workload (for the four-instance workload, after one nqs_energy_grad_multi
 call over all four at full batches):
   (1) the FP64 GPU path's local energies equal the oracle's on 16
-      configurations spread over the batch, to 1e-10 * S_i with
-      S_i = sum_k |summand_k| (the rounding scale of the K-term sum);
+      configurations spread over the batch (4 at 76 qubits, where the oracle
+      takes ~10 s each), to 1e-10 * S_i with S_i = sum_k |summand_k| (the
+      rounding scale of the K-term sum);
   (2) the BF16 path's weighted mean of the local energies over 1,024
       configurations spread over the batch is within 1e-5 Ha of the FP64 GPU
       path's mean over the same configurations and weights.
@@ -62,7 +63,7 @@ def _workload(nqs, ctx, name):
     return terms, H, params_np, p, cfg, x, w, mk(cfg["B"])
 
 
-def _bar(nqs, ctx, terms, H, cfg, params_np, p, x, w, el_b, label):
+def _bar(nqs, ctx, terms, H, cfg, params_np, p, x, w, el_b, label, n_oracle=16):
     B = x.shape[0]
     xs = x.cpu().numpy().view(np.uint64)
     wn = w.cpu().numpy()
@@ -72,7 +73,7 @@ def _bar(nqs, ctx, terms, H, cfg, params_np, p, x, w, el_b, label):
                    dedup=cfg["n"] != 64)
     el64 = nqs.local_energy(p64, p, xs[sub]).cpu().numpy()
     assert nqs.device_status(p64) == 0
-    j16 = np.unique(np.linspace(0, len(sub) - 1, 16).astype(np.int64))
+    j16 = np.unique(np.linspace(0, len(sub) - 1, n_oracle).astype(np.int64))
     ref = pauli.canonical_terms(terms.x_mask, terms.z_mask, terms.coeff)
     net = made.Net(n=cfg["n"], n_layers=cfg["L"], width=cfg["h"], n_up=cfg["n_up"], n_dn=cfg["n_dn"])
     el_ref, S = vmc.local_energy(ref, net, params_np, xs[sub[j16]], scale=True)
@@ -148,6 +149,30 @@ def test_energy_bar_four_instances_one_call(nqs, ctx):
         assert torch.equal(l1, it["eloc"]) and torch.equal(g1, it["grad"]) and torch.equal(e1, it["energy"])
         _bar(nqs, ctx, terms, H, cfg, params_np, it["params"], it["samples"], it["weights"],
              it["eloc"].cpu().numpy(), f"{cfg['n']} qubits in the four-instance call, {it['samples'].shape[0]}")
+
+
+def test_energy_bar_76_qubits(nqs, ctx):
+    """76 qubits (two-word strings) at the size of the benchmark's 76-qubit side workload: 38 orbitals, 19 + 19
+    electrons, two-electron integrals below 2.5e-5 dropped (1,618,663 strings), L = 4, h = 1024 with BF16
+    parameters, 512 configurations drawn from the network (10^12 draws), dedup on.  The FP64 GPU path
+    against the oracle on 4 of them (the oracle takes ~10 s per configuration here); the BF16-weight mean
+    over all 512 against the FP64 GPU mean over the same configurations and weights."""
+    terms = hamiltonian(38, 0, cutoff=2.5e-5)
+    H = nqs.Hamiltonian.from_terms(terms).upload(ctx)
+    assert H.K == 1618663
+    cfg = dict(n=76, L=4, h=1024, n_up=19, n_dn=19)
+    params_np = init_params(76, 4, 1024, seed=1, dtype="bf16")
+    p = torch.from_numpy(params_np).cuda()
+    mk = lambda mb: nqs.Plan(ctx, H, 4, 1024, 19, 19, "bf16w", max_batch=mb, dedup=True)
+    x, w = nqs.sample(mk(16), p, 10**12, seed=2, max_unique=512)
+    assert x.shape[0] == 512 and x.shape[1] == 2
+    plan = mk(512)
+    energy, grad, eloc = nqs.energy_grad(plan, p, x, w)
+    torch.cuda.synchronize()
+    assert nqs.device_status(plan) == 0 and bool(torch.isfinite(grad).all())
+    el, wn = eloc.cpu().numpy(), w.cpu().numpy()
+    assert abs(math.fsum(wn * el[:, 0]) / math.fsum(wn) - energy[0].item()) <= 1e-12 * abs(energy[0].item())
+    _bar(nqs, ctx, terms, H, cfg, params_np, p, x, w, el, "76 qubits, 512 sampled", n_oracle=4)
 
 
 def test_24_qubits_gradient_oracle_and_central_fd(nqs, ctx):
