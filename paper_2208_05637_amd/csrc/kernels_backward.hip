@@ -335,15 +335,35 @@ __global__ void relu_mask_kernel(const T* __restrict__ act, T* __restrict__ d, l
   if (e < count && !(act[e] > (T)0)) d[e] = (T)0;
 }
 
-// grad[off + j] += sum_i D[i * ld + j], sequential over i (deterministic).
+// grad[off + j] += sum_i D[i * ld + j] in a fixed order (deterministic): a
+// workgroup takes 64 columns; each of its 16 row segments is summed in order
+// in FP64, then the 16 segment sums in order.
+constexpr int kColsumCols = 64, kColsumSegs = 16;
 template <typename T>
-__global__ void colsum_kernel(const T* __restrict__ D, long long S, int cols, long long ld,
-                              double* __restrict__ grad, long long off) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= cols) return;
+__global__ __launch_bounds__(kColsumCols * kColsumSegs) void colsum_kernel(const T* __restrict__ D, long long S,
+                                                                           int cols, long long ld,
+                                                                           double* __restrict__ grad, long long off) {
+  __shared__ double part[kColsumSegs][kColsumCols];
+  const int c = threadIdx.x % kColsumCols, sg = threadIdx.x / kColsumCols;
+  const int j = blockIdx.x * kColsumCols + c;
+  const long long per = (S + kColsumSegs - 1) / kColsumSegs;
+  const long long i0 = sg * per, i1 = i0 + per < S ? i0 + per : S;
   double acc = 0.0;
-  for (long long i = 0; i < S; ++i) acc += (double)D[i * ld + j];
-  grad[off + j] += acc;
+  if (j < cols)
+    for (long long i = i0; i < i1; ++i) acc += (double)D[i * ld + j];
+  part[sg][c] = acc;
+  __syncthreads();
+  if (sg == 0 && j < cols) {
+    double t = 0.0;
+    for (int q = 0; q < kColsumSegs; ++q) t += part[q][c];
+    grad[off + j] += t;
+  }
+}
+template <typename T>
+static void colsum(const T* D, long long S, int cols, long long ld, double* grad, long long off, hipStream_t s) {
+  if (cols <= 0) return;
+  hipLaunchKernelGGL(colsum_kernel<T>, dim3((unsigned)((cols + kColsumCols - 1) / kColsumCols)),
+                     dim3(kColsumCols * kColsumSegs), 0, s, D, S, cols, ld, grad, off);
 }
 
 // Output seeds for sample i with g_la = 2 (w/W)(Re l - E), g_phi = 2 (w/W) Im l:
@@ -432,8 +452,7 @@ static void mlp_backward(const Geom& g, const T* wm, const T* in0, int k0, long 
     a.grad = grad; a.grad_off = g.poff[wi(l)]; a.grad_ld = K;
     a.mask_kind = mask_of(l);
     gemm<T, E_GRAD>(a, g, s);
-    hipLaunchKernelGGL(colsum_kernel<T>, dim3((unsigned)((h + 255) / 256)), dim3(256), 0, s, da, S, h,
-                       (long long)h, grad, g.poff[wi(l) + 1]);
+    colsum<T>(da, S, h, (long long)h, grad, g.poff[wi(l) + 1], s);
     if (l > 1) {
       GemmArgs b{};
       b.Mr = (int)S; b.Nc = K; b.K = h;
@@ -495,8 +514,7 @@ static void backward_t(const Geom& g, const T* wm, const uint64_t* x, long long 
     a.grad = grad; a.grad_off = g.poff[hw[part]]; a.grad_ld = h;
     a.mask_kind = part == 0 ? MK_HEAD_O : (two ? MK_NONE : MK_HEAD_P);
     gemm<T, E_GRAD>(a, g, s);
-    hipLaunchKernelGGL(colsum_kernel<T>, dim3((unsigned)((a.Mr + 255) / 256)), dim3(256), 0, s,
-                       dh + (part == 0 ? 0 : n), S, a.Mr, (long long)ld, grad, g.poff[hw[part] + 1]);
+    colsum<T>(dh + (part == 0 ? 0 : n), S, a.Mr, (long long)ld, grad, g.poff[hw[part] + 1], s);
   }
   // d a_L = d o (M_o W_o) [+ d p (M_p W_p) with the shared trunk]
   {
