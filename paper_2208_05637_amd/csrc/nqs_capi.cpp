@@ -945,6 +945,7 @@ static void forward_profiled(nqs_plan* p, void* ws, const WsLayout& L, const voi
   if (p->prof && p->next_slot < kProfSlots) {
     si = p->next_slot++;
     slot = at<long long>(ws, L.prof) + si;
+    launch_fill_u64(slot, 0ull, 1, p->ctx->stream);   // a launch with no tiles leaves it at zero rows
   }
   forward_net(p, packed, x, bound, d_count, out, slot, p->ctx->stream);
   prof_close(p, a, 2, si);

@@ -323,3 +323,29 @@ def test_dedup_look_back_rows_and_values(nqs, ctx, N, B, chunk, seed):
     assert nqs.multi_device_status(items, ws) == 0
     for it in items:
         assert torch.equal(it["eloc"], e_off)
+
+
+def test_dedup_look_back_with_empty_chunks(nqs, ctx):
+    """A Hamiltonian of Z strings only: no chunk has a connected configuration, so every dedup and
+    look-back set is empty; the local energies are the diagonal (bit-exact against the oracle's sum)
+    and the forward evaluates the samples alone."""
+    n = 12
+    rng = np.random.default_rng(21)
+    zm = np.array([int(v) for v in rng.integers(1, 1 << n, 30)], dtype=np.uint64)
+    cf = rng.normal(size=30)
+    H = nqs.Hamiltonian(n, np.zeros(30, dtype=np.uint64), zm, cf, conserves_spin=False).upload(ctx)
+    ref = pauli.canonical_terms(np.zeros(30, dtype=np.uint64), zm, cf)
+    xs = pauli.sector_basis(n, 3, 3).astype(np.uint64)[:50]
+    plan = nqs.Plan(ctx, H, 1, 64, -1, -1, "fp64", max_batch=len(xs), chunk_samples=7, dedup=True)
+    p = torch.from_numpy(init_params(n, 1, 64, seed=4)).cuda()
+    plan.profile(True)
+    el = nqs.local_energy(plan, p, xs)
+    torch.cuda.synchronize()
+    prof = plan.profile_read()
+    plan.profile(False)
+    assert nqs.device_status(plan) == 0
+    diag, ent = vmc.connected(ref, xs, sector_filter=False)
+    assert all(len(e[0]) == 0 for e in ent)
+    out = el.cpu().numpy()
+    assert np.array_equal(out[:, 0], diag.real) and np.array_equal(out[:, 1], diag.imag)
+    assert int(prof["forward_rows"]) == len(xs)
