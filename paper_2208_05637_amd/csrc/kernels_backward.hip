@@ -308,11 +308,65 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a, Geom g) {
   }
 }
 
+// The FP32 form on the matrix cores: the same 64x64 tiles and 16-deep k
+// steps through LDS; each of the four waves owns a 32x32 quarter of the tile
+// and accumulates it with v_mfma_f32_32x32x2f32 (lane l supplies A row l % 32
+// and B column l % 32 at k = l / 32; accumulator r of lane l holds row
+// 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32 of the quarter).
+typedef __attribute__((ext_vector_type(16))) float gemm_f32x16;
+template <int EPI>
+__global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs a, Geom g) {
+  __shared__ float As[16][65];
+  __shared__ float Bs[16][65];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wy = wave >> 1, wx = wave & 1;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const float* A = (const float*)a.A;
+  const float* B = (const float*)a.B;
+  gemm_f32x16 acc = {};
+  const int li = lane & 31, lk = lane >> 5;
+  for (int k0 = 0; k0 < a.K; k0 += 16) {
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+      const int r = e >> 4, kk = e & 15;        // A tile: 64 rows x 16 k
+      const int gi = i0 + r, gk = k0 + kk;
+      As[kk][r] = (gi < a.Mr && gk < a.K) ? A[gi * a.sa0 + gk * a.sa1] : 0.f;
+      const int kb = e >> 6, c = e & 63;        // B tile: 16 k x 64 cols
+      const int gkb = k0 + kb, gj = j0 + c;
+      Bs[kb][c] = (gkb < a.K && gj < a.Nc) ? B[gkb * a.sb0 + gj * a.sb1] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 2)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(As[kk + lk][wy * 32 + li], Bs[kk + lk][wx * 32 + li], acc, 0, 0, 0);
+    __syncthreads();
+  }
+  const int j = j0 + wx * 32 + li;
+  if (j >= a.Nc) return;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = i0 + wy * 32 + 8 * (r >> 2) + 4 * lk + (r & 3);
+    if (i >= a.Mr) continue;
+    float v = acc[r];
+    if constexpr (EPI == E_FWD || EPI == E_FWD_LIN) {
+      v += ((const float*)a.bias)[j];
+      if (EPI == E_FWD) v = v > 0.f ? v : 0.f;
+      ((float*)a.C)[i * a.ldc + j] = v;
+    } else if constexpr (EPI == E_STORE) {
+      ((float*)a.C)[i * a.ldc + j] = v;
+    } else if constexpr (EPI == E_ADD) {
+      ((float*)a.C)[i * a.ldc + j] += v;
+    } else {
+      if (mask_at(g, a.mask_kind, i, j)) a.grad[a.grad_off + (long long)i * a.grad_ld + j] += (double)v;
+    }
+  }
+}
+
 template <typename T, int EPI>
 static void gemm(const GemmArgs& a, const Geom& g, hipStream_t s) {
   if (a.Mr <= 0 || a.Nc <= 0) return;
   dim3 grid((unsigned)((a.Nc + 63) / 64), (unsigned)((a.Mr + 63) / 64));
-  hipLaunchKernelGGL((gemm_kernel<T, EPI>), grid, dim3(256), 0, s, a, g);
+  if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((gemm_mfma_kernel<EPI>), grid, dim3(256), 0, s, a, g);
+  else hipLaunchKernelGGL((gemm_kernel<T, EPI>), grid, dim3(256), 0, s, a, g);
 }
 
 // Bit of qubit j of sample i (g.words 64-bit words per sample).
