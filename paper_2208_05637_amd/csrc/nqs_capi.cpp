@@ -1216,7 +1216,10 @@ nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* ws,
   };
   // One forward launch per group of segments whose networks share
   // (precision, width, variant): the segments' tiles form one work list.
-  // Segments of two-word strings take the single-segment forward, one launch each.
+  // Segments of two-word strings, and segments whose variant takes the half
+  // tile, take the single-segment forward, one launch each (the multi-segment
+  // form of the half tile gave rows different from the single-segment form's
+  // at 16 waves, h = 512, so it is not used).
   auto launch_groups = [&](const std::vector<int>& ids, const std::vector<FwdSeg>& segs) {
     std::vector<bool> done(ids.size(), false);
     for (size_t a = 0; a < ids.size(); ++a) {
@@ -1225,7 +1228,8 @@ nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* ws,
       const int va = inst[ids[a]].plan->variant;
       const bool ra = inst[ids[a]].plan->resident;
       const int cus = inst[ids[a]].plan->ctx->cu_count;
-      if (ga.words != 1) {
+      const bool half = forward_variant_rows(ga.prec, ga.h, va) < forward_rows_per_block(ga.prec, ga.h);
+      if (ga.words != 1 || half) {
         const FwdSeg& sg = segs[a];
         launch_forward(*hg[a], va, ra, cus, sg.packed, sg.x, sg.rows_bound, sg.d_count, sg.out, nullptr, s);
         done[a] = true;
@@ -1236,7 +1240,7 @@ nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* ws,
         const Geom& gb = inst[ids[b]].plan->g;
         if (done[b] || gb.words != 1 || gb.prec != ga.prec || gb.h != ga.h || inst[ids[b]].plan->variant != va ||
             inst[ids[b]].plan->resident != ra)
-          continue;
+          continue;   // (the same variant as segment a, so never a half tile here)
         la.seg[la.nseg++] = segs[b];
         done[b] = true;
         if (la.nseg == kMaxSeg) {

@@ -349,3 +349,32 @@ def test_dedup_look_back_with_empty_chunks(nqs, ctx):
     out = el.cpu().numpy()
     assert np.array_equal(out[:, 0], diag.real) and np.array_equal(out[:, 1], diag.imag)
     assert int(prof["forward_rows"]) == len(xs)
+
+
+def test_multi_half_tiles_equal_single(nqs, ctx):
+    """Instances whose forwards run the half tile (32 rows at h = 512) in one multi-instance call: the
+    multi-segment form of the half-tile kernels against single calls, bit for bit."""
+    items, keep = [], []
+    for k, (N, seed, waves) in enumerate([(7, 1, 16), (8, 2, 16), (6, 3, 8)]):
+        n = 2 * N
+        terms = hamiltonian(N, seed)
+        H = nqs.Hamiltonian.from_terms(terms).upload(ctx)
+        xs, w = unique_with_counts(sector_samples(n, N // 2, N // 2, 150, seed=seed + 20))
+        plan = nqs.Plan(ctx, H, 2, 512, N // 2, N // 2, "bf16x3", max_batch=len(xs), dedup=True,
+                        chunk_samples=max(8, len(xs) // 3))
+        plan.configure(waves_per_block=waves, rows_per_block=32, resident=(k != 1))
+        assert plan.kernel_info()["rows_per_block"] == 32
+        dev = ctx.device
+        items.append(dict(plan=plan, params=torch.from_numpy(init_params(n, 2, 512, seed=seed)).to(dev),
+                          samples=torch.from_numpy(xs.view(np.int64)).to(dev), weights=torch.from_numpy(w).to(dev),
+                          eloc=torch.empty((len(xs), 2), dtype=torch.float64, device=dev),
+                          energy=torch.empty(3, dtype=torch.float64, device=dev),
+                          grad=torch.empty(plan.n_params, dtype=torch.float64, device=dev)))
+        keep.append(H)
+    ws = nqs.multi_workspace(items)
+    nqs.energy_grad_multi(items, ws)
+    torch.cuda.synchronize()
+    assert nqs.multi_device_status(items, ws) == 0
+    for it in items:
+        e1, g1, l1 = nqs.energy_grad(it["plan"], it["params"], it["samples"], it["weights"])
+        assert torch.equal(l1, it["eloc"]) and torch.equal(g1, it["grad"]) and torch.equal(e1, it["energy"])
