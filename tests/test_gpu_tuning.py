@@ -378,3 +378,27 @@ def test_multi_half_tiles_equal_single(nqs, ctx):
     for it in items:
         e1, g1, l1 = nqs.energy_grad(it["plan"], it["params"], it["samples"], it["weights"])
         assert torch.equal(l1, it["eloc"]) and torch.equal(g1, it["grad"]) and torch.equal(e1, it["energy"])
+
+
+@pytest.mark.parametrize("prec,h,waves", [("bf16x3", 512, 16), ("bf16w", 512, 16), ("bf16", 1024, 16),
+                                          ("fp32", 256, 8)])
+def test_half_tile_repeatable(nqs, ctx, prec, h, waves):
+    """The half-tile shapes give the same local energies on every call (five calls, resident grid and one
+    workgroup per tile), within 5e-4 of the full tile's."""
+    N = 8
+    n = 2 * N
+    terms = hamiltonian(N, 0)
+    H = nqs.Hamiltonian.from_terms(terms).upload(ctx)
+    xs, w = unique_with_counts(sector_samples(n, N // 2, N // 2, 300, seed=6))
+    plan = nqs.Plan(ctx, H, 2, h, N // 2, N // 2, prec, max_batch=len(xs), dedup=True, chunk_samples=100)
+    p = torch.from_numpy(init_params(n, 2, h, seed=2, dtype="bf16" if prec == "bf16w" else "fp32")).cuda()
+    full = plan.kernel_info()["rows_per_block"]
+    ref = nqs.local_energy(plan, p, xs).clone()
+    for resident in (True, False):
+        plan.configure(waves_per_block=waves, rows_per_block=full // 2, resident=resident)
+        first = nqs.local_energy(plan, p, xs).clone()
+        for _ in range(4):
+            assert torch.equal(nqs.local_energy(plan, p, xs), first)
+        tol = 0.05 if prec == "bf16" else 5e-4
+        assert float((first - ref).abs().max()) <= tol
+    assert nqs.device_status(plan) == 0
