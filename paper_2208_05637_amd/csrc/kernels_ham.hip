@@ -1052,7 +1052,7 @@ __global__ __launch_bounds__(256) void reduce_part_kernel(long long S, int R, co
   red[3][threadIdx.x] = ci.c;
   __syncthreads();
   for (int d = 128; d >= 1; d >>= 1) {
-    if (threadIdx.x < d) {
+    if ((int)threadIdx.x < d) {
       Comp x{red[0][threadIdx.x], red[1][threadIdx.x]}, y{red[0][threadIdx.x + d], red[1][threadIdx.x + d]};
       x.merge(y);
       red[0][threadIdx.x] = x.s;

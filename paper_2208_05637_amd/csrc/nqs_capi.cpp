@@ -1294,6 +1294,8 @@ nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* ws,
   return launch_check("energy gradient (multi)");
 }
 
+}  // extern "C"
+
 // ------------------------------------------------------------- autotuner
 namespace {
 using TuneKey = std::tuple<int, int, int, int, int64_t, int64_t, int64_t, int64_t, int, int, int>;
@@ -1313,6 +1315,8 @@ void set_chunk(nqs_plan* p, int64_t S) {
   grid_for(S, G - gfirst, p->R, p->gper);
 }
 }  // namespace
+
+extern "C" {
 
 nqs_status nqs_plan_autotune(nqs_plan* p, const float* params, const uint64_t* x, int64_t B, void* ws,
                              size_t ws_bytes, uint32_t flags, nqs_tune_report* rep) {
