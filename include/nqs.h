@@ -386,8 +386,10 @@ typedef struct {
   double*         d_energy;  /* [3] */
   double*         d_grad;    /* [n_params] */
 } nqs_instance;
-/* Instances of more than 64 qubits run their forwards as launches of their
-   own inside the same call (the shared work lists take one-word strings). */
+/* Instances of more than 64 qubits, and instances whose forward variant
+   takes the half tile (nqs_plan_configure), run their forwards as launches
+   of their own inside the same call: the shared work lists take one-word
+   strings in full tiles. */
 nqs_status nqs_multi_workspace_size(int n_inst, const nqs_instance* inst, size_t* bytes);
 nqs_status nqs_energy_grad_multi(int n_inst, const nqs_instance* inst, void* d_ws, size_t ws_bytes);
 
