@@ -108,6 +108,58 @@ def test_backward_matches_complex_step(L, constrained):
     assert np.all(gW1[M1 == 0] == 0)
 
 
+@pytest.mark.parametrize("n,L,h", [(8, 3, 16), (6, 2, 5), (10, 2, 40)])
+def test_every_hidden_unit_reaches_an_output(n, L, h):
+    """No hidden unit is cut off: following the masks back from the conditionals reaches every unit of
+    every hidden layer, and every unit sees at least one input (MADE keeps hidden degrees within
+    1 .. n-1, so that each unit feeds some later conditional)."""
+    for order in (None, np.random.default_rng(n).permutation(n)):
+        net = made.Net(n=n, n_layers=L, width=h, order=order)
+        M1, Mh, Mo, _ = made.masks(net)
+        reach = Mo > 0                                   # [n, h]: conditional j reads unit k of layer L
+        assert reach.any(axis=0).all()
+        for _ in range(L - 1):
+            reach = (reach.astype(np.float64) @ Mh) > 0  # units of the layer below
+            assert reach.any(axis=0).all()
+        assert (M1 > 0).any(axis=1).all()
+
+
+def test_relu_kink_takes_the_left_derivative():
+    """A unit whose pre-activation is exactly zero on every sample (zero incoming weights and bias)
+    passes no gradient to its incoming weights: the reverse pass takes the derivative from the left
+    of the kink, where the unit stays off and log psi does not change, while from the right it does."""
+    n, L, h = 8, 2, 14
+    net = _net(n=n, L=L, h=h)
+    params = init_params(n, L, h, seed=5, std=0.4).astype(np.float64)
+    xs = pauli.sector_basis(n, 2, 2)[::5]
+    rng = np.random.default_rng(9)
+    ga, gp = rng.standard_normal(len(xs)), rng.standard_normal(len(xs))
+    k1, k2 = 3, 2                                        # a layer-1 unit and a layer-2 unit
+    b1 = h * n
+    w2 = b1 + h
+    b2 = w2 + h * h
+    params[k1 * n:(k1 + 1) * n] = 0.0
+    params[b1 + k1] = 0.0
+    params[w2 + k2 * h:w2 + (k2 + 1) * h] = 0.0
+    params[b2 + k2] = 0.0
+    _, _, cache = made.forward(net, params, xs)
+    g = made.backward(net, params, cache, ga, gp)
+
+    def F(p):
+        la, ph, _ = made.forward(net, p, xs)
+        return np.sum(ga * la) + np.sum(gp * ph)
+
+    for bias in (b1 + k1, b2 + k2):
+        left, right = params.copy(), params.copy()
+        left[bias] -= 1e-3
+        right[bias] += 1e-3
+        assert F(left) == F(params)                      # the unit stays off
+        assert abs(F(right) - F(params)) > 1e-9          # and matters once it is on
+        assert g[bias] == 0.0
+    assert np.all(g[k1 * n:(k1 + 1) * n] == 0.0)
+    assert np.all(g[w2 + k2 * h:w2 + (k2 + 1) * h] == 0.0)
+
+
 def test_phase_submodel_single_layer_is_paper_mlp():
     """phase_mode 1, L = 1: the phase is Input[n-2] -> FC1 -> ReLU -> FC2 -> [4] on the
     first n-2 entries in sampling order (Sec. 4 Architecture), and the modulus is the

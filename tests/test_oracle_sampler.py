@@ -84,6 +84,89 @@ def test_binomial_large_mean_matches_distribution(c, p):
     assert abs(ks.var() / v - 1) < 0.1
 
 
+class _Rejected(Exception):
+    pass
+
+
+class _FirstAttempt:
+    """The uniforms (u, v) of one attempt of the rejection branch; a second attempt raises."""
+
+    def __init__(self, u, v):
+        self.vals = [u, v]
+
+    def next(self):
+        if not self.vals:
+            raise _Rejected
+        return self.vals.pop(0)
+
+
+def _attempt(c, p, u, v):
+    try:
+        return sampler.binomial(c, p, _FirstAttempt(u, v))
+    except _Rejected:
+        return None
+
+
+def _accept_level(c, p, u):
+    """A(u): the first attempt at (u, v) is accepted exactly for v <= A(u) (bisection on v)."""
+    if _attempt(c, p, u, 0.0) is None:
+        return 0.0
+    lo, hi = 0.0, 1.0
+    for _ in range(48):
+        mid = 0.5 * (lo + hi)
+        if _attempt(c, p, u, mid) is None:
+            hi = mid
+        else:
+            lo = mid
+    return 0.5 * (lo + hi)
+
+
+def _first_u(c, p, k):
+    """Smallest u whose candidate is k or above (the candidate rises with u; above u = 1/2 a
+    rejected candidate lies past c)."""
+    lo, hi = 1e-12, 1.0 - 1e-12
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        kk = _attempt(c, p, mid, 0.0)
+        if (kk is not None and kk >= k) or (kk is None and mid > 0.5):
+            hi = mid
+        else:
+            lo = mid
+    return hi
+
+
+@pytest.mark.parametrize("c,p,spread,tol", [(60, 0.45, 0, 1e-7), (1001, 0.3, 5, 1e-6), (10**7, 0.3, 4.5, 1e-6),
+                                            (10**9, 0.001, 4.5, 1e-6), (10**12, 0.37, 4.5, 2e-4)])
+def test_binomial_rejection_branch_is_exact(c, p, spread, tol):
+    """The output distribution of the rejection branch, computed rather than sampled.  Attempts take
+    fresh uniforms, so a draw is distributed as the first attempt's candidate given that it is
+    accepted: P(k) is proportional to the integral of A(u) over the u whose candidate is k.  Both
+    the candidate boundaries and A come from the branch's own decisions (bisection); the integral
+    is Gauss-Legendre quadrature.  Hormann's BTRS is exact, so P(k) / Bin(k; c, p) is the same for
+    every k (at c = 60 every k of probability above 1e-8: further out the candidate intervals shrink
+    toward the 2^-53 grain of the uniforms; a band of +-`spread` standard deviations otherwise).  At
+    10^12 the candidate's double-precision rounding (~4e-5 of one count) bounds the agreement."""
+    mu, sd = c * p, math.sqrt(c * p * (1 - p))
+    if spread == 0:
+        ks = [k for k in range(c + 1) if stats.binom.pmf(k, c, p) > 1e-8]
+    elif c <= 2000:
+        ks = list(range(int(mu - spread * sd), int(mu + spread * sd) + 1))
+    else:
+        ks = sorted(set(int(round(mu + z * sd)) for z in np.linspace(-spread, spread, 31)))
+    x, w = np.polynomial.legendre.leggauss(8)
+    ratio = []
+    for k in ks:
+        a, b = _first_u(c, p, k), _first_u(c, p, k + 1)
+        tot = 0.0
+        for s in range(6):
+            lo, hi = a + (b - a) * s / 6, a + (b - a) * (s + 1) / 6
+            for xi, wi in zip(x, w):
+                tot += 0.5 * (hi - lo) * wi * _accept_level(c, p, 0.5 * (lo + hi) + 0.5 * (hi - lo) * xi)
+        ratio.append(tot / stats.binom.pmf(k, c, p))
+    ratio = np.array(ratio)
+    assert (ratio.max() - ratio.min()) / ratio.mean() <= tol
+
+
 def test_binomial_reflection_and_counter_words():
     c = 10**7
     for i in range(50):
