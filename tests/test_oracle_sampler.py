@@ -23,6 +23,15 @@ def test_philox4x64_matches_numpy_philox():
             assert [int(v) for v in raw[4 * b:4 * b + 4]] == out
 
 
+def test_uniform53_is_numpys_double_conversion():
+    """A word becomes a double in [0, 1) as NumPy's generators make it from the same Philox words."""
+    for key in ([3, 4], [2**64 - 1, 0]):
+        bg1 = np.random.Philox(key=np.array(key, dtype=np.uint64))
+        bg2 = np.random.Philox(key=np.array(key, dtype=np.uint64))
+        raw = bg1.random_raw(256)
+        assert [sampler.uniform53(int(w)) for w in raw] == np.random.Generator(bg2).random(256).tolist()
+
+
 class _Given:
     """Uniforms given in advance (for the inversion branch: one per draw)."""
 
@@ -202,6 +211,35 @@ def test_sampler_matches_exact_distribution_8_qubits():
     counts[idx] = cs
     chi2 = np.sum((counts - N * pi) ** 2 / (N * pi))
     assert chi2 < stats.chi2.ppf(0.999, len(basis) - 1)
+
+
+def test_sampler_elimination_keeps_the_most_draws():
+    """A buffer bounded below the unique count of one sampling position keeps the children with the
+    most draws.  Unique counts never fall from one position to the next (each parent with draws
+    keeps a child), so with the bound between the counts before and at the last position t* where
+    the unbounded run grows, only t* eliminates, and every later position gives each kept entry one
+    child with all its draws (the split of a parent depends on its configuration and count only).
+    The bounded result is then the unbounded one's configurations whose prefixes at t* have the
+    largest counts."""
+    net = made.Net(n=10, n_layers=2, width=24, n_up=2, n_dn=3)
+    params = init_params(10, 2, 24, seed=8, std=0.6)
+    xs, cs = sampler.sample(net, params, 20000, seed=5, max_unique=10**6)
+    masks = [0]
+    for t in range(net.n):
+        masks.append(masks[-1] | (1 << int(net.order[t])))
+    sizes = [len(np.unique(xs & np.uint64(m))) for m in masks]
+    assert sizes == sorted(sizes) and sizes[-1] == len(xs)
+    ts = max(t for t in range(1, net.n + 1) if sizes[t] > sizes[t - 1])
+    assert sizes[ts:] == [len(xs)] * (net.n + 1 - ts)   # after t* each entry has a single child
+    order = np.sort(cs)[::-1]
+    cands = [u for u in range(sizes[ts - 1], sizes[ts]) if order[u - 1] > order[u]]
+    assert cands                                         # a bound with no tie at the threshold
+    for U in cands[:3]:
+        bx, bc = sampler.sample(net, params, 20000, seed=5, max_unique=U)
+        keep = cs >= order[U - 1]
+        assert len(bx) == U == keep.sum()
+        got = dict(zip(bx.tolist(), bc.tolist()))
+        assert got == dict(zip(xs[keep].tolist(), cs[keep].tolist()))
 
 
 def test_sampler_bounded_buffer():

@@ -124,6 +124,64 @@ def test_connected_counts_and_grouped_sum(N, nu, nd):
         assert abs(tot - el[i]) < 1e-12 * max(1.0, np.sum(np.abs(hv)))
 
 
+def _complex_terms(n, seed, K=40):
+    """Random Pauli strings (odd and even numbers of Y, so complex folded coefficients) with real
+    weights, and a pair that cancels: X_0 and X_0 Z_1 at equal weight give h = 0 wherever x_1 = 1."""
+    rng = np.random.default_rng(seed)
+    x = rng.integers(0, 1 << n, K).astype(np.uint64)
+    z = rng.integers(0, 1 << n, K).astype(np.uint64)
+    keep = x != 1
+    x = np.append(x[keep], [1, 1]).astype(np.uint64)
+    z = np.append(z[keep], [0, 2]).astype(np.uint64)
+    c = np.append(rng.standard_normal(keep.sum()), [0.5, 0.5])
+    return pauli.canonical_terms(x, z, c)
+
+
+def test_connected_unfiltered_matches_dense_rows():
+    """Without the sector filter, the connected entries of x are exactly the nonzero off-diagonal
+    entries of row x of the dense H (built term by term, pinned to Kronecker products), with equal
+    values, and the diagonal is H[x, x]; strings with an odd number of Y are included."""
+    n = 6
+    terms = _complex_terms(n, 4)
+    assert np.any(pauli.popcount(terms["x"] & terms["z"]) % 2 == 1)
+    H = pauli.dense_hamiltonian(terms, n)
+    xs = np.arange(1 << n, dtype=np.uint64)
+    diag, ent = vmc.connected(terms, xs, sector_filter=False)
+    cancelled = 0
+    for i, x in enumerate(xs.tolist()):
+        row = H[x]
+        assert abs(diag[i] - row[x]) <= 1e-14
+        _, xp, hv = ent[i]
+        nz = {j for j in np.nonzero(row)[0].tolist() if j != x}
+        assert set(xp.tolist()) == nz
+        for v, h in zip(xp.tolist(), hv):
+            assert abs(h - row[v]) <= 1e-14
+        cancelled += (x >> 1) & 1
+    assert cancelled > 0                                 # the cancelling group was dropped somewhere
+
+
+def test_sector_block_is_the_dense_block():
+    n = 6
+    terms = _complex_terms(n, 5)
+    H = pauli.dense_hamiltonian(terms, n)
+    for nu, nd in ((2, 1), (1, 2), (3, 3)):
+        basis = pauli.sector_basis(n, nu, nd)
+        idx = basis.astype(np.int64)
+        np.testing.assert_allclose(pauli.sector_block(terms, basis), H[np.ix_(idx, idx)], atol=1e-14, rtol=0)
+
+
+def test_energy_of_counts_equals_the_expanded_batch():
+    """Count weights (the unique-sample buffer's counts) give the estimate of the batch in which each
+    sample appears count times: the real and the imaginary mean and W."""
+    rng = np.random.default_rng(8)
+    el = rng.standard_normal(50) + 1j * rng.standard_normal(50)
+    cnt = rng.integers(1, 9, 50)
+    E, I, W = vmc.energy(el, cnt)
+    E2, I2, W2 = vmc.energy(np.repeat(el, cnt))
+    assert W == W2 == cnt.sum()
+    assert abs(E - E2) <= 1e-14 and abs(I - I2) <= 1e-14
+
+
 def test_gradient_matches_fd_of_frozen_surrogate():
     """g equals the central FD (h = 1e-4) of F = sum (w/W) 2[(Re l - E) log|psi| + Im l phi] with E_loc frozen."""
     N, L, h = 4, 2, 16
