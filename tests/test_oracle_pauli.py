@@ -91,6 +91,17 @@ def test_canonical_merge_drop_sort():
         pauli.canonical_terms(xs, zs, cs, coeff_imag=np.full(6, 1e-3))
 
 
+def test_canonical_drop_threshold_after_merge():
+    """The 1e-10 cut applies to merged coefficients: 2e-10 stays, 5e-11 goes, and two strings of 6e-11
+    that merge to 1.2e-10 stay although each alone would go."""
+    xs = np.array([1, 2, 4, 4], dtype=np.uint64)
+    zs = np.array([0, 0, 0, 0], dtype=np.uint64)
+    cs = np.array([2e-10, 5e-11, 6e-11, 6e-11])
+    t = pauli.canonical_terms(xs, zs, cs, drop_tol=1e-10)
+    assert t["x"].tolist() == [1, 4]
+    assert t["c"].tolist() == [2e-10, 6e-11 + 6e-11]
+
+
 # ---------------------------------------------------------------- generator
 
 def _ladder_ops(n):

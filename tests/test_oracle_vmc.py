@@ -124,6 +124,20 @@ def test_connected_counts_and_grouped_sum(N, nu, nd):
         assert abs(tot - el[i]) < 1e-12 * max(1.0, np.sum(np.abs(hv)))
 
 
+def test_local_energy_refuses_a_zero_amplitude_sample():
+    """E_loc divides by psi(x): a sample outside the network's sector (psi = 0) is an error."""
+    N = 3
+    n = 2 * N
+    terms = _terms(N)
+    net = made.Net(n=n, n_layers=1, width=8, n_up=1, n_dn=2)
+    params = init_params(n, 1, 8, seed=2, std=0.5)
+    good = pauli.sector_basis(n, 1, 2)[:3]
+    bad = pauli.sector_basis(n, 2, 1)[:1]
+    vmc.local_energy(terms, net, params, good)
+    with pytest.raises(ValueError):
+        vmc.local_energy(terms, net, params, np.concatenate([good, bad]))
+
+
 def _complex_terms(n, seed, K=40):
     """Random Pauli strings (odd and even numbers of Y, so complex folded coefficients) with real
     weights, and a pair that cancels: X_0 and X_0 Z_1 at equal weight give h = 0 wherever x_1 = 1."""
