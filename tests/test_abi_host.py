@@ -59,6 +59,19 @@ def test_canonical_tensor_bit_exact_vs_oracle(lib, N):
     assert np.array_equal(ex["tim"], ref["ct"].imag)
 
 
+def test_drop_threshold_after_merge_vs_oracle(lib):
+    """The library's 1e-10 cut keeps and drops the same strings as the oracle's: 2e-10 stays, 5e-11
+    goes, two strings of 6e-11 that merge to 1.2e-10 stay."""
+    x = np.array([1, 2, 4, 4, 8], dtype=np.uint64)
+    z = np.array([0, 0, 0, 0, 1], dtype=np.uint64)
+    c = np.array([2e-10, 5e-11, 6e-11, 6e-11, 0.3])
+    ref = pauli.canonical_terms(x, z, c, drop_tol=1e-10)
+    ex = _ham(4, x, z, c, tol=1e-10, flags=0).export()
+    assert ref["x"].tolist() == [1, 4, 8]
+    np.testing.assert_array_equal(ex["gx"], pauli.groups(ref)[0])
+    assert np.array_equal(ex["tre"], ref["ct"].real)
+
+
 def _words_to_ints(a):
     return [int(r[0]) | (int(r[1]) << 64) for r in np.asarray(a).tolist()]
 
