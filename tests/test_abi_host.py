@@ -220,6 +220,32 @@ def _table_h(tb, g, x_int, W):
     return complex(re, im)
 
 
+def test_structured_tables_complex_coefficients(lib):
+    """Tables of a Hamiltonian whose strings carry odd numbers of Y (imaginary folded coefficients),
+    flips of up to four qubits, several Z strings per flip: every group's h_g(x) for every x of 7
+    qubits equals the oracle's group sum to the rounding of two summation orders."""
+    from paper_2208_05637_amd import Hamiltonian
+    n = 7
+    rng = np.random.default_rng(12)
+    flips = [f for f in range(1 << n) if bin(f).count("1") <= 4]
+    x = np.array(rng.choice(flips, 90), dtype=np.uint64)
+    z = rng.integers(0, 1 << n, 90).astype(np.uint64)
+    c = rng.standard_normal(90)
+    ref = pauli.canonical_terms(x, z, c)
+    assert np.any(ref["ct"].imag != 0)
+    tb = Hamiltonian(n, x, z, c, tables=True).export_tables()
+    gx, goff = pauli.groups(ref)
+    eps = 2.0 ** -53
+    for xv in range(1 << n):
+        for g in range(len(gx)):
+            a, b = goff[g], goff[g + 1]
+            want = complex(0.0)
+            for k in range(a, b):
+                want += ref["ct"][k] * (-1.0 if bin(xv & int(ref["z"][k])).count("1") & 1 else 1.0)
+            got = _table_h(tb, g, xv, 1)
+            assert abs(got - want) <= 2 * (b - a) * eps * np.sum(np.abs(ref["c"][a:b])), (g, xv)
+
+
 @pytest.mark.parametrize("N,cutoff", [(6, 0.0), (12, 0.0), (38, 0.05)])
 def test_structured_tables_reproduce_the_group_sums(lib, N, cutoff):
     """Tables built by nqs_ham_create(NQS_H_TABLES): one 16-entry table per double
