@@ -220,7 +220,7 @@ def test_sampler_elimination_keeps_the_most_draws():
     the unbounded run grows, only t* eliminates, and every later position gives each kept entry one
     child with all its draws (the split of a parent depends on its configuration and count only).
     The bounded result is then the unbounded one's configurations whose prefixes at t* have the
-    largest counts."""
+    largest counts, ties at the threshold taken in buffer order."""
     net = made.Net(n=10, n_layers=2, width=24, n_up=2, n_dn=3)
     params = init_params(10, 2, 24, seed=8, std=0.6)
     xs, cs = sampler.sample(net, params, 20000, seed=5, max_unique=10**6)
@@ -240,6 +240,19 @@ def test_sampler_elimination_keeps_the_most_draws():
         assert len(bx) == U == keep.sum()
         got = dict(zip(bx.tolist(), bc.tolist()))
         assert got == dict(zip(xs[keep].tolist(), cs[keep].tolist()))
+    # Ties at the threshold are kept in buffer order.  Children with a 0 at the position just
+    # placed come before those with a 1, each in parent order, so an entry's place at t* is
+    # ordered by its bits at positions t*-1, t*-2, ..., 0.
+    pos_bits = [[(int(v) >> int(net.order[t])) & 1 for t in range(ts - 1, -1, -1)] for v in xs.tolist()]
+    place = sorted(range(len(xs)), key=lambda i: pos_bits[i])
+    rank = np.empty(len(xs), dtype=np.int64)
+    rank[place] = np.arange(len(xs))
+    ties = [u for u in range(sizes[ts - 1], sizes[ts]) if order[u - 1] == order[u]]
+    assert ties
+    for U in ties[:3]:
+        bx, bc = sampler.sample(net, params, 20000, seed=5, max_unique=U)
+        want = sorted(range(len(xs)), key=lambda i: (-cs[i], rank[i]))[:U]
+        assert dict(zip(bx.tolist(), bc.tolist())) == {int(xs[i]): int(cs[i]) for i in want}
 
 
 def test_sampler_bounded_buffer():
